@@ -1,0 +1,206 @@
+/*
+ * certglm: safe dual bounds for branch-and-bound nodes of the k-sparse, box-constrained,
+ * ridge-regularised GLM, computed on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Liu et al., "Scalable First-order Method for Certifying Optimal k-Sparse GLMs"
+ * (arXiv 2502.09502). The problem is problem (1) of Sec. 1,
+ *
+ *     min_beta f(X beta, y) + lambda2 ||beta||_2^2   s.t.  ||beta||_inf <= M,  ||beta||_0 <= k,
+ *
+ * with f the least-squares loss ||u - y||^2 or the logistic loss sum log(1 + exp(-y_i u_i)).
+ * A node fixes z_j = 0 on a set Z0 and z_j = 1 on a set Z1 in the perspective relaxation
+ * P_conv of Sec. 2; this library solves that relaxation by restarted FISTA (Alg. 3) with the
+ * exact prox of Alg. 1 (via the Moreau identity of Sec. 3.3) and the value of g from Alg. 2,
+ * and certifies every answer with the weak-duality bound of Sec. 3.4, evaluated in FP64.
+ *
+ * Conventions (every entry point):
+ *   - returns an int status, CGL_OK (0) on success; no C++ exception or abort crosses the ABI;
+ *     cgl_status_str() names a status, cgl_last_error() gives the detail of the last failure
+ *     on the calling thread;
+ *   - pointers are host pointers unless an argument says otherwise;
+ *   - the caller owns every buffer it passes; the library copies what it keeps;
+ *   - indices are 0-based; matrices are row-major with a leading dimension;
+ *   - a context and the objects created from it are used by one thread at a time.
+ */
+#ifndef CERTGLM_H
+#define CERTGLM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CGL_ABI_VERSION 1
+
+/* ------------------------------------------------------------------ statuses and enums */
+
+enum cgl_status {
+  CGL_OK = 0,
+  CGL_E_INVAL = 1,    /* an argument is invalid (detail in cgl_last_error) */
+  CGL_E_NOMEM = 2,    /* device or host allocation failed */
+  CGL_E_DEVICE = 3,   /* a HIP runtime call failed */
+  CGL_E_BUSY = 4,     /* server queue full */
+  CGL_E_NOTFOUND = 5, /* unknown ticket */
+  CGL_E_INTERNAL = 6
+};
+
+enum cgl_dtype { CGL_F64 = 0, CGL_F32 = 1, CGL_BF16 = 2 };
+enum cgl_mem { CGL_MEM_HOST = 0, CGL_MEM_DEVICE = 1 };
+enum cgl_loss { CGL_LOSS_LS = 0, CGL_LOSS_LOGISTIC = 1 };
+
+/* Arithmetic of the iteration. Every bound is certified in FP64 either way.
+ *   CGL_PREC_F64:   FP64 iterates and FP64 products with X in its stored precision
+ *                   (the plain per-node path);
+ *   CGL_PREC_MIXED: BF16 operands on MFMA with FP32 accumulation for the correction products
+ *                   around an FP64 base point that is re-centred in FP64 when progress stalls. */
+enum cgl_precision { CGL_PREC_F64 = 0, CGL_PREC_MIXED = 1 };
+
+/* Per-node result status. */
+enum cgl_node_status {
+  CGL_CONVERGED = 0,     /* FP64-certified relative gap <= tol */
+  CGL_NOT_CONVERGED = 1, /* max_iter reached; lower_bound is still a valid bound */
+  CGL_INFEASIBLE = 2,    /* |Z1| > k: no feasible z; lower_bound = +inf */
+  CGL_NUMERIC = 3,       /* a non-finite value appeared; lower_bound is the best valid one */
+  CGL_CANCELLED = 4,     /* server request cancelled before completion */
+  CGL_PRUNED = 5,        /* certified lower bound > incumbent: the node can be pruned */
+  CGL_BELOW_INCUMBENT = 6 /* primal value < incumbent: stop and branch (Sec. 4.3 rules) */
+};
+
+typedef struct cgl_ctx cgl_ctx;
+typedef struct cgl_problem cgl_problem;
+typedef struct cgl_server cgl_server;
+
+/* ------------------------------------------------------------------ node and result */
+
+/* One branch-and-bound node. fixed_zero = Z0 (beta_j = 0), fixed_in = Z1 (z_j = 1: the
+ * coordinate pays lambda2 beta_j^2 and |beta_j| <= M but not the cardinality budget beyond its
+ * own unit). Indices must be distinct, in [0, p) and Z0, Z1 disjoint, else CGL_E_INVAL.
+ * |Z1| > k is not an error: the result is CGL_INFEASIBLE with lower_bound = +inf.
+ * The relative gap is (P_best - D_best) / max(|P_best|, 1). */
+typedef struct cgl_node {
+  const int32_t* fixed_zero;
+  int32_t n_zero;
+  const int32_t* fixed_in;
+  int32_t n_in;
+  double tol;           /* relative-gap tolerance, e.g. 1e-6 */
+  int32_t max_iter;     /* iteration cap (>= 1) */
+  int32_t check_every;  /* dual monitor period in iterations (>= 1) */
+  int32_t precision;    /* enum cgl_precision */
+  const double* warm_start; /* NULL, or p host doubles: the first iterate */
+  double incumbent;     /* +inf for none; else the early-termination rules of Sec. 4.3 apply */
+} cgl_node;
+
+typedef struct cgl_result {
+  double lower_bound; /* FP64 weak-duality bound D(zeta); valid whatever the status */
+  double primal;      /* FP64 objective of the returned beta (an upper bound on P_conv) */
+  double gap_abs;     /* primal - lower_bound */
+  double gap_rel;     /* gap_abs / max(|primal|, 1) */
+  int32_t iters;      /* FISTA iterations run */
+  int32_t restarts;   /* momentum restarts (phi reset to 1) */
+  int32_t status;     /* enum cgl_node_status */
+  int32_t recentres;  /* FP64 re-centrings (mixed precision only) */
+  double err_vs_fp64_est; /* |working-precision objective - FP64 objective| / max(|P|, 1) at the
+                             returned beta: the error of the fast arithmetic against FP64 */
+} cgl_result;
+
+/* Fill a node with defaults: no fixed sets, tol 1e-6, max_iter 100000, check_every 1,
+ * CGL_PREC_F64, no warm start, incumbent +inf. */
+void cgl_node_init(cgl_node* node);
+
+int cgl_version(void);
+const char* cgl_status_str(int status);
+const char* cgl_last_error(void);
+
+/* ------------------------------------------------------------------ context */
+
+/* device: HIP device ordinal. hip_stream: a hipStream_t to run on, or NULL for a stream the
+ * context creates (default priority). CGL_E_DEVICE on HIP failures. */
+int cgl_ctx_create(int device, void* hip_stream, cgl_ctx** out);
+int cgl_ctx_destroy(cgl_ctx* ctx);
+
+/* ------------------------------------------------------------------ problem */
+
+/* Create the problem data of problem (1) on the device.
+ *   X      : n x p row-major, leading dimension ldx >= p, element type x_dtype (F64, F32, or
+ *            BF16 as raw 16-bit patterns); x_mem says whether X is a host or a device pointer.
+ *            The values given ARE the problem (a BF16 X is not an approximation of anything).
+ *   y      : n host doubles (logistic: each -1 or +1).
+ *   loss   : enum cgl_loss.  lambda2 > 0, M > 0, k >= 1.
+ *   L      : Lipschitz constant of grad F (Alg. 3); L <= 0 asks the library to compute it
+ *            (power iteration on X^T X in FP64, times 2 for least squares, / 4 for logistic,
+ *            then enlarged by a safety factor of 1.002).
+ * The library copies X (in its stored precision, plus a transposed BF16 copy for the mixed
+ * path) and y into device memory it owns. Errors: CGL_E_INVAL (n, p < 1; p > 32768; ldx < p;
+ * lambda2 <= 0; M <= 0; k < 1; non-finite y; logistic y not in {-1, +1}), CGL_E_NOMEM. */
+int cgl_problem_create(cgl_ctx* ctx, const void* X, int32_t x_dtype, int32_t x_mem, int64_t n,
+                       int64_t p, int64_t ldx, const double* y, int32_t loss, double lambda2,
+                       double M, int32_t k, double L, cgl_problem** out);
+int cgl_problem_destroy(cgl_problem* prob);
+/* The Lipschitz constant in use. */
+int cgl_problem_lipschitz(const cgl_problem* prob, double* L);
+
+/* ------------------------------------------------------------------ solves */
+
+/* Solve one node relaxation (blocking). beta_out: NULL or p host doubles (the best-primal
+ * iterate). res: one result. */
+int cgl_solve_node(cgl_problem* prob, const cgl_node* node, double* beta_out, cgl_result* res);
+
+/* Solve count nodes of one problem together (blocking). Nodes with precision CGL_PREC_MIXED
+ * share batched MFMA products over X; nodes with CGL_PREC_F64 are solved one after another on
+ * the plain path. beta_out: NULL or count x p host doubles. res: count results. Each result
+ * equals the cgl_solve_node result of the same node within the tolerances. */
+int cgl_solve_batch(cgl_problem* prob, const cgl_node* nodes, int32_t count, double* beta_out,
+                    cgl_result* res);
+
+/* ------------------------------------------------------------------ certification utilities */
+
+/* FP64 objective and weak-duality bound at a given beta (host, p doubles): primal = f(X beta) +
+ * 2 lambda2 g_node(beta) (+inf outside the domain) and dual = D(zeta) with
+ * zeta = -grad f(X beta) (Sec. 3.4). */
+int cgl_certify(cgl_problem* prob, const cgl_node* node, const double* beta, double* primal,
+                double* dual);
+
+/* FP64 products with the problem's X on the device: trans = 0: out (n) = X v (v: p doubles);
+ * trans = 1: out (p) = X^T v (v: n doubles). Host pointers. */
+int cgl_problem_matvec(cgl_problem* prob, int32_t trans, const double* v, double* out);
+
+/* The node prox on the device (Alg. 1 via the Moreau identity, node form): for each of count
+ * rows w_i (host, count x p doubles), beta_i = prox_{g_node/rho}(w_i) with k' = k - |Z1_i|, and
+ * gval_i = g_node(beta_i) (Alg. 2). nodes may be NULL (no fixed sets, only k used). beta_out:
+ * count x p doubles; gval_out: NULL or count doubles. */
+int cgl_prox_node_batch(cgl_ctx* ctx, double rho, double M, int32_t k, const cgl_node* nodes,
+                        const double* W, int32_t count, int64_t p, double* beta_out,
+                        double* gval_out);
+
+/* ------------------------------------------------------------------ serving */
+
+/* A request loop over resident problems: submitted node relaxations are admitted into device
+ * slots while slots and the HBM budget allow, advanced together (continuous batching: finished
+ * slots are refilled between iteration chunks), and returned through poll.
+ *   hbm_budget_bytes: upper bound on the device memory the server's slot state may use
+ *                     (0 = no limit beyond max_slots); max_slots: slots per problem. */
+int cgl_server_create(cgl_ctx* ctx, size_t hbm_budget_bytes, int32_t max_slots,
+                      cgl_server** out);
+/* Queue a node of prob (copied; never blocks). ticket receives its id. CGL_E_BUSY when the
+ * queue is full. */
+int cgl_server_submit(cgl_server* srv, cgl_problem* prob, const cgl_node* node,
+                      uint64_t* ticket);
+/* Advance the device work by one scheduling round (admit, run one chunk per active problem,
+ * retire), then return up to max finished results: tickets[i], res[i], and, if betas is not
+ * NULL, betas[i * p_i ...] for each (the caller sizes betas for its largest p). got receives the
+ * count. latency_s (nullable) receives submit-to-completion wall seconds per result. */
+int cgl_server_poll(cgl_server* srv, int32_t max, uint64_t* tickets, cgl_result* res,
+                    double* betas, int64_t betas_stride, double* latency_s, int32_t* got);
+/* Cancel a queued or running request; it is returned by poll with status CGL_CANCELLED. */
+int cgl_server_cancel(cgl_server* srv, uint64_t ticket);
+/* Counts: queued, running, finished-but-not-polled. */
+int cgl_server_stats(cgl_server* srv, int32_t* queued, int32_t* running, int32_t* done);
+int cgl_server_destroy(cgl_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CERTGLM_H */

@@ -1,0 +1,261 @@
+"""ctypes binding of libcertglm.so: argument marshalling only; every step of the solve runs in
+the library's HIP kernels. The binding never falls back to a CPU implementation: when the
+library is missing it raises."""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcertglm.so")
+
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_BUSY, E_NOTFOUND, E_INTERNAL = range(7)
+F64, F32, BF16 = 0, 1, 2
+MEM_HOST, MEM_DEVICE = 0, 1
+LOSS = {"ls": 0, "logistic": 1}
+PREC = {"f64": 0, "mixed": 1}
+STATUS = {0: "converged", 1: "not_converged", 2: "infeasible", 3: "numeric", 4: "cancelled",
+          5: "pruned", 6: "below_incumbent"}
+
+EXPORTS = [
+    "cgl_version", "cgl_status_str", "cgl_last_error", "cgl_node_init", "cgl_ctx_create",
+    "cgl_ctx_destroy", "cgl_problem_create", "cgl_problem_destroy", "cgl_problem_lipschitz",
+    "cgl_solve_node", "cgl_solve_batch", "cgl_certify", "cgl_problem_matvec",
+    "cgl_prox_node_batch", "cgl_server_create", "cgl_server_submit", "cgl_server_poll",
+    "cgl_server_cancel", "cgl_server_stats", "cgl_server_destroy",
+]
+
+
+class CglNode(C.Structure):
+    _fields_ = [
+        ("fixed_zero", C.POINTER(C.c_int32)), ("n_zero", C.c_int32),
+        ("fixed_in", C.POINTER(C.c_int32)), ("n_in", C.c_int32),
+        ("tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
+        ("precision", C.c_int32), ("warm_start", C.POINTER(C.c_double)),
+        ("incumbent", C.c_double),
+    ]
+
+
+class CglResult(C.Structure):
+    _fields_ = [
+        ("lower_bound", C.c_double), ("primal", C.c_double), ("gap_abs", C.c_double),
+        ("gap_rel", C.c_double), ("iters", C.c_int32), ("restarts", C.c_int32),
+        ("status", C.c_int32), ("recentres", C.c_int32), ("err_vs_fp64_est", C.c_double),
+    ]
+
+
+class CglError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is not built; run paper_2502_09502_amd/build.py")
+    lib = C.CDLL(path)
+    P, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    pd = C.POINTER(C.c_double)
+    lib.cgl_version.restype = C.c_int
+    lib.cgl_status_str.restype = C.c_char_p
+    lib.cgl_status_str.argtypes = [C.c_int]
+    lib.cgl_last_error.restype = C.c_char_p
+    lib.cgl_node_init.argtypes = [C.POINTER(CglNode)]
+    lib.cgl_node_init.restype = None
+    lib.cgl_ctx_create.argtypes = [C.c_int, P, C.POINTER(P)]
+    lib.cgl_ctx_destroy.argtypes = [P]
+    lib.cgl_problem_create.argtypes = [P, P, i32, i32, i64, i64, i64, pd, i32, dbl, dbl, i32, dbl,
+                                       C.POINTER(P)]
+    lib.cgl_problem_destroy.argtypes = [P]
+    lib.cgl_problem_lipschitz.argtypes = [P, pd]
+    lib.cgl_solve_node.argtypes = [P, C.POINTER(CglNode), pd, C.POINTER(CglResult)]
+    lib.cgl_solve_batch.argtypes = [P, C.POINTER(CglNode), i32, pd, C.POINTER(CglResult)]
+    lib.cgl_certify.argtypes = [P, C.POINTER(CglNode), pd, pd, pd]
+    lib.cgl_problem_matvec.argtypes = [P, i32, pd, pd]
+    lib.cgl_prox_node_batch.argtypes = [P, dbl, dbl, i32, C.POINTER(CglNode), pd, i32, i64, pd, pd]
+    if hasattr(lib, "cgl_server_create"):
+        lib.cgl_server_create.argtypes = [P, C.c_size_t, i32, C.POINTER(P)]
+        lib.cgl_server_submit.argtypes = [P, P, C.POINTER(CglNode), C.POINTER(C.c_uint64)]
+        lib.cgl_server_poll.argtypes = [P, i32, C.POINTER(C.c_uint64), C.POINTER(CglResult), pd,
+                                        i64, pd, C.POINTER(i32)]
+        lib.cgl_server_cancel.argtypes = [P, C.c_uint64]
+        lib.cgl_server_stats.argtypes = [P, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+        lib.cgl_server_destroy.argtypes = [P]
+    _lib = lib
+    return lib
+
+
+def check(code):
+    if code != OK:
+        lib = load()
+        raise CglError(code, lib.cgl_last_error().decode())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        self.lib = load()
+        self.h = C.c_void_p()
+        check(self.lib.cgl_ctx_create(device, stream, C.byref(self.h)))
+
+    def close(self):
+        if self.h:
+            self.lib.cgl_ctx_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Result:
+    lower_bound: float
+    primal: float
+    gap_abs: float
+    gap_rel: float
+    iters: int
+    restarts: int
+    status: str
+    recentres: int
+    err_vs_fp64_est: float
+    beta: np.ndarray | None = None
+
+
+def _result(r: CglResult, beta=None) -> Result:
+    return Result(r.lower_bound, r.primal, r.gap_abs, r.gap_rel, r.iters, r.restarts,
+                  STATUS.get(r.status, str(r.status)), r.recentres, r.err_vs_fp64_est, beta)
+
+
+class NodeSpec:
+    """Holds a CglNode together with the arrays it points to."""
+
+    def __init__(self, p, Z0=(), Z1=(), tol=1e-6, max_iter=100000, check_every=1,
+                 precision="f64", warm_start=None, incumbent=math.inf):
+        self.z0 = np.ascontiguousarray(np.asarray(Z0, dtype=np.int32).reshape(-1))
+        self.z1 = np.ascontiguousarray(np.asarray(Z1, dtype=np.int32).reshape(-1))
+        self.ws = None if warm_start is None else np.ascontiguousarray(warm_start, dtype=np.float64)
+        c = CglNode()
+        load().cgl_node_init(C.byref(c))
+        c.fixed_zero = self.z0.ctypes.data_as(C.POINTER(C.c_int32)) if self.z0.size else None
+        c.n_zero = int(self.z0.size)
+        c.fixed_in = self.z1.ctypes.data_as(C.POINTER(C.c_int32)) if self.z1.size else None
+        c.n_in = int(self.z1.size)
+        c.tol = float(tol)
+        c.max_iter = int(max_iter)
+        c.check_every = int(check_every)
+        c.precision = PREC[precision] if isinstance(precision, str) else int(precision)
+        c.warm_start = _dptr(self.ws) if self.ws is not None else None
+        c.incumbent = float(incumbent)
+        self.c = c
+
+
+class Problem:
+    """A problem (X, y, loss, lambda2, M, k) resident on the device.
+
+    X: numpy array (float64, float32, or uint16 bfloat16 patterns), or a torch CUDA tensor of
+    one of those dtypes (then no host copy is made)."""
+
+    def __init__(self, ctx: Context, X, y, loss="ls", lam2=1e-3, M=2.0, k=10, L=0.0):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        mem = MEM_HOST
+        if hasattr(X, "data_ptr"):  # torch tensor on the device
+            import torch
+
+            assert X.is_cuda and X.is_contiguous()
+            dt = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}[X.dtype]
+            n, p = X.shape
+            ptr = C.c_void_p(X.data_ptr())
+            mem = MEM_DEVICE
+            self._keep = X
+        else:
+            X = np.ascontiguousarray(X)
+            dt = {np.dtype(np.float64): F64, np.dtype(np.float32): F32,
+                  np.dtype(np.uint16): BF16}[X.dtype]
+            n, p = X.shape
+            ptr = X.ctypes.data_as(C.c_void_p)
+            self._keep = X
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        self.n, self.p = int(n), int(p)
+        self.h = C.c_void_p()
+        check(self.lib.cgl_problem_create(ctx.h, ptr, dt, mem, n, p, p, _dptr(y), LOSS[loss],
+                                          float(lam2), float(M), int(k), float(L),
+                                          C.byref(self.h)))
+        self._keep = None
+
+    def close(self):
+        if self.h:
+            self.lib.cgl_problem_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def L(self) -> float:
+        v = C.c_double()
+        check(self.lib.cgl_problem_lipschitz(self.h, C.byref(v)))
+        return v.value
+
+    def node(self, **kw) -> NodeSpec:
+        return NodeSpec(self.p, **kw)
+
+    def solve(self, Z0=(), Z1=(), **kw) -> Result:
+        spec = NodeSpec(self.p, Z0=Z0, Z1=Z1, **kw)
+        beta = np.empty(self.p)
+        r = CglResult()
+        check(self.lib.cgl_solve_node(self.h, C.byref(spec.c), _dptr(beta), C.byref(r)))
+        return _result(r, beta)
+
+    def solve_batch(self, specs: list[NodeSpec]) -> list[Result]:
+        arr = (CglNode * len(specs))(*[s.c for s in specs])
+        res = (CglResult * len(specs))()
+        betas = np.empty((len(specs), self.p))
+        check(self.lib.cgl_solve_batch(self.h, arr, len(specs), _dptr(betas), res))
+        return [_result(res[i], betas[i]) for i in range(len(specs))]
+
+    def certify(self, beta, Z0=(), Z1=()):
+        spec = NodeSpec(self.p, Z0=Z0, Z1=Z1)
+        b = np.ascontiguousarray(beta, dtype=np.float64)
+        P, D = C.c_double(), C.c_double()
+        check(self.lib.cgl_certify(self.h, C.byref(spec.c), _dptr(b), C.byref(P), C.byref(D)))
+        return P.value, D.value
+
+    def matvec(self, v, trans=False):
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        out = np.empty(self.p if trans else self.n)
+        check(self.lib.cgl_problem_matvec(self.h, 1 if trans else 0, _dptr(v), _dptr(out)))
+        return out
+
+
+def prox_node_batch(ctx: Context, W, rho, M, k, sets=None):
+    """Device prox for each row of W; sets: None or a list of (Z0, Z1). Returns (beta, g)."""
+    W = np.ascontiguousarray(np.atleast_2d(W), dtype=np.float64)
+    count, p = W.shape
+    specs = [NodeSpec(p, Z0=z0, Z1=z1) for (z0, z1) in sets] if sets is not None else None
+    arr = (CglNode * count)(*[s.c for s in specs]) if specs else None
+    beta = np.empty_like(W)
+    g = np.empty(count)
+    check(ctx.lib.cgl_prox_node_batch(ctx.h, float(rho), float(M), int(k), arr, _dptr(W), count,
+                                      p, _dptr(beta), _dptr(g)))
+    return beta, g

@@ -1,0 +1,89 @@
+// Host-side engine objects of libcertglm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/certglm.h"
+#include "kernels.h"
+#include "solver.h"
+
+struct cgl_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+};
+
+namespace cgl {
+
+[[noreturn]] void invalid(const std::string& m);
+
+// Owning device allocation.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf();
+  void alloc(size_t b);
+  void reset();
+  template <typename T>
+  T* as() const { return static_cast<T*>(ptr); }
+};
+
+int64_t pad_cols(int64_t p);
+
+// Validated node on the host.
+struct NodeHost {
+  std::vector<uint8_t> cls;  // per coordinate: CLS_FREE / CLS_ZERO / CLS_ONE
+  int kp = 0;                // k - |Z1|
+  int nfree = 0;
+  bool infeasible = false;
+};
+
+NodeHost make_node_host(const cgl_node& nd, int64_t p, int k);
+NodeDev make_node_dev(const cgl_node& nd, const NodeHost& h);
+void fill_result(const NodeDev& s, cgl_result* r);
+void infeasible_result(cgl_result* r, double* beta_out, int64_t p);
+
+struct Problem;
+
+// Workspace of the plain per-node path (reused across solves of one problem).
+struct PlainWork {
+  bool ready = false;
+  PlainGeom geom{};
+  DevBuf bring, uring, bbest, w, h, part, fpart, lpart, cls, st;
+  NodeDev* st_host = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  void ensure(Problem& P);
+  ~PlainWork();
+};
+
+struct MixedWork;  // batch.cpp
+
+struct Problem {
+  cgl_ctx* ctx = nullptr;
+  int64_t n = 0, p = 0, ldx = 0;
+  int xtype = XT_F64;
+  int loss = LOSS_LS;
+  double lam2 = 0, M = 0, L = 0, rho = 0;
+  int k = 0;
+  DevBuf X;  // n x ldx in the stored precision, zero padded
+  DevBuf y;  // n doubles
+  PlainWork plain;
+  MixedWork* mixed = nullptr;  // created on first mixed solve
+  ~Problem();
+};
+
+void solve_plain(Problem& P, const cgl_node& nd, const NodeHost& nh, double* beta_out,
+                 cgl_result* res);
+void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_out,
+                 cgl_result* res);
+void certify_host_beta(Problem& P, const NodeHost& nh, const double* beta, double* primal,
+                       double* dual);
+
+}  // namespace cgl

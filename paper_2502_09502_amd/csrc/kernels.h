@@ -1,0 +1,50 @@
+// Host-side launchers of the HIP kernels (implemented in kernels_*.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "solver.h"
+
+namespace cgl {
+
+struct PlainGeom {
+  int64_t ntiles;      // column tiles of k_xt
+  int nchunks;         // row chunks of k_xt (partials per column)
+  int64_t chunk_rows;  // rows per chunk
+  int nxb;             // workgroups of k_xb (loss partials)
+};
+
+int64_t xt_vec(int xtype);
+PlainGeom plain_geometry(int xtype, int64_t n, int64_t p_pad);
+int prox_elems(int64_t p);
+
+void launch_xb(int xtype, const void* X, int64_t ldx, int64_t n, int64_t p_pad, const double* b,
+               int64_t bs, double* u, int64_t us, const NodeDev* st, const double* y, int loss,
+               double* loss_part, hipStream_t stream);
+void launch_xt(int xtype, const void* X, int64_t ldx, int64_t n, int64_t p_pad,
+               const PlainGeom& g, const double* u, int64_t us, const NodeDev* st,
+               const double* y, int loss, int mode, double* part, double* fpart,
+               hipStream_t stream);
+void launch_grad_step(const double* part, int nchunks, int64_t p_pad, const NodeDev* st,
+                      const double* b_base, int64_t b_stride, double inv_L, double* h, double* w,
+                      hipStream_t stream);
+void launch_prox(int nodes, const double* w, int64_t w_ld, const double* h, int64_t h_ld,
+                 const uint8_t* cls, int64_t cls_ld, int64_t p, double rho, double M,
+                 double two_l2, NodeDev* st, double* b_base, int64_t b_stride,
+                 int64_t b_node_stride, hipStream_t stream);
+void launch_finish(const double* loss_part, int nloss, const double* fstar_part, int nfstar,
+                   double two_l2, NodeDev* st, const double* b_base, int64_t b_stride,
+                   double* b_best, int64_t p, hipStream_t stream);
+void launch_init_state(const double* loss_part, int nloss, double L0_g, NodeDev* st,
+                       hipStream_t stream);
+
+void launch_power_normalize(const double* z, double* v, int64_t p, double* lam,
+                            hipStream_t stream);
+void launch_resid(const double* u, const double* y, int64_t n, int loss, double* r,
+                  double* part2, hipStream_t stream);
+void launch_g_gstar(int nodes, const double* beta, int64_t b_ld, const double* h, int64_t h_ld,
+                    const uint8_t* cls, int64_t cls_ld, const NodeDev* st, int64_t p, double M,
+                    double two_l2, double* out, hipStream_t stream);
+
+}  // namespace cgl

@@ -370,8 +370,8 @@ __global__ __launch_bounds__(256) void k_finish(const double* __restrict__ loss_
     int status = kRunning;
     if (!isfinite(Lnew) && !isinf(Lnew)) status = 3;           // NUMERIC (NaN)
     else if (gap <= st->tol) status = 0;                      // CONVERGED
-    else if (st->D_best > st->incumbent) status = 5;          // PRUNED
-    else if (st->P_best < st->incumbent) status = 6;          // BELOW_INCUMBENT
+    else if (isfinite(st->incumbent) && st->D_best > st->incumbent) status = 5;  // PRUNED
+    else if (isfinite(st->incumbent) && st->P_best < st->incumbent) status = 6;  // BELOW_INC.
     else if (iter + 1 > st->max_iter) status = 1;             // NOT_CONVERGED
     st->iter = iter + 1;
     st->c = st->phi / (st->phi + 3.0);

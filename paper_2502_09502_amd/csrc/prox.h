@@ -10,11 +10,12 @@
 //   phi(v) = sum_{head} [ (v - u_j) + rho min(v, M) ]_+  -  sum_{tail} (u_j - v)_+ ,
 //
 // (the stationarity of the pooled block objective: head members are those with
-// huber_prox(rho, u_j) < v, tail members those with u_j > v). Every pooled value equals v*, so
-// after the Moreau identity
+// huber_prox(rho, u_j) < v, tail members those with u_j > v). Every pooled value equals v*: the
+// isotonic solution is nu_j = max(huber_prox(rho, u_j), v*) on the head and min(u_j, v*) on the
+// tail, so after the Moreau identity (|beta_j| = (u_j - nu_j) / rho)
 //
 //   |beta_j| = ( u_j - max(c_j, v*) )_+ / rho,   c_j = huber_prox(rho, u_j) on the head,
-//                                                c_j = u_j on the tail,
+//                                                c_j = 0 on the tail,
 //
 // i.e. ridge-and-clip min(rho|w_j|/(1+rho), M) for head non-members, soft threshold
 // |w_j| - v*/rho for block members and 0 for the rest of the tail; signs follow w.
@@ -300,10 +301,16 @@ __device__ double tail_root(const double (&u)[E], const bool (&act)[E], int kh, 
         const int b = lane * 4 + i;
         const int ic = runc + c[i];
         const double is = runs + sv[i];
-        const double tau = bitsd(prefix | (((uint64_t)b) << shift));
+        const uint64_t ekey = prefix | (((uint64_t)b) << shift);
+        const double tau = bitsd(ekey);
+        // only edges inside [lo, hi] order like their bins: a digit that covers the sign bit
+        // would otherwise decode to negative edges, and NaN / inf edges are meaningless
+        const bool eligible = (ekey >> 63) == 0 && tau <= hi;
         const double ph = head_part(sm.hu, kh, tau, rho, M) -
                           ((s_above + is) - (double)(m_above + ic) * tau);
-        if (best < 0 && ph <= 0.0) { best = b; best_above_c = runc; best_above_s = runs; }
+        if (best < 0 && eligible && ph <= 0.0) {
+          best = b; best_above_c = runc; best_above_s = runs;
+        }
         runc = ic;
         runs = is;
       }
@@ -341,7 +348,10 @@ __device__ double tail_root(const double (&u)[E], const bool (&act)[E], int kh, 
     m_above += above_c;
     s_above += above_s;
     lo = bitsd(prefix | (((uint64_t)b) << shift));
-    if (b < 255) hi = fmin(hi, bitsd(prefix | (((uint64_t)(b + 1)) << shift)));
+    if (b < 255) {
+      const uint64_t nkey = prefix | (((uint64_t)(b + 1)) << shift);
+      if ((nkey >> 63) == 0) hi = fmin(hi, bitsd(nkey));
+    }
     if (binc == 0) return final_root(sm.hu, kh, lo, hi, m_above, s_above, rho, M, sm);
     if (binc == 1 || shift == 0) {
       const double uc = (binc == 1) ? bins : bitsd(prefix | (uint64_t)b);
@@ -470,7 +480,7 @@ __device__ ProxOut node_prox(const double (&w)[E], const uint8_t (&cls)[E], int 
 #pragma unroll
   for (int s = 0; s < E; ++s) {
     if (freeb[s]) {
-      const double c = head[s] ? huber_prox(rho, u[s], M) : u[s];
+      const double c = head[s] ? huber_prox(rho, u[s], M) : 0.0;
       const double t = u[s] - fmax(c, vstar);
       double mag = t > 0.0 ? t / rho : 0.0;
       beta[s] = copysign(mag, w[s]);

@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Node relaxations solved per second at 1e-6 relative gap on one MI355X.
+
+Workload (one step): 256 least-squares node relaxations of the k-sparse, box-constrained ridge
+GLM that share one design X (n = 20000, p = 10000, Toeplitz-correlated Gaussian rows with
+rho = 0.5, standardised columns, stored in BF16), k = 10, M = 2, lambda2 = 1e-3, each node with
+random fixed-zero / fixed-in sets of sizes uniform in [0, 20] / [0, 10]. Every node is solved to
+an FP64-certified relative gap <= 1e-6.
+
+The step runs the batched mixed-precision engine (BF16 MFMA products with FP32 accumulation
+around FP64 base points) when the library has it, else the plain FP64 per-node path; the plain
+FP64 per-node path is also timed on a subset of the same nodes as the comparator.
+
+Prints one JSON line (see the printed keys). Inputs are resident in HBM before the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2502_09502_amd import _lib, synth  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = ("256 least-squares node relaxations sharing X: n=20000, p=10000, BF16 X "
+            "(Toeplitz rho=0.5, standardised), k=10, M=2, lambda2=1e-3, |Z0|~U[0,20], "
+            "|Z1|~U[0,10], FP64-certified rel. gap 1e-6")
+KERNEL_NAMES = {0: "k_xt (plain X^T pass)", 1: "k_xb (plain X pass)",
+                2: "mfma X^T pass", 3: "mfma X pass", 4: "fp64 batched pass"}
+
+
+def algorithmic_bytes(which: int, n: int, p: int, sx: int, nodes: int) -> float:
+    """Bytes a launch must move at minimum: X once, plus the vectors it reads and writes."""
+    if which == 0:  # h = X^T grad f(u_gamma): X, u^t, u^{t-1}, y, h
+        return n * p * sx + 8.0 * (3 * n + p)
+    if which == 1:  # u = X beta: X, beta, u, y
+        return n * p * sx + 8.0 * (p + 2 * n)
+    if which == 2:  # batched X^T pass: X, BF16 operand (nodes x n), FP32 output (nodes x p)
+        return n * p * sx + nodes * (2.0 * n + 4.0 * p)
+    if which == 3:  # batched X pass: X, BF16 operand (nodes x p), FP32 output (nodes x n)
+        return n * p * sx + nodes * (2.0 * p + 4.0 * n)
+    return n * p * sx + nodes * 8.0 * (n + p)
+
+
+def roofline(ctx, n, p, sx, nodes, candidates):
+    best = None
+    for w in candidates:
+        ms, cnt = ctx.kernel_stats(w)
+        if cnt > 0 and (best is None or ms > best[1]):
+            best = (w, ms, cnt)
+    if best is None:
+        return None
+    w, ms, cnt = best
+    avg_s = ms / cnt / 1e3
+    achieved = algorithmic_bytes(w, n, p, sx, nodes) / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": KERNEL_NAMES[w], "avg_launch_us": round(avg_s * 1e6, 2),
+            "launches": cnt, "bytes_per_launch": algorithmic_bytes(w, n, p, sx, nodes)}
+
+
+def cpu_baseline(d, node_set, L, gpu_iters):
+    """The oracle on the machine's host cores, on a bounded sample: the first iterations of Alg. 3
+    for node 0 of the workload, scaled to the iterations that node needs on the GPU."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = sum(int(i.get("num_threads", 0)) for i in threadpool_info()
+                    if i.get("user_api") == "blas") or os.cpu_count()
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count()
+    z0, z1 = node_set
+    t0 = time.perf_counter()
+    r = oracle.solve_node(d.X, d.y, "ls", d.lam2, d.M, d.k, z0, z1, tol=1e-6, max_iter=2, L=L)
+    t_first = time.perf_counter() - t0
+    per_it = t_first / max(r.iters, 1)
+    more = int(max(2, min(60, 15.0 / max(per_it, 1e-3))))
+    t0 = time.perf_counter()
+    r = oracle.solve_node(d.X, d.y, "ls", d.lam2, d.M, d.k, z0, z1, tol=1e-6, max_iter=more, L=L)
+    t = time.perf_counter() - t0
+    per_it = t / max(r.iters, 1)
+    value = 1.0 / (per_it * max(gpu_iters, 1))
+    return {"value": value, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"oracle (FP64 NumPy) Alg. 3 on node 0 of the workload: {r.iters} "
+                       f"iterations in {t:.1f} s ({per_it * 1e3:.0f} ms/iteration), scaled to the "
+                       f"{gpu_iters} iterations node 0 takes to certify 1e-6 on the GPU")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nodes", type=int, default=256)
+    ap.add_argument("--plain-nodes", type=int, default=16,
+                    help="nodes of the plain FP64 per-node comparator")
+    ap.add_argument("--mode", choices=["auto", "batched", "plain"], default="auto")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (nodes shard "
+              "across GPUs with no per-iteration communication; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    t_setup = time.perf_counter()
+    d = synth.make_config("c4")
+    sets = synth.node_sets(d.p, d.k, args.nodes, 20, config_id=4)
+    ctx = _lib.Context(0)
+    prob = _lib.Problem(ctx, d.X_store, d.y, loss="ls", lam2=d.lam2, M=d.M, k=d.k)
+    L = prob.L
+    print(f"# setup {time.perf_counter() - t_setup:.1f}s  L={L:.6g}", file=sys.stderr, flush=True)
+
+    def specs(prec):
+        return [prob.node(Z0=z0, Z1=z1, tol=1e-6, precision=prec) for z0, z1 in sets]
+
+    mode = args.mode
+    if mode == "auto":
+        mode = "batched"
+        try:
+            prob.solve_batch(specs("mixed")[:1])
+        except _lib.CglError:
+            mode = "plain"
+    step_specs = specs("mixed" if mode == "batched" else "f64")
+
+    for _ in range(args.warmup):
+        prob.solve_batch(step_specs)
+    ctx.set_profiling(True)
+    for w in range(8):
+        ctx.kernel_stats(w, reset=True)
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(args.steps):
+        results = prob.solve_batch(step_specs)
+    t1 = time.perf_counter()
+    ctx.set_profiling(False)
+    elapsed = t1 - t0
+    value = args.steps * len(step_specs) / elapsed
+    roof = roofline(ctx, d.n, d.p, 2, len(step_specs), [2, 3, 4] if mode == "batched" else [0, 1])
+    ok = all(r.status == "converged" and r.gap_rel <= 1e-6 for r in results)
+    iters = [r.iters for r in results]
+    print(f"# {mode}: {value:.2f} solves/s, all certified: {ok}, iterations median "
+          f"{statistics.median(iters)} max {max(iters)}", file=sys.stderr, flush=True)
+
+    # plain FP64 per-node comparator on the first nodes (each solve is its own latency)
+    plain = None
+    if mode == "batched" and args.plain_nodes > 0:
+        pspecs = specs("f64")[: args.plain_nodes]
+        lat = []
+        tp0 = time.perf_counter()
+        for s in pspecs:
+            ts = time.perf_counter()
+            prob.solve_batch([s])
+            lat.append(time.perf_counter() - ts)
+        tp = time.perf_counter() - tp0
+        plain = {"solves_per_s": len(pspecs) / tp, "nodes": len(pspecs),
+                 "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                 "p99_ms": 1e3 * float(np.percentile(lat, 99))}
+
+    out = {
+        "metric": "node relaxations solved/sec at 1e-6 gap, batched vs plain; p50/p99 latency",
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16-mfma/fp32-acc + fp64 bound" if mode == "batched" else "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "nodes": len(step_specs), "n": d.n, "p": d.p,
+                   "x_dtype": "bf16", "engine": mode},
+        "all_certified": ok,
+        "iterations": {"median": statistics.median(iters), "p99": float(np.percentile(iters, 99)),
+                       "max": max(iters)},
+        "roofline": roof,
+    }
+    if mode == "plain":
+        out["latency_ms"] = {"note": "per-node solve time on the plain path, sequential",
+                             "p50": round(1e3 * elapsed / args.steps / len(step_specs), 3)}
+    if plain is not None:
+        out["plain_fp64_per_node"] = plain
+        out["speedup_vs_plain"] = round(value / plain["solves_per_s"], 2)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(d, sets[0], L, results[0].iters)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -23,7 +23,7 @@ STATUS = {0: "converged", 1: "not_converged", 2: "infeasible", 3: "numeric", 4: 
 
 EXPORTS = [
     "cgl_version", "cgl_status_str", "cgl_last_error", "cgl_node_init", "cgl_ctx_create",
-    "cgl_ctx_destroy", "cgl_problem_create", "cgl_problem_destroy", "cgl_problem_lipschitz",
+    "cgl_ctx_destroy", "cgl_ctx_set_profiling", "cgl_ctx_kernel_stats", "cgl_problem_create", "cgl_problem_destroy", "cgl_problem_lipschitz",
     "cgl_solve_node", "cgl_solve_batch", "cgl_certify", "cgl_problem_matvec",
     "cgl_prox_node_batch", "cgl_server_create", "cgl_server_submit", "cgl_server_poll",
     "cgl_server_cancel", "cgl_server_stats", "cgl_server_destroy",
@@ -75,6 +75,8 @@ def load(path: str = LIB_PATH):
     lib.cgl_node_init.restype = None
     lib.cgl_ctx_create.argtypes = [C.c_int, P, C.POINTER(P)]
     lib.cgl_ctx_destroy.argtypes = [P]
+    lib.cgl_ctx_set_profiling.argtypes = [P, i32]
+    lib.cgl_ctx_kernel_stats.argtypes = [P, i32, i32, pd, C.POINTER(i64)]
     lib.cgl_problem_create.argtypes = [P, P, i32, i32, i64, i64, i64, pd, i32, dbl, dbl, i32, dbl,
                                        C.POINTER(P)]
     lib.cgl_problem_destroy.argtypes = [P]
@@ -116,6 +118,16 @@ class Context:
         if self.h:
             self.lib.cgl_ctx_destroy(self.h)
             self.h = C.c_void_p()
+
+    def set_profiling(self, on: bool):
+        check(self.lib.cgl_ctx_set_profiling(self.h, 1 if on else 0))
+
+    def kernel_stats(self, which: int, reset: bool = False):
+        """(total milliseconds, launches) of one timed kernel (see cgl_ctx_kernel_stats)."""
+        ms, n = C.c_double(), C.c_int64()
+        check(self.lib.cgl_ctx_kernel_stats(self.h, which, 1 if reset else 0, C.byref(ms),
+                                            C.byref(n)))
+        return ms.value, n.value
 
     def __del__(self):
         try:

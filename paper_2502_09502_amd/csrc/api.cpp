@@ -15,6 +15,20 @@
 #include "kernels.h"
 #include "prox.h"
 
+hipEvent_t cgl_ctx::event(size_t i) {
+  while (events.size() <= i) {
+    hipEvent_t e;
+    CGL_HIP(hipEventCreate(&e));
+    events.push_back(e);
+  }
+  return events[i];
+}
+
+cgl_ctx::~cgl_ctx() {
+  for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
 namespace cgl {
 
 static thread_local std::string g_last_error;
@@ -199,17 +213,23 @@ PlainWork::~PlainWork() {
   if (st_host) (void)hipHostFree(st_host);
 }
 
-static void plain_iteration(Problem& P, PlainWork& W, hipStream_t s) {
+// One iteration of Alg. 3 on the plain path. ev (optional): four events bracketing the X^T pass
+// and the X pass, for kernel timing.
+static void plain_iteration(Problem& P, PlainWork& W, hipStream_t s, hipEvent_t* ev = nullptr) {
   const double two_l2 = 2.0 * P.lam2;
   NodeDev* st = W.st.as<NodeDev>();
+  if (ev) CGL_HIP(hipEventRecord(ev[0], s));
   launch_xt(P.xtype, P.X.ptr, P.ldx, P.n, P.ldx, W.geom, W.uring.as<double>(), P.n, st,
             P.y.as<double>(), P.loss, 0, W.part.as<double>(), W.fpart.as<double>(), s);
+  if (ev) CGL_HIP(hipEventRecord(ev[1], s));
   launch_grad_step(W.part.as<double>(), W.geom.nchunks, P.ldx, st, W.bring.as<double>(), P.ldx,
                    1.0 / P.L, W.h.as<double>(), W.w.as<double>(), s);
   launch_prox(1, W.w.as<double>(), 0, W.h.as<double>(), 0, W.cls.as<uint8_t>(), 0, P.p, P.rho,
               P.M, two_l2, st, W.bring.as<double>(), P.ldx, 0, s);
+  if (ev) CGL_HIP(hipEventRecord(ev[2], s));
   launch_xb(P.xtype, P.X.ptr, P.ldx, P.n, P.ldx, W.bring.as<double>(), P.ldx,
             W.uring.as<double>(), P.n, st, P.y.as<double>(), P.loss, W.lpart.as<double>(), s);
+  if (ev) CGL_HIP(hipEventRecord(ev[3], s));
   launch_finish(W.lpart.as<double>(), W.geom.nxb, W.fpart.as<double>(), W.geom.nchunks, two_l2,
                 st, W.bring.as<double>(), P.ldx, W.bbest.as<double>(), P.p, s);
 }
@@ -258,11 +278,36 @@ void solve_plain(Problem& P, const cgl_node& nd, const NodeHost& nh, double* bet
     CGL_HIP(hipGraphDestroy(graph));
   }
   NodeDev* sh = W.st_host;
+  cgl_ctx* ctx = P.ctx;
+  int iter_before = 1;
   for (;;) {
-    if (W.graph_exec) CGL_HIP(hipGraphLaunch(W.graph_exec, s));
-    else for (int i = 0; i < chunk; ++i) plain_iteration(P, W, s);
+    if (ctx->profiling) {
+      for (int i = 0; i < chunk; ++i) {
+        hipEvent_t ev[4] = {ctx->event(4 * i), ctx->event(4 * i + 1), ctx->event(4 * i + 2),
+                            ctx->event(4 * i + 3)};
+        plain_iteration(P, W, s, ev);
+      }
+    } else if (W.graph_exec) {
+      CGL_HIP(hipGraphLaunch(W.graph_exec, s));
+    } else {
+      for (int i = 0; i < chunk; ++i) plain_iteration(P, W, s);
+    }
     CGL_HIP(hipMemcpyAsync(sh, W.st.ptr, sizeof(NodeDev), hipMemcpyDeviceToHost, s));
     CGL_HIP(hipStreamSynchronize(s));
+    if (ctx->profiling) {
+      // only launches of iterations that ran (the rest returned at once) are counted
+      const int ran = std::min(chunk, sh->iter - iter_before);
+      for (int i = 0; i < ran; ++i) {
+        float a = 0.f, b = 0.f;
+        CGL_HIP(hipEventElapsedTime(&a, ctx->event(4 * i), ctx->event(4 * i + 1)));
+        CGL_HIP(hipEventElapsedTime(&b, ctx->event(4 * i + 2), ctx->event(4 * i + 3)));
+        ctx->kt_ms[0] += a;
+        ctx->kt_ms[1] += b;
+        ctx->kt_n[0] += 1;
+        ctx->kt_n[1] += 1;
+      }
+    }
+    iter_before = sh->iter;
     if (sh->done) break;
   }
   fill_result(*sh, res);
@@ -402,8 +447,30 @@ int cgl_ctx_destroy(cgl_ctx* ctx) {
   CGL_API_BEGIN
   if (!ctx) return CGL_OK;
   (void)hipSetDevice(ctx->device);
-  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
+  return CGL_OK;
+  CGL_API_END
+}
+
+int cgl_ctx_set_profiling(cgl_ctx* ctx, int32_t on) {
+  CGL_API_BEGIN
+  if (!ctx) invalid("ctx is NULL");
+  ctx->profiling = on != 0;
+  return CGL_OK;
+  CGL_API_END
+}
+
+int cgl_ctx_kernel_stats(cgl_ctx* ctx, int32_t which, int32_t reset, double* total_ms,
+                         int64_t* launches) {
+  CGL_API_BEGIN
+  if (!ctx) invalid("ctx is NULL");
+  if (which < 0 || which >= 8) invalid("which out of range");
+  if (total_ms) *total_ms = ctx->kt_ms[which];
+  if (launches) *launches = ctx->kt_n[which];
+  if (reset) {
+    ctx->kt_ms[which] = 0.0;
+    ctx->kt_n[which] = 0;
+  }
   return CGL_OK;
   CGL_API_END
 }

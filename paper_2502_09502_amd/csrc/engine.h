@@ -15,6 +15,13 @@ struct cgl_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // kernel timing (cgl_ctx_set_profiling)
+  bool profiling = false;
+  double kt_ms[8] = {0};
+  int64_t kt_n[8] = {0};
+  std::vector<hipEvent_t> events;  // pool, grown on demand
+  hipEvent_t event(size_t i);
+  ~cgl_ctx();
 };
 
 namespace cgl {

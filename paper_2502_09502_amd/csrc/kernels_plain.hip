@@ -305,7 +305,7 @@ __global__ __launch_bounds__(1024) void k_prox(const double* __restrict__ w, int
     else { wr[s] = 0.0; cr[s] = CLS_PAD; }
   }
   double br[E];
-  const ProxOut po = node_prox<E>(wr, cr, st->kp, st->nfree, rho, M, br, sm);
+  const ProxOut po = node_prox<E>(wr, cr, st->kp, st->nfree, rho, M, st->vstar, br, sm);
   double* bout = slot_ptr(b_base + (int64_t)node * b_node_stride, b_stride, iter, 1);
 #pragma unroll
   for (int s = 0; s < E; ++s) {
@@ -328,6 +328,7 @@ __global__ __launch_bounds__(1024) void k_prox(const double* __restrict__ w, int
     st->g_new = po.gval;
     st->gstar_new = gs;
     st->checked = check ? 1 : 0;
+    st->vstar = po.vstar;
   }
 }
 

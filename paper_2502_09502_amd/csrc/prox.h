@@ -20,11 +20,18 @@
 // i.e. ridge-and-clip min(rho|w_j|/(1+rho), M) for head non-members, soft threshold
 // |w_j| - v*/rho for block members and 0 for the rest of the tail; signs follow w.
 //
-// On the GPU the head is found by a byte-wise radix select on the FP64 bit patterns of u (they
-// order like the values for u >= 0), and v* by a radix search over the tail bit patterns that
-// keeps FP64 per-bin counts and sums, so phi can be evaluated exactly at every bin edge; the
-// last interval is solved in closed form. No sort of the p entries is needed.
+// GPU realisation, no sort of the p entries:
+//  * head: the k'+1 largest u (ties: smaller index first) by k'+1 rounds of wave-wide argmax in
+//    each of the 16 waves, merged by one wave; the result comes out sorted (byte-wise radix
+//    select on the FP64 bit patterns for k' > 63);
+//  * v*: a monotone fixed-point iteration. From a lower bound v_0 (the previous iteration's v*
+//    when phi(v_0) <= 0, else 0), take the tail set A = {u > v_k} (one block reduction of its
+//    count and sum) and let v_{k+1} be the exact root of H(v) - sum_A (u - v), solved in closed
+//    form over the <= k'+1 head breakpoints. That function lies above phi on [v_k, inf), so
+//    v_k <= v_{k+1} <= v*; when A stops shrinking, phi(v_{k+1}) = 0 exactly. All sums are FP64.
 #pragma once
+
+#include <limits.h>
 
 #include "common.h"
 
@@ -33,20 +40,22 @@ namespace cgl {
 constexpr int kProxThreads = 1024;
 constexpr int kProxWaves = kProxThreads / kWave;
 constexpr int kMaxHead = 256;  // supports k' <= 256
+constexpr int kWaveSel = 64;   // wave selection handles up to 64 winners (k' <= 63)
 
 enum : uint8_t { CLS_FREE = 0, CLS_ZERO = 1, CLS_ONE = 2, CLS_PAD = 3 };
 
 struct ProxSmem {
-  uint32_t cnt[256];
-  double sum[256];
-  double hu[kMaxHead];  // head u values, sorted decreasingly after gather
+  uint32_t cnt[256];                     // radix histogram (k' > 63)
+  double cand_v[kProxWaves * kWaveSel];  // per-wave winners
+  int cand_i[kProxWaves * kWaveSel];
+  double hu[kMaxHead + 1];  // sorted head u values; hu[k'] = largest tail value
+  int hidx[kMaxHead + 1];
   double tmp[kMaxHead];
-  double redd[kProxWaves * 2];
+  double redd[kProxWaves * 4];
   uint64_t redu[kProxWaves];
   int redi[kProxWaves];
   int head_fill;
   int ties_left;
-  // broadcast slots
   int b_int[4];
   double b_dbl[4];
 };
@@ -70,6 +79,27 @@ __device__ __forceinline__ uint64_t band(uint64_t v, ProxSmem& sm) {
   return block_reduce(v, sm.redu, OpAnd(), ~(uint64_t)0);
 }
 
+// Sum of N values over the block in one pass (N <= 4); every thread receives the totals.
+template <int N>
+__device__ __forceinline__ void block_sum_n(double (&v)[N], ProxSmem& sm) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) sm.redd[i * kProxWaves + wid] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double r = 0.0;
+    for (int w = 0; w < kProxWaves; ++w) r += sm.redd[i * kProxWaves + w];
+    v[i] = r;
+  }
+}
+
 // Inclusive suffix scan across the 64 lanes of a wave (lane i gets sum over lanes >= i).
 template <typename T>
 __device__ __forceinline__ T wave_suffix_incl(T v) {
@@ -82,8 +112,90 @@ __device__ __forceinline__ T wave_suffix_incl(T v) {
   return v;
 }
 
-// Result of a descending selection: selected = key > lo, plus `take` of the keys == lo when
-// `exact`; when !exact, selected = key >= lo (and the count is exactly the requested one).
+// Wave-wide argmax of (value, index): larger value wins, ties go to the smaller index. Every
+// lane receives the winner.
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off, kWave);
+    const int oi = __shfl_xor(i, off, kWave);
+    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+  }
+}
+
+// The K largest active keys (K <= kWaveSel, K <= number of active keys), sorted decreasingly
+// (ties: smaller index first), into sm.hu[0..K) / sm.hidx[0..K). Element s of thread t has index
+// s * kProxThreads + t.
+template <int E>
+__device__ void block_topk(const double (&key)[E], const bool (&act)[E], int K, ProxSmem& sm) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  uint32_t taken = 0;
+  for (int r = 0; r < K; ++r) {
+    double bv = -1.0;  // keys are >= 0
+    int bi = INT_MAX;
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const int j = s * kProxThreads + (int)threadIdx.x;
+      if (act[s] && !((taken >> s) & 1u) && (key[s] > bv || (key[s] == bv && j < bi))) {
+        bv = key[s];
+        bi = j;
+      }
+    }
+    wave_argmax(bv, bi);
+    if (bi != INT_MAX && (bi & (kProxThreads - 1)) == (int)threadIdx.x)
+      taken |= 1u << (bi / kProxThreads);
+    if (lane == 0) {
+      sm.cand_v[wid * kWaveSel + r] = bv;
+      sm.cand_i[wid * kWaveSel + r] = bi;
+    }
+  }
+  __syncthreads();
+  if (wid == 0) {
+    // lane l holds the candidates of waves l / 4 ... : slot q covers wave (q * 4 + l / 16)
+    // simpler: candidate c = q * 64 + lane over the flattened list of kProxWaves * K entries
+    const int total = kProxWaves * K;
+    double cv[kProxWaves];
+    int ci[kProxWaves];
+#pragma unroll
+    for (int q = 0; q < kProxWaves; ++q) {
+      const int c = q * 64 + lane;
+      if (c < total) {
+        const int w = c / K, r = c % K;
+        cv[q] = sm.cand_v[w * kWaveSel + r];
+        ci[q] = sm.cand_i[w * kWaveSel + r];
+      } else {
+        cv[q] = -1.0;
+        ci[q] = INT_MAX;
+      }
+    }
+    uint32_t tk = 0;
+    for (int r = 0; r < K; ++r) {
+      double bv = -1.0;
+      int bi = INT_MAX, bq = -1;
+#pragma unroll
+      for (int q = 0; q < kProxWaves; ++q) {
+        if (!((tk >> q) & 1u) && (cv[q] > bv || (cv[q] == bv && ci[q] < bi))) {
+          bv = cv[q];
+          bi = ci[q];
+          bq = q;
+        }
+      }
+      double wv = bv;
+      int wi = bi;
+      wave_argmax(wv, wi);
+      if (bq >= 0 && bi == wi && wi != INT_MAX) tk |= 1u << bq;
+      if (lane == 0) {
+        sm.hu[r] = wv;
+        sm.hidx[r] = wi;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Result of a descending radix selection: selected = key > lo, plus `take` of the keys == lo
+// when `exact`; when !exact, selected = key >= lo (and the count is exactly the requested one).
 struct Select {
   uint64_t lo;
   bool exact;
@@ -122,18 +234,16 @@ __device__ Select radix_select_desc(const uint64_t (&key)[E], const bool (&act)[
       int loc = 0;
 #pragma unroll
       for (int i = 3; i >= 0; --i) { c[i] = (int)sm.cnt[lane * 4 + i]; loc += c[i]; }
-      int suf = wave_suffix_incl(loc);
-      int excl = suf - loc;  // bins of higher lanes
+      const int suf = wave_suffix_incl(loc);
       int best = -1, above = 0, binc = 0;
-      int run = excl;
+      int run = suf - loc;  // bins of higher lanes
 #pragma unroll
       for (int i = 3; i >= 0; --i) {
-        int incl = run + c[i];
+        const int incl = run + c[i];
         if (best < 0 && incl >= remaining) { best = lane * 4 + i; above = run; binc = c[i]; }
         run = incl;
       }
-      // highest bin whose suffix reaches `remaining`
-      int cand = best;
+      int cand = best;  // highest bin whose suffix count reaches `remaining`
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) cand = max(cand, __shfl_xor(cand, off, kWave));
       if (best == cand && best >= 0) {
@@ -155,215 +265,6 @@ __device__ Select radix_select_desc(const uint64_t (&key)[E], const bool (&act)[
   }
 }
 
-__device__ __forceinline__ bool selected(uint64_t k, const Select& sel, int& tie_slot_out) {
-  tie_slot_out = -1;
-  if (!sel.exact) return k >= sel.lo;
-  if (k > sel.lo) return true;
-  return false;  // ties handled by the caller
-}
-
-// head part of phi: sum over head values hu[0..kh) of [(v - u) + rho min(v, M)]_+
-__device__ __forceinline__ double head_part(const double* hu, int kh, double v, double rho,
-                                            double M) {
-  double acc = 0.0;
-  const double pen = rho * fmin(v, M);
-  for (int i = 0; i < kh; ++i) {
-    double t = (v - hu[i]) + pen;
-    acc += t > 0.0 ? t : 0.0;
-  }
-  return acc;
-}
-
-// Closed form of the root of phi on an interval where the tail members (m, S) are fixed:
-// members of the head are those with huber_prox(rho, u) < v; solve at the membership of `mid`.
-__device__ __forceinline__ double solve_linear_piece(const double* hu, int kh, double mid, int m,
-                                                     double S, double rho, double M) {
-  int nh = 0;
-  double sh = 0.0;
-  for (int i = 0; i < kh; ++i) {
-    if (huber_prox(rho, hu[i], M) < mid) { ++nh; sh += hu[i]; }
-  }
-  if (mid <= M) {
-    double den = (double)m + (double)nh * (1.0 + rho);
-    return den > 0.0 ? (S + sh) / den : mid;
-  }
-  double den = (double)(m + nh);
-  return den > 0.0 ? (S + sh - rho * M * (double)nh) / den : mid;
-}
-
-// Exact root of phi on [lo, hi] with tail members (m, S) fixed. Breakpoints inside come from
-// the head (huber_prox values) and from M. Evaluated by wave 0; result broadcast.
-__device__ double final_root(const double* hu, int kh, double lo, double hi, int m, double S,
-                             double rho, double M, ProxSmem& sm) {
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    // largest point with phi <= 0 and smallest point with phi > 0 among {lo, hi, M, c_i}
-    double a = lo, b = hi;
-    const int npts = kh + 1;
-    for (int base = 0; base < npts; base += 64) {
-      int i = base + lane;
-      if (i < npts) {
-        double pt = (i < kh) ? huber_prox(rho, hu[i], M) : M;
-        if (pt > lo && pt < hi) {
-          double ph = head_part(hu, kh, pt, rho, M) - (S - (double)m * pt);
-          if (ph <= 0.0) a = fmax(a, pt);
-          else b = fmin(b, pt);
-        }
-      }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      a = fmax(a, __shfl_xor(a, off, kWave));
-      b = fmin(b, __shfl_xor(b, off, kWave));
-    }
-    if (lane == 0) {
-      double mid = 0.5 * (a + b);
-      double v = solve_linear_piece(hu, kh, mid, m, S, rho, M);
-      v = fmin(fmax(v, a), b);
-      sm.b_dbl[0] = v;
-    }
-  }
-  __syncthreads();
-  double v = sm.b_dbl[0];
-  __syncthreads();
-  return v;
-}
-
-// v* for the tail (act = free and not head), given the sorted head values in sm.hu[0..kh).
-// Returns v*. umax_tail: largest tail u (phi(umax_tail) >= 0).
-template <int E>
-__device__ double tail_root(const double (&u)[E], const bool (&act)[E], int kh, double rho,
-                            double M, ProxSmem& sm) {
-  uint64_t key[E];
-  uint64_t o = 0, a = ~(uint64_t)0;
-  double umax = 0.0;
-#pragma unroll
-  for (int s = 0; s < E; ++s) {
-    key[s] = dbits(u[s]);
-    if (act[s]) { o |= key[s]; a &= key[s]; umax = fmax(umax, u[s]); }
-  }
-  o = bor(o, sm);
-  a = band(a, sm);
-  umax = bmax(umax, sm);
-  int m_above = 0;
-  double s_above = 0.0;
-  double lo = 0.0, hi = umax;
-  const uint64_t diff = o ^ a;
-  if (diff == 0) {
-    // every tail value equals umax: members iff v* < umax
-    int c = 0;
-#pragma unroll
-    for (int s = 0; s < E; ++s) c += act[s] ? 1 : 0;
-    c = bsum_i(c, sm);
-    double ph = head_part(sm.hu, kh, umax, rho, M);
-    if (ph > 0.0) return final_root(sm.hu, kh, 0.0, umax, c, (double)c * umax, rho, M, sm);
-    return umax;  // phi(umax) = 0 with no tail member: no pooled tail
-  }
-  const int hb = 63 - __clzll(diff);
-  int shift = (hb >> 3) << 3;
-  uint64_t prefix = (shift + 8 >= 64) ? 0 : (a & ~((((uint64_t)1) << (shift + 8)) - 1));
-  const int lane = threadIdx.x & 63;
-  bool first = true;
-  for (;;) {
-    for (int i = threadIdx.x; i < 256; i += blockDim.x) { sm.cnt[i] = 0; sm.sum[i] = 0.0; }
-    __syncthreads();
-    const int hs = shift + 8;
-#pragma unroll
-    for (int s = 0; s < E; ++s) {
-      if (act[s] && (hs >= 64 || (key[s] >> hs) == (prefix >> hs))) {
-        const int bin = (int)((key[s] >> shift) & 255);
-        atomicAdd(&sm.cnt[bin], 1u);
-        atomicAdd(&sm.sum[bin], u[s]);
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      int c[4];
-      double sv[4];
-      int loc = 0;
-      double locs = 0.0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        c[i] = (int)sm.cnt[lane * 4 + i];
-        sv[i] = sm.sum[lane * 4 + i];
-        loc += c[i];
-        locs += sv[i];
-      }
-      const int sufc = wave_suffix_incl(loc);
-      const double sufs = wave_suffix_incl(locs);
-      int runc = sufc - loc;      // bins above this lane's four
-      double runs = sufs - locs;
-      int best = -1;
-      int best_above_c = 0;
-      double best_above_s = 0.0;
-#pragma unroll
-      for (int i = 3; i >= 0; --i) {
-        const int b = lane * 4 + i;
-        const int ic = runc + c[i];
-        const double is = runs + sv[i];
-        const uint64_t ekey = prefix | (((uint64_t)b) << shift);
-        const double tau = bitsd(ekey);
-        // only edges inside [lo, hi] order like their bins: a digit that covers the sign bit
-        // would otherwise decode to negative edges, and NaN / inf edges are meaningless
-        const bool eligible = (ekey >> 63) == 0 && tau <= hi;
-        const double ph = head_part(sm.hu, kh, tau, rho, M) -
-                          ((s_above + is) - (double)(m_above + ic) * tau);
-        if (best < 0 && eligible && ph <= 0.0) {
-          best = b; best_above_c = runc; best_above_s = runs;
-        }
-        runc = ic;
-        runs = is;
-      }
-      int cand = best;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) cand = max(cand, __shfl_xor(cand, off, kWave));
-      if (lane == 0 && cand < 0) {
-        sm.b_int[0] = -1;
-        sm.b_int[1] = sufc;  // lane 0 holds the total
-        sm.b_dbl[1] = sufs;
-      }
-      if (cand >= 0 && best == cand) {
-        sm.b_int[0] = best;
-        sm.b_int[1] = best_above_c;
-        sm.b_dbl[1] = best_above_s;
-        sm.b_int[2] = c[best & 3];
-        sm.b_dbl[2] = sv[best & 3];
-      }
-    }
-    __syncthreads();
-    const int b = sm.b_int[0];
-    const int above_c = sm.b_int[1];
-    const double above_s = sm.b_dbl[1];
-    const int binc = sm.b_int[2];
-    const double bins = sm.b_dbl[2];
-    __syncthreads();
-    if (b < 0) {
-      // phi > 0 at the bottom of the range: every candidate is a member (first pass only)
-      const double top = bitsd(prefix);
-      (void)first;
-      return final_root(sm.hu, kh, lo, fmin(top, hi), m_above + above_c, s_above + above_s,
-                        rho, M, sm);
-    }
-    first = false;
-    m_above += above_c;
-    s_above += above_s;
-    lo = bitsd(prefix | (((uint64_t)b) << shift));
-    if (b < 255) {
-      const uint64_t nkey = prefix | (((uint64_t)(b + 1)) << shift);
-      if ((nkey >> 63) == 0) hi = fmin(hi, bitsd(nkey));
-    }
-    if (binc == 0) return final_root(sm.hu, kh, lo, hi, m_above, s_above, rho, M, sm);
-    if (binc == 1 || shift == 0) {
-      const double uc = (binc == 1) ? bins : bitsd(prefix | (uint64_t)b);
-      const double ph = head_part(sm.hu, kh, uc, rho, M) - (s_above - (double)m_above * uc);
-      if (ph <= 0.0) return final_root(sm.hu, kh, uc, hi, m_above, s_above, rho, M, sm);
-      return final_root(sm.hu, kh, lo, uc, m_above + binc, s_above + bins, rho, M, sm);
-    }
-    prefix |= ((uint64_t)b) << shift;
-    shift -= 8;
-  }
-}
-
 // Rank-sort sm.hu[0..kh) decreasingly (ties keep an arbitrary but consistent order).
 __device__ __forceinline__ void sort_head_desc(int kh, ProxSmem& sm) {
   for (int i = threadIdx.x; i < kh; i += blockDim.x) sm.tmp[i] = sm.hu[i];
@@ -378,6 +279,86 @@ __device__ __forceinline__ void sort_head_desc(int kh, ProxSmem& sm) {
     sm.hu[r] = x;
   }
   __syncthreads();
+}
+
+// head part of phi: sum over head values hu[0..kh) of [(v - u) + rho min(v, M)]_+
+__device__ __forceinline__ double head_part(const double* hu, int kh, double v, double rho,
+                                            double M) {
+  double acc = 0.0;
+  const double pen = rho * fmin(v, M);
+  for (int i = 0; i < kh; ++i) {
+    const double t = (v - hu[i]) + pen;
+    acc += t > 0.0 ? t : 0.0;
+  }
+  return acc;
+}
+
+// Root of psi(v) = H(v) - (S - m v) on [vlo, inf) (psi increasing, psi(vlo) <= 0). Breakpoints
+// of H: huber_prox(rho, hu_i, M) and M. Every wave evaluates it (no barrier needed).
+__device__ double psi_root(const double* hu, int kh, double vlo, double m, double S, double rho,
+                           double M) {
+  const int lane = threadIdx.x & 63;
+  double a = vlo, b = HUGE_VAL;
+  for (int base = 0; base <= kh; base += 64) {
+    const int i = base + lane;
+    if (i <= kh) {
+      const double pt = (i < kh) ? huber_prox(rho, hu[i], M) : M;
+      if (pt > vlo) {
+        const double ps = head_part(hu, kh, pt, rho, M) - (S - m * pt);
+        if (ps <= 0.0) a = fmax(a, pt);
+        else b = fmin(b, pt);
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a = fmax(a, __shfl_xor(a, off, kWave));
+    b = fmin(b, __shfl_xor(b, off, kWave));
+  }
+  // membership of the head and the regime of min(v, M) are constant on (a, b)
+  const double mid = isinf(b) ? a + fmax(1.0, fabs(a)) : 0.5 * (a + b);
+  double nh = 0.0, sh = 0.0;
+  for (int i = 0; i < kh; ++i) {
+    if (huber_prox(rho, hu[i], M) < mid) { nh += 1.0; sh += hu[i]; }
+  }
+  double v;
+  if (mid <= M) {
+    const double den = m + nh * (1.0 + rho);
+    v = den > 0.0 ? (S + sh) / den : a;
+  } else {
+    const double den = m + nh;
+    v = den > 0.0 ? (S + sh - rho * M * nh) / den : a;
+  }
+  return fmin(fmax(v, a), b);
+}
+
+// v* over the tail (see the file comment). hu[0..kh): sorted head values. v0: a hint.
+template <int E>
+__device__ double tail_root(const double (&u)[E], const bool (&tail)[E], const double* hu,
+                           int kh, double v0, double rho, double M, ProxSmem& sm) {
+  double v = v0 > 0.0 ? v0 : 0.0;
+  double m_prev = -1.0;
+  bool checked_start = v == 0.0;
+  for (int it = 0; it < 4096; ++it) {
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      if (tail[s] && u[s] > v) { acc[0] += 1.0; acc[1] += u[s]; }
+    }
+    block_sum_n<2>(acc, sm);
+    const double m = acc[0], S = acc[1];
+    if (!checked_start) {
+      checked_start = true;
+      if (head_part(hu, kh, v, rho, M) - (S - m * v) > 0.0) {  // hint above v*: start at 0
+        v = 0.0;
+        continue;
+      }
+    }
+    if (m == m_prev) break;  // the member set did not change: v is the root
+    v = psi_root(hu, kh, v, m, S, rho, M);
+    m_prev = m;
+  }
+  return v;
 }
 
 // Alg. 2 on the head magnitudes |beta| (sorted decreasingly, kh entries, the top of |beta_F|)
@@ -398,15 +379,16 @@ __device__ __forceinline__ double alg2_from_sorted(const double* mag, int kh, in
 }
 
 struct ProxOut {
-  double gval;  // g_node(beta)
-  double vstar; // pooled value (diagnostic)
+  double gval;   // g_node(beta)
+  double vstar;  // pooled value (warm start of the next call)
 };
 
-// Node prox in registers. w: element s of this thread is index j = s * blockDim + tid.
-// cls: CLS_*; kp = k - |Z1| (>= 0); nfree = |F|. beta receives the result.
+// Node prox in registers. w: element s of this thread is index j = s * kProxThreads + tid.
+// cls: CLS_*; kp = k - |Z1| (>= 0); nfree = |F|; vhint: previous v* (0 if none).
 template <int E>
 __device__ ProxOut node_prox(const double (&w)[E], const uint8_t (&cls)[E], int kp, int nfree,
-                             double rho, double M, double (&beta)[E], ProxSmem& sm) {
+                             double rho, double M, double vhint, double (&beta)[E],
+                             ProxSmem& sm) {
   double u[E];
   bool freeb[E];
   double z1sq = 0.0;
@@ -424,20 +406,16 @@ __device__ ProxOut node_prox(const double (&w)[E], const uint8_t (&cls)[E], int 
   }
   ProxOut out;
   out.vstar = 0.0;
-  if (kp <= 0 || nfree == 0) {
-    // F pinned to zero (no budget) or empty
+  if (kp <= 0 || nfree == 0) {  // F pinned to zero (no budget left) or empty
     out.gval = 0.5 * bsum(z1sq, sm);
     return out;
   }
-  if (kp >= nfree) {
-    // every free coordinate can take z = 1: ridge-and-clip, g = 1/2 ||beta||^2
+  if (kp >= nfree) {  // every free coordinate can take z = 1: ridge-and-clip, g = 1/2 ||beta||^2
     double sq = z1sq;
 #pragma unroll
     for (int s = 0; s < E; ++s) {
-      if (freeb[s]) {
-        double b = fmin(u[s] / (1.0 + rho), M);
-        b = copysign(b, w[s]);
-        if (w[s] == 0.0) b = 0.0;
+      if (freeb[s] && w[s] != 0.0) {
+        const double b = copysign(fmin(u[s] / (1.0 + rho), M), w[s]);
         beta[s] = b;
         sq += b * b;
       }
@@ -445,60 +423,76 @@ __device__ ProxOut node_prox(const double (&w)[E], const uint8_t (&cls)[E], int 
     out.gval = 0.5 * bsum(sq, sm);
     return out;
   }
-  // ---- head: top-kp of u over F
-  uint64_t key[E];
-#pragma unroll
-  for (int s = 0; s < E; ++s) key[s] = dbits(u[s]);
-  const Select sel = radix_select_desc<E>(key, freeb, kp, sm);
-  if (threadIdx.x == 0) { sm.head_fill = 0; sm.ties_left = sel.exact ? sel.take : 0; }
-  __syncthreads();
+  // ---- head: the kp largest u over F (sorted into sm.hu), and the largest tail value
   bool head[E];
+  double umax_tail;
+  if (kp + 1 <= kWaveSel) {
+    block_topk<E>(u, freeb, kp + 1, sm);
+    const double tv = sm.hu[kp - 1];
+    const int ti = sm.hidx[kp - 1];
 #pragma unroll
-  for (int s = 0; s < E; ++s) {
-    bool h = false;
-    if (freeb[s]) {
-      if (!sel.exact) h = key[s] >= sel.lo;
-      else if (key[s] > sel.lo) h = true;
-      else if (key[s] == sel.lo) h = atomicSub(&sm.ties_left, 1) > 0;
+    for (int s = 0; s < E; ++s) {
+      const int j = s * kProxThreads + (int)threadIdx.x;
+      head[s] = freeb[s] && (u[s] > tv || (u[s] == tv && j <= ti));
     }
-    head[s] = h;
-    if (h) {
-      const int slot = atomicAdd(&sm.head_fill, 1);
-      sm.hu[slot] = u[s];
+    umax_tail = sm.hu[kp];
+  } else {
+    uint64_t key[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) key[s] = dbits(u[s]);
+    const Select sel = radix_select_desc<E>(key, freeb, kp, sm);
+    if (threadIdx.x == 0) { sm.head_fill = 0; sm.ties_left = sel.exact ? sel.take : 0; }
+    __syncthreads();
+    double tmax = -1.0;
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      bool h = false;
+      if (freeb[s]) {
+        if (!sel.exact) h = key[s] >= sel.lo;
+        else if (key[s] > sel.lo) h = true;
+        else if (key[s] == sel.lo) h = atomicSub(&sm.ties_left, 1) > 0;
+      }
+      head[s] = h;
+      if (h) sm.hu[atomicAdd(&sm.head_fill, 1)] = u[s];
+      else if (freeb[s]) tmax = fmax(tmax, u[s]);
     }
+    __syncthreads();
+    sort_head_desc(kp, sm);
+    umax_tail = bmax(tmax, sm);
   }
-  __syncthreads();
-  sort_head_desc(kp, sm);
-  // ---- tail root
+  // ---- v*
   bool tail[E];
 #pragma unroll
   for (int s = 0; s < E; ++s) tail[s] = freeb[s] && !head[s];
-  const double vstar = tail_root<E>(u, tail, kp, rho, M, sm);
+  double vstar;
+  if (huber_prox(rho, sm.hu[kp - 1], M) >= umax_tail) {
+    vstar = umax_tail;  // no isotonic violation at the junction: no pooled block
+  } else {
+    vstar = tail_root<E>(u, tail, sm.hu, kp, vhint, rho, M, sm);
+  }
   out.vstar = vstar;
-  // ---- assemble beta, |beta_F| total, Z1 squares
-  double absF = 0.0;
+  // ---- assemble beta; |beta_F| total and Z1 squares in one reduction
+  double acc[2] = {0.0, z1sq};
 #pragma unroll
   for (int s = 0; s < E; ++s) {
     if (freeb[s]) {
       const double c = head[s] ? huber_prox(rho, u[s], M) : 0.0;
       const double t = u[s] - fmax(c, vstar);
-      double mag = t > 0.0 ? t / rho : 0.0;
-      beta[s] = copysign(mag, w[s]);
-      if (mag == 0.0) beta[s] = 0.0;
-      absF += mag;
+      const double mag = t > 0.0 ? t / rho : 0.0;
+      beta[s] = mag > 0.0 ? copysign(mag, w[s]) : 0.0;
+      acc[0] += mag;
     }
   }
-  // head magnitudes in sorted order (monotone in u)
+  // head magnitudes in sorted order (|beta| is monotone in u)
   for (int i = threadIdx.x; i < kp; i += blockDim.x) {
     const double uh = sm.hu[i];
     const double t = uh - fmax(huber_prox(rho, uh, M), vstar);
     sm.tmp[i] = t > 0.0 ? t / rho : 0.0;
   }
-  const double sF = bsum(absF, sm);
-  const double sq1 = bsum(z1sq, sm);
-  if (threadIdx.x == 0) sm.b_dbl[3] = alg2_from_sorted(sm.tmp, kp, kp, sF);
+  block_sum_n<2>(acc, sm);
+  if (threadIdx.x == 0) sm.b_dbl[3] = alg2_from_sorted(sm.tmp, kp, kp, acc[0]);
   __syncthreads();
-  out.gval = 0.5 * sq1 + sm.b_dbl[3];
+  out.gval = 0.5 * acc[1] + sm.b_dbl[3];
   __syncthreads();
   return out;
 }
@@ -509,11 +503,11 @@ __device__ double gstar_node(const double (&a)[E], const uint8_t (&cls)[E], int 
                              double M, ProxSmem& sm) {
   double z1 = 0.0;
   bool freeb[E];
-  uint64_t key[E];
+  double mag[E];
 #pragma unroll
   for (int s = 0; s < E; ++s) {
     freeb[s] = cls[s] == CLS_FREE;
-    key[s] = dbits(fabs(a[s]));
+    mag[s] = fabs(a[s]);
     if (cls[s] == CLS_ONE) z1 += huber(a[s], M);
   }
   double top = 0.0;
@@ -522,7 +516,14 @@ __device__ double gstar_node(const double (&a)[E], const uint8_t (&cls)[E], int 
 #pragma unroll
       for (int s = 0; s < E; ++s)
         if (freeb[s]) top += huber(a[s], M);
+    } else if (kp <= kWaveSel) {
+      block_topk<E>(mag, freeb, kp, sm);
+      if (threadIdx.x == 0)
+        for (int r = 0; r < kp; ++r) top += huber(sm.hu[r], M);
     } else {
+      uint64_t key[E];
+#pragma unroll
+      for (int s = 0; s < E; ++s) key[s] = dbits(mag[s]);
       const Select sel = radix_select_desc<E>(key, freeb, kp, sm);
 #pragma unroll
       for (int s = 0; s < E; ++s) {

@@ -21,7 +21,7 @@ struct NodeDev {
   double P_best;     // best primal value so far
   double D_best;     // best dual value so far
   double L_work;     // last working-precision objective
-  double pad0;
+  double vstar;      // pooled prox value of the last iteration (warm start of the next)
   int iter;          // t (1-based): beta^t is the current iterate
   int restarts;
   int status;        // cgl_node_status; -1 while running

@@ -123,9 +123,12 @@ def prox_gstar(mu, rho, M, k):
 
 
 def prox_g(x, rho, M, k):
-    """prox_{g/rho}(x) by the Moreau identity (Sec. 3.3): x - prox_{rho g*}(rho x) / rho."""
+    """prox_{g/rho}(x) by the Moreau identity (Sec. 3.3): x - prox_{rho g*}(rho x) / rho, evaluated
+    as (mu - prox_{rho g*}(mu)) / rho with mu = rho x, so that entries the prox of g* leaves
+    unchanged (alpha_j = mu_j, e.g. every entry when k = 0) give beta_j = 0 exactly."""
     x = np.asarray(x, dtype=np.float64)
-    return x - prox_gstar(rho * x, rho, M, k) / rho
+    mu = rho * x
+    return (mu - prox_gstar(mu, rho, M, k)) / rho
 
 
 def in_dom_g(beta, k, M, slack=1e-12):

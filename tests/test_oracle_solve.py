@@ -208,3 +208,19 @@ def test_lipschitz_matches_eigenvalue_and_lanczos_path():
     assert oracle.lambda_max_gram(X) == pytest.approx(lam, rel=1e-10)  # Lanczos branch (p > 2000)
     assert oracle.lipschitz(X, "ls") == pytest.approx(2 * lam, rel=1e-10)
     assert oracle.lipschitz(X, "logistic") == pytest.approx(lam / 4, rel=1e-10)
+
+
+def test_budget_exhausted_by_fixed_in_set():
+    """k' = k - |Z1| = 0: g restricted to the free set is the indicator of beta_F = 0, so the node
+    is the box ridge problem on Z1 alone (closed form by bounded least squares)."""
+    d = synth.make_dataset(150, 40, 4, config_id=82)
+    Z1 = [3, 5, 7, 9]
+    r = oracle.solve_node(d.X, d.y, "ls", d.lam2, d.M, 4, (), Z1, tol=1e-10)
+    A = np.vstack([d.X[:, Z1], math.sqrt(d.lam2) * np.eye(4)])
+    rhs = np.concatenate([d.y, np.zeros(4)])
+    res = lsq_linear(A, rhs, bounds=(-d.M, d.M), tol=1e-14, method="bvls")
+    ref = float(np.sum((A @ res.x - rhs) ** 2))
+    assert r.status == oracle.CONVERGED and r.iters < 1000
+    assert r.primal == pytest.approx(ref, rel=1e-9)
+    free = [j for j in range(40) if j not in Z1]
+    assert np.all(r.beta[free] == 0.0)

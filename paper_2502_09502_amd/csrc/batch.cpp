@@ -1,18 +1,380 @@
-// Batched mixed-precision engine (BF16 MFMA correction products around an FP64 base point).
+// Batched mixed-precision engine: node slots sharing one X, BF16 MFMA correction products around
+// FP64 base points, batched FP64 re-centring / certification rounds, and continuous refill of
+// finished slots from a queue (used by cgl_solve_batch, cgl_solve_node with CGL_PREC_MIXED and
+// the server).
+#include "batch.h"
+
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
 #include "engine.h"
+#include "kernels.h"
+#include "mixed.h"
+#include "prox.h"
 
 namespace cgl {
 
-struct MixedWork {};
-
 Problem::~Problem() { delete mixed; }
+
+MixedWork::~MixedWork() {
+  if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+  if (st_host) (void)hipHostFree(st_host);
+}
+
+static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+void MixedWork::ensure(Problem& P) {
+  if (ready) return;
+  hipStream_t s = P.ctx->stream;
+  S = kSlots;
+  S_pad = (int)round_up(S, 256);
+  n_pad = round_up(P.n, 64);
+  ldp = P.ldx;
+  // BF16 design and its transpose
+  Xb.alloc((size_t)n_pad * ldp * 2);
+  Xbt.alloc((size_t)ldp * n_pad * 2);
+  launch_make_bf16(P.xtype, P.X.ptr, P.ldx, P.n, P.p, n_pad, ldp, Xb.as<uint16_t>(),
+                   Xbt.as<uint16_t>(), s);
+  ypad.alloc((size_t)n_pad * 8);
+  CGL_HIP(hipMemsetAsync(ypad.ptr, 0, (size_t)n_pad * 8, s));
+  CGL_HIP(hipMemcpyAsync(ypad.ptr, P.y.ptr, (size_t)P.n * 8, hipMemcpyDeviceToDevice, s));
+  // slots
+  const size_t Sp = (size_t)S * ldp, Sn = (size_t)S * n_pad;
+  st.alloc((size_t)S * sizeof(NodeDev));
+  cls.alloc(Sp);
+  bring.alloc(3 * Sp * 8);
+  beta0.alloc(Sp * 8);
+  H0.alloc(Sp * 8);
+  base0.alloc(Sn * 8);
+  base1.alloc(P.loss == LOSS_LS ? 8 : Sn * 8);
+  bres.alloc(Sp * 8);
+  dop.alloc((size_t)S_pad * ldp * 2);
+  gop.alloc((size_t)S_pad * n_pad * 2);
+  dU.alloc(2 * (size_t)S_pad * n_pad * 4);
+  ksplit = ldp / 64 >= 256 ? 1 : 2;  // enough workgroups for the X^T pass
+  xt_kchunk = round_up((n_pad + ksplit - 1) / ksplit, 32);
+  dH.alloc((size_t)ksplit * S_pad * ldp * 4);
+  nmt = (int)(n_pad / 64);
+  lpart.alloc((size_t)S * nmt * 8);
+  rchunk = 2048;
+  nrt = (int)((n_pad + rchunk - 1) / rchunk);
+  fpart.alloc((size_t)S * nrt * 8);
+  cycle.alloc(sizeof(int));
+  CGL_HIP(hipMemsetAsync(cycle.ptr, 0, sizeof(int), s));
+  CGL_HIP(hipMemsetAsync(dop.ptr, 0, (size_t)S_pad * ldp * 2, s));
+  CGL_HIP(hipMemsetAsync(gop.ptr, 0, (size_t)S_pad * n_pad * 2, s));
+  CGL_HIP(hipMemsetAsync(dU.ptr, 0, 2 * (size_t)S_pad * n_pad * 4, s));
+  CGL_HIP(hipMemsetAsync(dH.ptr, 0, (size_t)ksplit * S_pad * ldp * 4, s));
+  // certification buffers
+  B64.alloc(Sp * 8);
+  U64.alloc(Sn * 8);
+  R64.alloc(Sn * 8);
+  H64.alloc(Sp * 8);
+  CGL_HIP(hipMemsetAsync(H64.ptr, 0, Sp * 8, s));
+  CGL_HIP(hipMemsetAsync(U64.ptr, 0, Sn * 8, s));
+  cchunk = 2048;
+  ncchunk = (int)((n_pad + cchunk - 1) / cchunk);
+  cpart.alloc((size_t)S * ncchunk * 16);
+  list.alloc((size_t)S * sizeof(int));
+  // cold-start base: u_0 = 0, r_0 = grad f(0) (least squares -2y, logistic -y/2),
+  // H_0 = X^T r_0 in FP64
+  {
+    const PlainGeom g = plain_geometry(P.xtype, P.n, P.ldx);
+    DevBuf part;
+    part.alloc((size_t)g.nchunks * P.ldx * 8);
+    H0_cold.alloc((size_t)ldp * 8);
+    launch_xt(P.xtype, P.X.ptr, P.ldx, P.n, P.ldx, g, P.y.as<double>(), 0, nullptr, nullptr, 0,
+              1, part.as<double>(), nullptr, s);
+    launch_grad_step(part.as<double>(), g.nchunks, P.ldx, nullptr, nullptr, 0, 0.0,
+                     H0_cold.as<double>(), nullptr, s);
+    CGL_HIP(hipStreamSynchronize(s));
+    std::vector<double> h((size_t)ldp), yv((size_t)P.n);
+    CGL_HIP(hipMemcpy(h.data(), H0_cold.ptr, (size_t)ldp * 8, hipMemcpyDeviceToHost));
+    CGL_HIP(hipMemcpy(yv.data(), P.y.ptr, (size_t)P.n * 8, hipMemcpyDeviceToHost));
+    const double f = P.loss == LOSS_LS ? -2.0 : -0.5;
+    for (auto& v : h) v *= f;
+    CGL_HIP(hipMemcpy(H0_cold.ptr, h.data(), (size_t)ldp * 8, hipMemcpyHostToDevice));
+    std::vector<double> b0((size_t)n_pad, 0.0), b1((size_t)n_pad, 0.0);
+    for (int64_t i = 0; i < P.n; ++i) {
+      if (P.loss == LOSS_LS) b0[(size_t)i] = -yv[(size_t)i];  // e_0 = 0 - y
+      else b1[(size_t)i] = -0.5 * yv[(size_t)i];              // r_0 = -y sigmoid(0)
+    }
+    base0_cold.alloc((size_t)n_pad * 8);
+    base1_cold.alloc((size_t)n_pad * 8);
+    CGL_HIP(hipMemcpy(base0_cold.ptr, b0.data(), (size_t)n_pad * 8, hipMemcpyHostToDevice));
+    CGL_HIP(hipMemcpy(base1_cold.ptr, b1.data(), (size_t)n_pad * 8, hipMemcpyHostToDevice));
+    double f0 = 0.0;
+    for (int64_t i = 0; i < P.n; ++i)
+      f0 += P.loss == LOSS_LS ? yv[(size_t)i] * yv[(size_t)i] : std::log(2.0);
+    f_cold = f0;
+  }
+  CGL_HIP(hipHostMalloc(&st_host, (size_t)S * sizeof(NodeDev), hipHostMallocDefault));
+  std::memset(st_host, 0, (size_t)S * sizeof(NodeDev));
+  CGL_HIP(hipMemcpyAsync(st.ptr, st_host, (size_t)S * sizeof(NodeDev), hipMemcpyHostToDevice, s));
+  cls_host.assign(Sp, CLS_PAD);
+  slot_owner.assign((size_t)S, -1);
+  // device view
+  md.Xb = Xb.as<uint16_t>();
+  md.Xbt = Xbt.as<uint16_t>();
+  md.n = P.n;
+  md.p = P.p;
+  md.n_pad = n_pad;
+  md.ldp = ldp;
+  md.y = ypad.as<double>();
+  md.loss = P.loss;
+  md.lam2 = P.lam2;
+  md.M = P.M;
+  md.L = P.L;
+  md.rho = P.rho;
+  md.slots = S;
+  md.S_pad = S_pad;
+  md.st = st.as<NodeDev>();
+  md.cls = cls.as<uint8_t>();
+  md.bring = bring.as<double>();
+  md.bring_stride = (int64_t)Sp;
+  md.beta0 = beta0.as<double>();
+  md.H0 = H0.as<double>();
+  md.base0 = base0.as<double>();
+  md.base1 = base1.as<double>();
+  md.bres = bres.as<double>();
+  md.dop = dop.as<uint16_t>();
+  md.gop = gop.as<uint16_t>();
+  md.dU = dU.as<float>();
+  md.dU_ring = (int64_t)S_pad * n_pad;
+  md.dH = dH.as<float>();
+  md.dH_split = (int64_t)S_pad * ldp;
+  md.ksplit = ksplit;
+  md.xt_kchunk = xt_kchunk;
+  md.lpart = lpart.as<double>();
+  md.nmt = nmt;
+  md.fpart = fpart.as<double>();
+  md.nrt = nrt;
+  md.rchunk = rchunk;
+  md.cycle = cycle.as<int>();
+  CGL_HIP(hipStreamSynchronize(s));
+  ready = true;
+}
+
+// One iteration of Alg. 3 for every running slot; ev (optional): events around the two MFMA
+// passes for kernel timing.
+static void mixed_cycle(MixedWork& W, hipStream_t s, hipEvent_t* ev = nullptr) {
+  if (ev) CGL_HIP(hipEventRecord(ev[0], s));
+  launch_gemm_x(W.md, s);
+  if (ev) CGL_HIP(hipEventRecord(ev[1], s));
+  launch_mixed_restart(W.md, s);
+  launch_mixed_resid(W.md, s);
+  if (ev) CGL_HIP(hipEventRecord(ev[2], s));
+  launch_gemm_xt(W.md, s);
+  if (ev) CGL_HIP(hipEventRecord(ev[3], s));
+  launch_mixed_node(W.md, s);
+  launch_cycle_advance(W.md, s);
+}
+
+static bool mixed_graphs() {
+  const char* e = std::getenv("CGL_NO_GRAPH");
+  return !(e && e[0] == '1');
+}
+
+void MixedWork::run_chunk(Problem& P) {
+  hipStream_t s = P.ctx->stream;
+  cgl_ctx* ctx = P.ctx;
+  if (ctx->profiling) {
+    for (int i = 0; i < kChunk; ++i) {
+      hipEvent_t ev[4] = {ctx->event(4 * i), ctx->event(4 * i + 1), ctx->event(4 * i + 2),
+                          ctx->event(4 * i + 3)};
+      mixed_cycle(*this, s, ev);
+    }
+  } else if (mixed_graphs()) {
+    if (!graph_exec) {
+      hipGraph_t graph;
+      CGL_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      for (int i = 0; i < kChunk; ++i) mixed_cycle(*this, s);
+      CGL_HIP(hipStreamEndCapture(s, &graph));
+      CGL_HIP(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
+      CGL_HIP(hipGraphDestroy(graph));
+    }
+    CGL_HIP(hipGraphLaunch(graph_exec, s));
+  } else {
+    for (int i = 0; i < kChunk; ++i) mixed_cycle(*this, s);
+  }
+  CGL_HIP(hipMemcpyAsync(st_host, st.ptr, (size_t)S * sizeof(NodeDev), hipMemcpyDeviceToHost, s));
+  CGL_HIP(hipStreamSynchronize(s));
+  if (ctx->profiling) {
+    for (int i = 0; i < kChunk; ++i) {
+      float a = 0.f, b = 0.f;
+      CGL_HIP(hipEventElapsedTime(&a, ctx->event(4 * i), ctx->event(4 * i + 1)));
+      CGL_HIP(hipEventElapsedTime(&b, ctx->event(4 * i + 2), ctx->event(4 * i + 3)));
+      ctx->kt_ms[3] += a;  // X pass
+      ctx->kt_ms[2] += b;  // X^T pass
+      ctx->kt_n[3] += 1;
+      ctx->kt_n[2] += 1;
+    }
+  }
+  cycles += kChunk;
+}
+
+bool MixedWork::cert_round(Problem& P) {
+  std::vector<int> want;
+  for (int sl = 0; sl < S; ++sl) {
+    const NodeDev& d = st_host[sl];
+    if (slot_owner[(size_t)sl] >= 0 && d.active && !d.done && d.want_cert) want.push_back(sl);
+  }
+  if (want.empty()) return false;
+  hipStream_t s = P.ctx->stream;
+  cgl_ctx* ctx = P.ctx;
+  const int nq = (int)want.size();
+  for (int sl : want) st_host[sl].L_work = st_host[sl].L_work;  // keep the working value
+  CGL_HIP(hipMemcpyAsync(list.ptr, want.data(), (size_t)nq * sizeof(int), hipMemcpyHostToDevice, s));
+  hipEvent_t e0 = ctx->profiling ? ctx->event(100) : nullptr;
+  hipEvent_t e1 = ctx->profiling ? ctx->event(101) : nullptr;
+  launch_cert_gather(md, list.as<int>(), nq, B64.as<double>(), s);
+  if (e0) CGL_HIP(hipEventRecord(e0, s));
+  launch_gemm_f64(P.xtype, P.X.ptr, P.ldx, P.n, P.p, 0, B64.as<double>(), ldp, nq,
+                  U64.as<double>(), n_pad, s);
+  if (e1) CGL_HIP(hipEventRecord(e1, s));
+  launch_cert_resid(md, list.as<int>(), nq, U64.as<double>(), R64.as<double>(),
+                    cpart.as<double>(), ncchunk, cchunk, s);
+  launch_gemm_f64(P.xtype, P.X.ptr, P.ldx, P.p, P.n, 1, R64.as<double>(), n_pad, nq,
+                  H64.as<double>(), ldp, s);
+  launch_cert_finish(md, list.as<int>(), nq, B64.as<double>(), H64.as<double>(),
+                     cpart.as<double>(), ncchunk, s);
+  CGL_HIP(hipMemcpyAsync(st_host, st.ptr, (size_t)S * sizeof(NodeDev), hipMemcpyDeviceToHost, s));
+  CGL_HIP(hipStreamSynchronize(s));
+  if (e0) {
+    float a = 0.f;
+    CGL_HIP(hipEventElapsedTime(&a, e0, e1));
+    ctx->kt_ms[4] += a;
+    ctx->kt_n[4] += 1;
+  }
+  cert_rounds += 1;
+  return true;
+}
+
+int MixedWork::free_slots() const {
+  int c = 0;
+  for (int o : slot_owner) c += o < 0 ? 1 : 0;
+  return c;
+}
+
+void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
+  if (adm.empty()) return;
+  hipStream_t s = P.ctx->stream;
+  std::vector<int> slots;
+  for (const Admission& a : adm) {
+    const int sl = a.slot;
+    slots.push_back(sl);
+    slot_owner[(size_t)sl] = a.owner;
+    NodeDev d = make_node_dev(a.node, a.host);
+    d.active = 1;
+    d.primed = 0;
+    d.P_best = HUGE_VAL;
+    d.D_best = -HUGE_VAL;
+    d.P_cert = HUGE_VAL;
+    d.D_cert = -HUGE_VAL;
+    d.mgap_ref = HUGE_VAL;
+    d.L_prev = HUGE_VAL;
+    d.g_new = 0.0;  // g(0)
+    if (d.iter >= d.max_iter) d.want_cert = 1;  // no iteration allowed: certify the start
+    st_host[sl] = d;
+    std::copy(a.host.cls.begin(), a.host.cls.end(), cls_host.begin() + (int64_t)sl * ldp);
+    std::fill(cls_host.begin() + (int64_t)sl * ldp + P.p, cls_host.begin() + (int64_t)(sl + 1) * ldp,
+              (uint8_t)CLS_PAD);
+    admitted_at[sl] = cycles;
+  }
+  CGL_HIP(hipMemcpyAsync(list.ptr, slots.data(), slots.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  launch_admit(md, list.as<int>(), (int)slots.size(), H0_cold.as<double>(),
+               base0_cold.as<double>(), base1_cold.as<double>(), s);
+  CGL_HIP(hipMemcpyAsync(cls.ptr, cls_host.data(), cls_host.size(), hipMemcpyHostToDevice, s));
+  CGL_HIP(hipMemcpyAsync(st.ptr, st_host, (size_t)S * sizeof(NodeDev), hipMemcpyHostToDevice, s));
+  CGL_HIP(hipStreamSynchronize(s));
+}
+
+void MixedWork::retire(Problem& P, int sl, cgl_result* res, double* beta_out) {
+  hipStream_t s = P.ctx->stream;
+  const NodeDev& d = st_host[sl];
+  res->primal = d.P_cert;
+  res->lower_bound = d.D_cert;
+  res->gap_abs = d.P_cert - d.D_cert;
+  res->gap_rel = res->gap_abs / std::max(std::fabs(d.P_cert), 1.0);
+  res->iters = d.iter - 1;
+  res->restarts = d.restarts;
+  res->status = d.status == kRunning ? CGL_NOT_CONVERGED : d.status;
+  res->recentres = d.recentres;
+  res->err_vs_fp64_est = std::isfinite(d.P_cert)
+                             ? std::fabs(d.L_work - d.P_cert) / std::max(std::fabs(d.P_cert), 1.0)
+                             : 0.0;
+  if (beta_out)
+    CGL_HIP(hipMemcpyAsync(beta_out, bres.as<double>() + (int64_t)sl * ldp, (size_t)P.p * 8,
+                           hipMemcpyDeviceToHost, s));
+  st_host[sl].active = 0;
+  slot_owner[(size_t)sl] = -1;
+}
+
+// Upload the host image of the slot states (after retire/admit edits; the device is idle).
+void MixedWork::push_states(Problem& P) {
+  CGL_HIP(hipMemcpyAsync(st.ptr, st_host, (size_t)S * sizeof(NodeDev), hipMemcpyHostToDevice,
+                         P.ctx->stream));
+}
 
 void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_out,
                  cgl_result* res) {
-  (void)P; (void)nodes; (void)count; (void)beta_out; (void)res;
-  invalid("mixed precision is not available in this build");
+  if (!P.mixed) P.mixed = new MixedWork();
+  MixedWork& W = *P.mixed;
+  W.ensure(P);
+  hipStream_t s = P.ctx->stream;
+  std::vector<NodeHost> hosts;
+  hosts.reserve((size_t)count);
+  for (int32_t i = 0; i < count; ++i) {
+    if (nodes[i].warm_start)
+      invalid("warm starts are not supported with CGL_PREC_MIXED; use CGL_PREC_F64");
+    hosts.push_back(make_node_host(nodes[i], P.p, P.k));
+  }
+  int32_t next = 0, finished = 0;
+  // infeasible nodes never take a slot
+  std::vector<char> handled((size_t)count, 0);
+  for (int32_t i = 0; i < count; ++i) {
+    if (hosts[(size_t)i].infeasible) {
+      infeasible_result(&res[i], beta_out ? beta_out + (int64_t)i * P.p : nullptr, P.p);
+      handled[(size_t)i] = 1;
+      ++finished;
+    }
+  }
+  auto fill = [&]() {
+    std::vector<Admission> adm;
+    for (int sl = 0; sl < W.S && next < count; ++sl) {
+      if (W.slot_owner[(size_t)sl] >= 0) continue;
+      while (next < count && handled[(size_t)next]) ++next;
+      if (next >= count) break;
+      adm.push_back(Admission{sl, next, nodes[next], hosts[(size_t)next]});
+      ++next;
+    }
+    W.admit(P, adm);
+  };
+  fill();
+  while (finished < count) {
+    W.run_chunk(P);
+    W.cert_round(P);
+    bool changed = false;
+    for (int sl = 0; sl < W.S; ++sl) {
+      const int owner = W.slot_owner[(size_t)sl];
+      if (owner < 0 || !W.st_host[sl].done) continue;
+      W.retire(P, sl, &res[owner], beta_out ? beta_out + (int64_t)owner * P.p : nullptr);
+      ++finished;
+      changed = true;
+    }
+    if (changed) {
+      W.push_states(P);
+      fill();
+    }
+    // a run with nothing active and work pending would spin: guard
+    if (finished < count && W.free_slots() == W.S && next >= count) break;
+  }
+  CGL_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace cgl

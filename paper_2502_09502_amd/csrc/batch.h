@@ -1,0 +1,54 @@
+// Host side of the batched mixed-precision engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "engine.h"
+#include "mixed.h"
+
+namespace cgl {
+
+constexpr int kSlots = 256;  // node slots per problem
+constexpr int kChunk = 4;    // iterations per graph launch between host checks
+
+struct Admission {
+  int slot;
+  int owner;  // caller's index (solve) or request id (server)
+  cgl_node node;
+  NodeHost host;
+};
+
+struct MixedWork {
+  bool ready = false;
+  int S = 0, S_pad = 0;
+  int64_t n_pad = 0, ldp = 0;
+  int ksplit = 1;
+  int64_t xt_kchunk = 0;
+  int nmt = 0, nrt = 0, ncchunk = 0;
+  int64_t rchunk = 0, cchunk = 0;
+  double f_cold = 0.0;
+  DevBuf Xb, Xbt, ypad, st, cls, bring, beta0, H0, base0, base1, bres, dop, gop, dU, dH, lpart,
+      fpart, cycle, B64, U64, R64, H64, cpart, list, H0_cold, base0_cold, base1_cold;
+  NodeDev* st_host = nullptr;
+  std::vector<uint8_t> cls_host;
+  std::vector<int> slot_owner;
+  int64_t admitted_at[kSlots] = {0};
+  int64_t cycles = 0;
+  int64_t cert_rounds = 0;
+  hipGraphExec_t graph_exec = nullptr;
+  MixedDev md{};
+
+  void ensure(Problem& P);
+  void run_chunk(Problem& P);
+  bool cert_round(Problem& P);
+  void admit(Problem& P, const std::vector<Admission>& adm);
+  void retire(Problem& P, int slot, cgl_result* res, double* beta_out);
+  void push_states(Problem& P);
+  int free_slots() const;
+  ~MixedWork();
+};
+
+}  // namespace cgl

@@ -1,0 +1,772 @@
+// Batched mixed-precision engine kernels.
+//
+// S node slots share one design X. Each slot iterates Alg. 3 around an FP64 base point beta_0
+// with FP64 quantities u_0 = X beta_0, r_0 = grad f(u_0), H_0 = X^T r_0. The two products of an
+// iteration are corrections to that base, computed for all slots at once on MFMA with BF16
+// operands and FP32 accumulation:
+//
+//   dU = X~ bf16(beta^{t+1} - beta_0)           (X pass; S x n)
+//   dH = X~^T bf16(grad f(u_gamma) - r_0)       (X^T pass; S x p), u_gamma = u_0 + dU_gamma
+//
+// so grad F(gamma) = H_0 + dH and f(X beta^{t+1}) = f(u_0 + dU). X~ is the BF16 copy of X (equal
+// to X when X is stored in BF16). Errors of the BF16 operands are relative to the size of the
+// correction, which shrinks as the iterate approaches the base; the base is re-centred in FP64
+// (and the bound certified, Sec. 3.4) when the working-precision gap stops improving.
+//
+// One iteration (cycle) for every active slot: k_gemm_x (loss epilogue) -> k_mixed_restart ->
+// k_mixed_resid -> k_gemm_xt -> k_mixed_node (prox) -> k_cycle_advance.
+#include <limits.h>
+
+#include "common.h"
+#include "kernels.h"
+#include "mixed.h"
+#include "prox.h"
+#include "solver.h"
+
+namespace cgl {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double doublex4;
+
+__device__ __forceinline__ double softplus_d(double t) {
+  return t > 0.0 ? t + log1p(exp(-t)) : log1p(exp(t));
+}
+__device__ __forceinline__ double sigmoid_d(double t) {
+  if (t >= 0.0) return 1.0 / (1.0 + exp(-t));
+  const double e = exp(t);
+  return e / (1.0 + e);
+}
+
+// A slot advances while it holds a node that is not finished and has iterations left (a slot at
+// its cap waits for the certification that ends it).
+__device__ __forceinline__ bool slot_running(const NodeDev* st) {
+  return st->active != 0 && st->done == 0 && st->iter < st->max_iter;
+}
+
+// =====================================================================================
+// BF16 MFMA GEMM: C[node][m] = sum_k A[m][k] * B[node][k]
+//   A: M x K bf16 row-major (lda), B: nodes x K bf16 row-major (ldb); M multiple of GT_M, K
+//   multiple of GT_K, node rows padded to a multiple of GT_N with zero rows.
+// Workgroup tile: 64 rows of A x 256 nodes; 4 waves, wave w covers nodes [64w, 64w + 64) with
+// 2 x 2 tiles of v_mfma_f32_32x32x16_bf16. Double-buffered LDS, one barrier per k-step.
+// =====================================================================================
+
+constexpr int GT_M = 64;
+constexpr int GT_N = 256;
+constexpr int GT_K = 32;
+constexpr int GT_LD = GT_K + 8;  // LDS row pitch in bf16 (80 bytes)
+
+enum { EPI_STORE = 0, EPI_LOSS = 1 };
+
+struct GemmArgs {
+  const uint16_t* A;
+  int64_t lda;
+  const uint16_t* B;
+  int64_t ldb;
+  int64_t M, K;
+  int64_t kchunk;  // split-K chunk (multiple of GT_K)
+  float* C;
+  int64_t ldc;
+  int64_t c_split_stride;
+  int ring2;       // EPI_LOSS: C is a 2-slot ring selected by the cycle counter
+  int64_t c_ring_stride;
+};
+
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, MixedDev md) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][GT_M * GT_LD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][GT_N * GT_LD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const int64_t m0 = (int64_t)blockIdx.x * GT_M;
+  const int64_t n0 = (int64_t)blockIdx.y * GT_N;
+  const int64_t k0 = (int64_t)blockIdx.z * g.kchunk;
+  const int64_t k1 = min(g.K, k0 + g.kchunk);
+
+  const int lrow = tid >> 2;       // 0..63
+  const int lk = (tid & 3) * 8;    // 0, 8, 16, 24
+  const uint16_t* ag = g.A + (m0 + lrow) * g.lda + lk;
+  const uint16_t* bg = g.B + (n0 + lrow) * g.ldb + lk;
+  uint4 ra, rb[4];
+  auto gload = [&](int64_t kk) {
+    ra = *reinterpret_cast<const uint4*>(ag + kk);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rb[q] = *reinterpret_cast<const uint4*>(bg + (int64_t)q * 64 * g.ldb + kk);
+  };
+  auto lstore = [&](int buf) {
+    *reinterpret_cast<uint4*>(&As[buf][lrow * GT_LD + lk]) = ra;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      *reinterpret_cast<uint4*>(&Bs[buf][(lrow + 64 * q) * GT_LD + lk]) = rb[q];
+  };
+
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.f;
+
+  if (k0 < k1) {
+    gload(k0);
+    lstore(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  const int fr = lane & 31;
+  const int fk = (lane >> 5) * 8;
+  for (int64_t kk = k0; kk < k1; kk += GT_K) {
+    const bool more = kk + GT_K < k1;
+    if (more) gload(kk + GT_K);
+#pragma unroll
+    for (int ks = 0; ks < GT_K / 16; ++ks) {
+      bf16x8 af[2], bfr[2];
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+        af[r] = *reinterpret_cast<const bf16x8*>(&As[buf][(r * 32 + fr) * GT_LD + ks * 16 + fk]);
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        bfr[c] = *reinterpret_cast<const bf16x8*>(
+            &Bs[buf][(wid * 64 + c * 32 + fr) * GT_LD + ks * 16 + fk]);
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[r], bfr[c], acc[r][c], 0, 0, 0);
+    }
+    if (more) lstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  // ---- epilogue. Element e of lane l in tile (r, c): row i = (e%4) + 4 (l/32) + 8 (e/4),
+  // node j = l % 32.
+  const int hi = lane >> 5;
+  float* Cbase = g.C + (int64_t)blockIdx.z * g.c_split_stride;
+  if (EPI == EPI_LOSS && g.ring2) {
+    const int cyc = *md.cycle;
+    Cbase += (int64_t)(cyc & 1) * g.c_ring_stride;
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int64_t node = n0 + wid * 64 + c * 32 + (lane & 31);
+    double lsum = 0.0;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t m = m0 + r * 32 + 4 * hi + 8 * q;
+        float4 v;
+        v.x = acc[r][c][4 * q + 0];
+        v.y = acc[r][c][4 * q + 1];
+        v.z = acc[r][c][4 * q + 2];
+        v.w = acc[r][c][4 * q + 3];
+        *reinterpret_cast<float4*>(Cbase + node * g.ldc + m) = v;
+        if (EPI == EPI_LOSS && node < md.slots) {
+          const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int64_t mm = m + t;
+            if (mm < md.n) {
+              const double b0 = md.base0[node * md.n_pad + mm];
+              const double u = b0 + (double)vv[t];
+              if (md.loss == LOSS_LS) lsum += u * u;  // base0 holds e_0 = u_0 - y
+              else lsum += softplus_d(-md.y[mm] * u);  // base0 holds u_0
+            }
+          }
+        }
+      }
+    }
+    if (EPI == EPI_LOSS) {
+      lsum += __shfl_xor(lsum, 32, kWave);
+      if (hi == 0 && node < md.slots) md.lpart[node * md.nmt + blockIdx.x] = lsum;
+    }
+  }
+}
+
+// =====================================================================================
+// Per-slot restart test (Alg. 3): L^{t+1} = f(X beta^{t+1}) + 2 lambda2 g(beta^{t+1}).
+// =====================================================================================
+__global__ __launch_bounds__(64) void k_mixed_restart(MixedDev md) {
+  NodeDev* st = md.st + blockIdx.x;
+  if (!slot_running(st)) return;
+  double a = 0.0;
+  for (int i = threadIdx.x; i < md.nmt; i += 64) a += md.lpart[(int64_t)blockIdx.x * md.nmt + i];
+  a = wave_sum(a);
+  if (threadIdx.x == 0) {
+    const double Lnew = a + 2.0 * md.lam2 * st->g_new;
+    st->L_work = Lnew;
+    if (!st->primed) {
+      st->primed = 1;
+    } else if (Lnew >= st->L_prev) {
+      st->phi = 1.0;
+      st->restarts += 1;
+    } else {
+      st->phi += 1.0;
+    }
+    st->L_prev = Lnew;
+    if (Lnew < st->P_best) st->P_best = Lnew;  // working-precision best (monitor only)
+    st->c = st->phi / (st->phi + 3.0);
+  }
+}
+
+// =====================================================================================
+// Residual operand: u_gamma = u_0 + dU^{t+1} + c (dU^{t+1} - dU^t); r = grad f(u_gamma);
+// G = bf16(r - r_0); F*(-zeta) partial sums with zeta = -r (dual monitor at gamma).
+// grid: (chunks, slots); 256 threads.
+// =====================================================================================
+__global__ __launch_bounds__(256) void k_mixed_resid(MixedDev md) {
+  __shared__ double red[4];
+  const int slot = blockIdx.y;
+  const NodeDev* st = md.st + slot;
+  if (!slot_running(st)) return;
+  const int cyc = *md.cycle;
+  const float* dun = md.dU + (int64_t)(cyc & 1) * md.dU_ring + (int64_t)slot * md.n_pad;
+  const float* duo = md.dU + (int64_t)((cyc + 1) & 1) * md.dU_ring + (int64_t)slot * md.n_pad;
+  const double c = st->c;
+  const int64_t i0 = (int64_t)blockIdx.x * md.rchunk;
+  const int64_t i1 = min(md.n_pad, i0 + md.rchunk);
+  double fs = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+    uint16_t gv = 0;
+    if (i < md.n) {
+      const double dg = (double)dun[i] + c * ((double)dun[i] - (double)duo[i]);
+      const double y = md.y[i];
+      if (md.loss == LOSS_LS) {
+        const double e = md.base0[(int64_t)slot * md.n_pad + i] + dg;  // u_gamma - y
+        const double r = 2.0 * e;
+        fs += 0.25 * r * r + y * r;  // F*(-zeta), zeta = -r: ||zeta||^2/4 - y.zeta
+        gv = float_to_bf16((float)(2.0 * dg));
+      } else {
+        const double u = md.base0[(int64_t)slot * md.n_pad + i] + dg;
+        const double t = -y * u;
+        const double q = sigmoid_d(t);
+        const double r = -y * q;
+        fs += -q * softplus_d(-t) - (1.0 - q) * softplus_d(t);
+        gv = float_to_bf16((float)(r - md.base1[(int64_t)slot * md.n_pad + i]));
+      }
+    }
+    md.gop[(int64_t)slot * md.n_pad + i] = gv;
+  }
+  fs = block_reduce(fs, red, OpAdd(), 0.0);
+  if (threadIdx.x == 0) md.fpart[(int64_t)slot * md.nrt + blockIdx.x] = fs;
+}
+
+// =====================================================================================
+// Per-slot gradient step, prox, operand update and dual monitor. One 1024-thread workgroup
+// per slot.
+// =====================================================================================
+template <int E>
+__global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
+  __shared__ ProxSmem sm;
+  const int slot = blockIdx.x;
+  NodeDev* st = md.st + slot;
+  if (!slot_running(st)) return;
+  const int cyc = *md.cycle;
+  const int64_t p = md.p;
+  const double* bt1 = md.bring + (int64_t)(cyc % 3) * md.bring_stride + (int64_t)slot * md.ldp;
+  const double* bt0 =
+      md.bring + (int64_t)((cyc + 2) % 3) * md.bring_stride + (int64_t)slot * md.ldp;
+  double* bout = md.bring + (int64_t)((cyc + 1) % 3) * md.bring_stride + (int64_t)slot * md.ldp;
+  const double* H0 = md.H0 + (int64_t)slot * md.ldp;
+  const double* b0 = md.beta0 + (int64_t)slot * md.ldp;
+  const uint8_t* cl = md.cls + (int64_t)slot * md.ldp;
+  const double c = st->c;
+  const double invL = 1.0 / md.L;
+  double wr[E], hg[E], b1[E];
+  uint8_t cr[E];
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
+    if (j < p) {
+      double h = H0[j];
+      for (int q = 0; q < md.ksplit; ++q)
+        h += (double)md.dH[(int64_t)q * md.dH_split + (int64_t)slot * md.ldp + j];
+      const double x1 = bt1[j];
+      const double gam = x1 + c * (x1 - bt0[j]);
+      hg[s] = h;
+      b1[s] = x1;
+      wr[s] = gam - h * invL;
+      cr[s] = cl[j];
+    } else {
+      hg[s] = 0.0; b1[s] = 0.0; wr[s] = 0.0; cr[s] = CLS_PAD;
+    }
+  }
+  double br[E];
+  const ProxOut po = node_prox<E>(wr, cr, st->kp, st->nfree, md.rho, md.M, st->vstar, br, sm);
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
+    if (j < p) {
+      bout[j] = br[s];
+      md.dop[(int64_t)slot * md.ldp + j] = float_to_bf16((float)(br[s] - b0[j]));
+    }
+  }
+  // dual monitor at gamma: D = -F*(-zeta) - 2 lambda2 g_node*(-grad F(gamma) / (2 lambda2))
+  const int iter = st->iter;
+  const bool check = (iter % st->check_every) == 0;
+  double gs = 0.0;
+  if (check) {
+    double a[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) a[s] = -hg[s] / (2.0 * md.lam2);
+    gs = gstar_node<E>(a, cr, st->kp, st->nfree, md.M, sm);
+  }
+  double fs = 0.0;
+  if (check) {
+    for (int i = threadIdx.x; i < md.nrt; i += blockDim.x)
+      fs += md.fpart[(int64_t)slot * md.nrt + i];
+    fs = bsum(fs, sm);
+  }
+  if (threadIdx.x == 0) {
+    st->g_new = po.gval;
+    st->vstar = po.vstar;
+    if (check) {
+      const double D = -fs - 2.0 * md.lam2 * gs;
+      if (D > st->D_best) st->D_best = D;  // working-precision monitor
+    }
+    const double Pw = st->P_best, Dw = st->D_best;
+    const double mgap = (Pw - Dw) / fmax(fabs(Pw), 1.0);
+    if (!(Pw == Pw) || !(po.gval == po.gval)) {
+      st->status = 3;  // NUMERIC
+      st->done = 1;
+    }
+    if (mgap < 0.5 * st->mgap_ref) {
+      st->mgap_ref = mgap;
+      st->since_improve = 0;
+    } else {
+      st->since_improve += 1;
+    }
+    st->since_recentre += 1;
+    if (mgap <= 0.5 * st->tol ||
+        (st->since_improve >= kStallCycles && st->since_recentre >= kStallCycles) ||
+        iter + 1 >= st->max_iter) {
+      st->want_cert = 1;
+    }
+    st->iter = iter + 1;
+    st->last_ring = (cyc + 1) % 3;
+  }
+}
+
+__global__ void k_cycle_advance(int* cycle) {
+  if (threadIdx.x == 0) *cycle += 1;
+}
+
+// =====================================================================================
+// FP64 batched products for re-centring and certification:
+//   C[q][m] = sum_k A(m, k) B[q][k],  A(m, k) = X[m][k] (TRANS = 0) or X[k][m] (TRANS = 1),
+// X in its stored precision (converted exactly to FP64), B FP64 node-major. v_mfma_f64_16x16x4.
+// Workgroup tile 64 (m) x 64 (q), k-step 16; wave w: rows 32 (w % 2) .. +32, nodes 32 (w / 2)
+// .. +32 as 2 x 2 MFMA tiles.
+// =====================================================================================
+
+constexpr int FT_M = 64, FT_Q = 64, FT_K = 16;
+
+template <typename XT, int TRANS>
+__global__ __launch_bounds__(256) void k_gemm_f64(const XT* __restrict__ X, int64_t ldx,
+                                                  int64_t M, int64_t K,
+                                                  const double* __restrict__ B, int64_t ldb,
+                                                  int Q, double* __restrict__ C, int64_t ldc) {
+  __shared__ double As[FT_K][FT_M + 1];
+  __shared__ double Bs[FT_K][FT_Q + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const int64_t m0 = (int64_t)blockIdx.x * FT_M;
+  const int q0 = blockIdx.y * FT_Q;
+  doublex4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[a][b][e] = 0.0;
+  const int wm = (wid & 1) * 32, wq = (wid >> 1) * 32;
+  for (int64_t k0 = 0; k0 < K; k0 += FT_K) {
+    // A tile (64 x 16): 1024 values, 4 per thread
+    if (TRANS == 0) {
+      const int r = tid >> 2, kk = (tid & 3) * 4;
+      const int64_t m = m0 + r;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t k = k0 + kk + t;
+        As[kk + t][r] = (m < M && k < K) ? XLoad<XT>::get(X, (size_t)(m * ldx + k)) : 0.0;
+      }
+    } else {
+      const int kk = tid >> 4, mm = (tid & 15) * 4;
+      const int64_t k = k0 + kk;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t m = m0 + mm + t;
+        As[kk][mm + t] = (m < M && k < K) ? XLoad<XT>::get(X, (size_t)(k * ldx + m)) : 0.0;
+      }
+    }
+    {  // B tile (64 nodes x 16): 4 per thread
+      const int q = tid >> 2, kk = (tid & 3) * 4;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t k = k0 + kk + t;
+        Bs[kk + t][q] = (q0 + q < Q && k < K) ? B[(int64_t)(q0 + q) * ldb + k] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < FT_K / 4; ++ks) {
+      double af[2], bf[2];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) af[r] = As[ks * 4 + (lane >> 4)][wm + r * 16 + (lane & 15)];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) bf[c] = Bs[ks * 4 + (lane >> 4)][wq + c * 16 + (lane & 15)];
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[r], bf[c], acc[r][c], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // C[i][j]: lane j + 16 (i % 4), element i / 4
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = (lane >> 4) + 4 * e;
+        const int j = lane & 15;
+        const int64_t m = m0 + wm + r * 16 + i;
+        const int q = q0 + wq + c * 16 + j;
+        if (m < M && q < Q) C[(int64_t)q * ldc + m] = acc[r][c][e];
+      }
+}
+
+// =====================================================================================
+// Certification / re-centring helpers
+// =====================================================================================
+
+// B64[q][j] = latest iterate of slot list[q] (ring slot cycle % 3).
+__global__ __launch_bounds__(256) void k_cert_gather(MixedDev md, const int* list, int nq,
+                                                     double* B64) {
+  const int q = blockIdx.y;
+  if (q >= nq) return;
+  const int slot = list[q];
+  const int ring = md.st[slot].last_ring;
+  const double* src = md.bring + (int64_t)ring * md.bring_stride + (int64_t)slot * md.ldp;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < md.ldp; j += (int64_t)gridDim.x * 256)
+    B64[(int64_t)q * md.ldp + j] = src[j];
+}
+
+// From U64 = X beta (FP64): the loss f, F*(-zeta) with zeta = -grad f(u) (partials per chunk),
+// R64 = grad f(u), and the slot's new base (e_0 = u - y or u_0 and r_0).
+__global__ __launch_bounds__(256) void k_cert_resid(MixedDev md, const int* list, int nq,
+                                                    const double* U64, double* R64,
+                                                    double* part, int nchunk, int64_t chunk) {
+  __shared__ double red[8];
+  const int q = blockIdx.y;
+  if (q >= nq) return;
+  const int slot = list[q];
+  const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(md.n_pad, i0 + chunk);
+  double ls = 0.0, fs = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+    double r = 0.0, b0 = 0.0, b1 = 0.0;
+    if (i < md.n) {
+      const double u = U64[(int64_t)q * md.n_pad + i];
+      const double y = md.y[i];
+      if (md.loss == LOSS_LS) {
+        const double e = u - y;
+        r = 2.0 * e;
+        ls += e * e;
+        fs += 0.25 * r * r + y * r;
+        b0 = e;
+      } else {
+        const double t = -y * u;
+        const double qq = sigmoid_d(t);
+        r = -y * qq;
+        ls += softplus_d(t);
+        fs += -qq * softplus_d(-t) - (1.0 - qq) * softplus_d(t);
+        b0 = u;
+        b1 = r;
+      }
+    }
+    R64[(int64_t)q * md.n_pad + i] = r;
+    md.base0[(int64_t)slot * md.n_pad + i] = b0;
+    if (md.loss != LOSS_LS) md.base1[(int64_t)slot * md.n_pad + i] = b1;
+  }
+  ls = block_reduce(ls, red, OpAdd(), 0.0);
+  fs = block_reduce(fs, red + 4, OpAdd(), 0.0);
+  if (threadIdx.x == 0) {
+    part[((int64_t)q * nchunk + blockIdx.x) * 2] = ls;
+    part[((int64_t)q * nchunk + blockIdx.x) * 2 + 1] = fs;
+  }
+}
+
+// Per certified slot: P = f + 2 lambda2 g, D = -F* - 2 lambda2 g*(X^T zeta / (2 lambda2)) with
+// X^T zeta = -H64 (FP64 weak-duality bound, Sec. 3.4). Keeps the best certified P (and its
+// beta) and D; finishes the slot or re-centres it on the certified iterate.
+template <int E>
+__global__ __launch_bounds__(1024) void k_cert_finish(MixedDev md, const int* list, int nq,
+                                                      const double* B64, const double* H64,
+                                                      const double* part, int nchunk) {
+  __shared__ ProxSmem sm;
+  const int q = blockIdx.x;
+  if (q >= nq) return;
+  const int slot = list[q];
+  NodeDev* st = md.st + slot;
+  const int64_t p = md.p;
+  const uint8_t* cl = md.cls + (int64_t)slot * md.ldp;
+  double a[E];
+  uint8_t cr[E];
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
+    if (j < p) {
+      a[s] = -H64[(int64_t)q * md.ldp + j] / (2.0 * md.lam2);
+      cr[s] = cl[j];
+    } else {
+      a[s] = 0.0;
+      cr[s] = CLS_PAD;
+    }
+  }
+  const double gs = gstar_node<E>(a, cr, st->kp, st->nfree, md.M, sm);
+  double acc[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < nchunk; i += blockDim.x) {
+    acc[0] += part[((int64_t)q * nchunk + i) * 2];
+    acc[1] += part[((int64_t)q * nchunk + i) * 2 + 1];
+  }
+  block_sum_n<2>(acc, sm);
+  if (threadIdx.x == 0) {
+    const double P = acc[0] + 2.0 * md.lam2 * st->g_new;  // g of the gathered iterate
+    const double D = -acc[1] - 2.0 * md.lam2 * gs;
+    int improve = 0;
+    if (P < st->P_cert) { st->P_cert = P; improve = 1; }
+    if (D > st->D_cert) st->D_cert = D;
+    st->b_int0 = improve;
+    const double gap = (st->P_cert - st->D_cert) / fmax(fabs(st->P_cert), 1.0);
+    int status = kRunning;
+    if (!(P == P) || !(D == D)) status = 3;
+    else if (gap <= st->tol) status = 0;
+    else if (isfinite(st->incumbent) && st->D_cert > st->incumbent) status = 5;
+    else if (st->iter >= st->max_iter) status = 1;
+    else if (isfinite(st->incumbent) && st->P_cert < st->incumbent) status = 6;
+    if (status != kRunning) {
+      st->status = status;
+      st->done = 1;
+    } else {
+      // re-centre on this iterate: restart the momentum (Alg. 3 with phi = 1)
+      st->recentres += 1;
+      st->primed = 0;
+      st->phi = 1.0;
+      st->c = 0.25;
+      st->L_prev = HUGE_VAL;
+      st->P_best = P;
+      st->D_best = D;
+      st->mgap_ref = HUGE_VAL;
+      st->since_improve = 0;
+      st->since_recentre = 0;
+    }
+    st->want_cert = 0;
+  }
+  __syncthreads();
+  const bool improve = st->b_int0 != 0;
+  const bool done = st->done != 0;
+  const int cyc = *md.cycle;
+  for (int64_t j = threadIdx.x; j < md.ldp; j += blockDim.x) {
+    const double bj = B64[(int64_t)q * md.ldp + j];
+    if (improve) md.bres[(int64_t)slot * md.ldp + j] = bj;
+    if (!done) {
+      md.beta0[(int64_t)slot * md.ldp + j] = bj;
+      md.H0[(int64_t)slot * md.ldp + j] = H64[(int64_t)q * md.ldp + j];
+      for (int r = 0; r < 3; ++r) md.bring[(int64_t)r * md.bring_stride + (int64_t)slot * md.ldp + j] = bj;
+    }
+    md.dop[(int64_t)slot * md.ldp + j] = 0;
+  }
+  if (!done) {
+    for (int64_t i = threadIdx.x; i < md.n_pad; i += blockDim.x) {
+      md.dU[(int64_t)slot * md.n_pad + i] = 0.f;
+      md.dU[md.dU_ring + (int64_t)slot * md.n_pad + i] = 0.f;
+    }
+  }
+  (void)cyc;
+}
+
+// Admission from the cold start beta = 0 (the base quantities are the same for every node:
+// u_0 = 0, r_0 = grad f(0), H_0 = X^T r_0).
+__global__ __launch_bounds__(256) void k_admit(MixedDev md, const int* list, int nq,
+                                               const double* H0_cold, const double* base0_cold,
+                                               const double* base1_cold) {
+  const int q = blockIdx.y;
+  if (q >= nq) return;
+  const int slot = list[q];
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < md.ldp; j += stride) {
+    const int64_t o = (int64_t)slot * md.ldp + j;
+    for (int r = 0; r < 3; ++r) md.bring[(int64_t)r * md.bring_stride + o] = 0.0;
+    md.beta0[o] = 0.0;
+    md.bres[o] = 0.0;
+    md.H0[o] = H0_cold[j];
+    md.dop[o] = 0;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < md.n_pad; i += stride) {
+    const int64_t o = (int64_t)slot * md.n_pad + i;
+    md.base0[o] = base0_cold[i];
+    if (md.loss != LOSS_LS) md.base1[o] = base1_cold[i];
+    md.dU[o] = 0.f;
+    md.dU[md.dU_ring + o] = 0.f;
+    md.gop[o] = 0;
+  }
+}
+
+void launch_admit(const MixedDev& md, const int* list, int nq, const double* H0_cold,
+                  const double* base0_cold, const double* base1_cold, hipStream_t s) {
+  hipLaunchKernelGGL(k_admit, dim3(16, (unsigned)nq), dim3(256), 0, s, md, list, nq, H0_cold,
+                     base0_cold, base1_cold);
+}
+
+// Zero a slot's operand rows (retired or empty slots must not contribute to the products).
+__global__ __launch_bounds__(256) void k_slot_clear(MixedDev md, int slot) {
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < md.ldp; j += (int64_t)gridDim.x * 256)
+    md.dop[(int64_t)slot * md.ldp + j] = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < md.n_pad; i += (int64_t)gridDim.x * 256) {
+    md.gop[(int64_t)slot * md.n_pad + i] = 0;
+    md.dU[(int64_t)slot * md.n_pad + i] = 0.f;
+    md.dU[md.dU_ring + (int64_t)slot * md.n_pad + i] = 0.f;
+  }
+}
+
+// X~ (n_pad x ldp) and X~^T (ldp x n_pad) in BF16 from X in its stored precision.
+template <typename XT>
+__global__ __launch_bounds__(256) void k_make_bf16(const XT* __restrict__ X, int64_t ldx,
+                                                   int64_t n, int64_t p, int64_t n_pad,
+                                                   int64_t ldp, uint16_t* __restrict__ Xb,
+                                                   uint16_t* __restrict__ Xbt) {
+  __shared__ uint16_t tile[32][33];
+  const int64_t j0 = (int64_t)blockIdx.x * 32, i0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = i0 + r, j = j0 + tx;
+    uint16_t v = 0;
+    if (i < n && j < p) v = float_to_bf16((float)XLoad<XT>::get(X, (size_t)(i * ldx + j)));
+    if (i < n_pad && j < ldp) Xb[i * ldp + j] = v;
+    tile[r][tx] = v;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t j = j0 + r, i = i0 + tx;
+    if (j < ldp && i < n_pad) Xbt[j * n_pad + i] = tile[tx][r];
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+
+void launch_make_bf16(int xtype, const void* X, int64_t ldx, int64_t n, int64_t p, int64_t n_pad,
+                      int64_t ldp, uint16_t* Xb, uint16_t* Xbt, hipStream_t s) {
+  dim3 grid((unsigned)((ldp + 31) / 32), (unsigned)((n_pad + 31) / 32));
+  if (xtype == XT_F64)
+    hipLaunchKernelGGL(k_make_bf16<double>, grid, dim3(256), 0, s, (const double*)X, ldx, n, p, n_pad, ldp, Xb, Xbt);
+  else if (xtype == XT_F32)
+    hipLaunchKernelGGL(k_make_bf16<float>, grid, dim3(256), 0, s, (const float*)X, ldx, n, p, n_pad, ldp, Xb, Xbt);
+  else
+    hipLaunchKernelGGL(k_make_bf16<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)X, ldx, n, p, n_pad, ldp, Xb, Xbt);
+}
+
+void launch_gemm_x(const MixedDev& md, hipStream_t s) {
+  GemmArgs g;
+  g.A = md.Xb;
+  g.lda = md.ldp;
+  g.B = md.dop;
+  g.ldb = md.ldp;
+  g.M = md.n_pad;
+  g.K = md.ldp;
+  g.kchunk = md.ldp;
+  g.C = md.dU;
+  g.ldc = md.n_pad;
+  g.c_split_stride = 0;
+  g.ring2 = 1;
+  g.c_ring_stride = md.dU_ring;
+  dim3 grid((unsigned)(md.n_pad / GT_M), (unsigned)(md.S_pad / GT_N), 1);
+  hipLaunchKernelGGL(k_gemm_bf16<EPI_LOSS>, grid, dim3(256), 0, s, g, md);
+}
+
+void launch_gemm_xt(const MixedDev& md, hipStream_t s) {
+  GemmArgs g;
+  g.A = md.Xbt;
+  g.lda = md.n_pad;
+  g.B = md.gop;
+  g.ldb = md.n_pad;
+  g.M = md.ldp;
+  g.K = md.n_pad;
+  g.kchunk = md.xt_kchunk;
+  g.C = md.dH;
+  g.ldc = md.ldp;
+  g.c_split_stride = md.dH_split;
+  g.ring2 = 0;
+  g.c_ring_stride = 0;
+  dim3 grid((unsigned)(md.ldp / GT_M), (unsigned)(md.S_pad / GT_N), (unsigned)md.ksplit);
+  hipLaunchKernelGGL(k_gemm_bf16<EPI_STORE>, grid, dim3(256), 0, s, g, md);
+}
+
+void launch_mixed_restart(const MixedDev& md, hipStream_t s) {
+  hipLaunchKernelGGL(k_mixed_restart, dim3(md.slots), dim3(64), 0, s, md);
+}
+
+void launch_mixed_resid(const MixedDev& md, hipStream_t s) {
+  hipLaunchKernelGGL(k_mixed_resid, dim3((unsigned)md.nrt, (unsigned)md.slots), dim3(256), 0, s,
+                     md);
+}
+
+#define CGL_E_SWITCH(E_, CALL)   \
+  switch (E_) {                  \
+    case 1: { constexpr int EE = 1; CALL; break; }   \
+    case 2: { constexpr int EE = 2; CALL; break; }   \
+    case 4: { constexpr int EE = 4; CALL; break; }   \
+    case 8: { constexpr int EE = 8; CALL; break; }   \
+    case 16: { constexpr int EE = 16; CALL; break; } \
+    case 32: { constexpr int EE = 32; CALL; break; } \
+    default: break;              \
+  }
+
+void launch_mixed_node(const MixedDev& md, hipStream_t s) {
+  const int E = prox_elems(md.p);
+  CGL_E_SWITCH(E, hipLaunchKernelGGL(k_mixed_node<EE>, dim3(md.slots), dim3(kProxThreads), 0, s, md));
+}
+
+void launch_cycle_advance(const MixedDev& md, hipStream_t s) {
+  hipLaunchKernelGGL(k_cycle_advance, dim3(1), dim3(64), 0, s, md.cycle);
+}
+
+void launch_gemm_f64(int xtype, const void* X, int64_t ldx, int64_t M, int64_t K, int trans,
+                     const double* B, int64_t ldb, int Q, double* C, int64_t ldc, hipStream_t s) {
+  dim3 grid((unsigned)((M + FT_M - 1) / FT_M), (unsigned)((Q + FT_Q - 1) / FT_Q));
+#define CGL_F64_CALL(T)                                                                          \
+  if (trans) hipLaunchKernelGGL((k_gemm_f64<T, 1>), grid, dim3(256), 0, s, (const T*)X, ldx, M, K, B, ldb, Q, C, ldc); \
+  else hipLaunchKernelGGL((k_gemm_f64<T, 0>), grid, dim3(256), 0, s, (const T*)X, ldx, M, K, B, ldb, Q, C, ldc);
+  if (xtype == XT_F64) { CGL_F64_CALL(double) }
+  else if (xtype == XT_F32) { CGL_F64_CALL(float) }
+  else { CGL_F64_CALL(uint16_t) }
+#undef CGL_F64_CALL
+}
+
+void launch_cert_gather(const MixedDev& md, const int* list, int nq, double* B64, hipStream_t s) {
+  hipLaunchKernelGGL(k_cert_gather, dim3(8, (unsigned)nq), dim3(256), 0, s, md, list, nq, B64);
+}
+
+void launch_cert_resid(const MixedDev& md, const int* list, int nq, const double* U64,
+                       double* R64, double* part, int nchunk, int64_t chunk, hipStream_t s) {
+  hipLaunchKernelGGL(k_cert_resid, dim3((unsigned)nchunk, (unsigned)nq), dim3(256), 0, s, md,
+                     list, nq, U64, R64, part, nchunk, chunk);
+}
+
+void launch_cert_finish(const MixedDev& md, const int* list, int nq, const double* B64,
+                        const double* H64, const double* part, int nchunk, hipStream_t s) {
+  const int E = prox_elems(md.p);
+  CGL_E_SWITCH(E, hipLaunchKernelGGL(k_cert_finish<EE>, dim3((unsigned)nq), dim3(kProxThreads), 0, s, md, list, nq, B64, H64, part, nchunk));
+}
+
+void launch_slot_clear(const MixedDev& md, int slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_slot_clear, dim3(16), dim3(256), 0, s, md, slot);
+}
+
+}  // namespace cgl

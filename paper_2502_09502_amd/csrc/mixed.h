@@ -1,0 +1,68 @@
+// Device view of the batched mixed-precision engine and its launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "solver.h"
+
+namespace cgl {
+
+constexpr int kStallCycles = 15;  // re-centre when the working gap has not halved for this long
+
+struct MixedDev {
+  // problem
+  const uint16_t* Xb;   // n_pad x ldp, BF16 copy of X (zero padded)
+  const uint16_t* Xbt;  // ldp x n_pad, its transpose
+  int64_t n, p, n_pad, ldp;
+  const double* y;      // n_pad (zero padded)
+  int loss;
+  double lam2, M, L, rho;
+  // slots
+  int slots;            // S
+  int S_pad;            // operand rows, multiple of 256
+  NodeDev* st;          // S
+  const uint8_t* cls;   // S x ldp
+  double* bring;        // 3 rings x S x ldp (FP64 iterates)
+  int64_t bring_stride; // S x ldp
+  double* beta0;        // S x ldp base point
+  double* H0;           // S x ldp: X^T grad f(X beta_0)
+  double* base0;        // S x n_pad: least squares e_0 = X beta_0 - y; logistic u_0 = X beta_0
+  double* base1;        // S x n_pad: logistic r_0 = grad f(u_0)
+  double* bres;         // S x ldp: best certified iterate
+  uint16_t* dop;        // S_pad x ldp: bf16(beta - beta_0)
+  uint16_t* gop;        // S_pad x n_pad: bf16(grad f(u_gamma) - r_0)
+  float* dU;            // 2 rings x S_pad x n_pad
+  int64_t dU_ring;
+  float* dH;            // ksplit x S_pad x ldp
+  int64_t dH_split;
+  int ksplit;
+  int64_t xt_kchunk;
+  double* lpart;        // S x nmt loss partials (X pass epilogue)
+  int nmt;
+  double* fpart;        // S x nrt F* partials (residual kernel)
+  int nrt;
+  int64_t rchunk;
+  int* cycle;           // global cycle counter
+};
+
+void launch_make_bf16(int xtype, const void* X, int64_t ldx, int64_t n, int64_t p, int64_t n_pad,
+                      int64_t ldp, uint16_t* Xb, uint16_t* Xbt, hipStream_t s);
+void launch_gemm_x(const MixedDev& md, hipStream_t s);
+void launch_gemm_xt(const MixedDev& md, hipStream_t s);
+void launch_mixed_restart(const MixedDev& md, hipStream_t s);
+void launch_mixed_resid(const MixedDev& md, hipStream_t s);
+void launch_mixed_node(const MixedDev& md, hipStream_t s);
+void launch_cycle_advance(const MixedDev& md, hipStream_t s);
+void launch_gemm_f64(int xtype, const void* X, int64_t ldx, int64_t M, int64_t K, int trans,
+                     const double* B, int64_t ldb, int Q, double* C, int64_t ldc, hipStream_t s);
+void launch_cert_gather(const MixedDev& md, const int* list, int nq, double* B64, hipStream_t s);
+void launch_cert_resid(const MixedDev& md, const int* list, int nq, const double* U64,
+                       double* R64, double* part, int nchunk, int64_t chunk, hipStream_t s);
+void launch_cert_finish(const MixedDev& md, const int* list, int nq, const double* B64,
+                        const double* H64, const double* part, int nchunk, hipStream_t s);
+void launch_slot_clear(const MixedDev& md, int slot, hipStream_t s);
+void launch_admit(const MixedDev& md, const int* list, int nq, const double* H0_cold,
+                  const double* base0_cold, const double* base1_cold, hipStream_t s);
+
+}  // namespace cgl

@@ -36,6 +36,16 @@ struct NodeDev {
   int want_cert;     // mixed path: the node asks for an FP64 re-centring / certificate
   double tol;
   double incumbent;
+  // mixed path
+  double P_cert;     // best FP64-certified primal value
+  double D_cert;     // best FP64-certified dual value
+  double mgap_ref;   // working gap at the last halving
+  int active;        // slot holds a node whose base point is set
+  int primed;        // L^t of the current base is known (no restart test before that)
+  int since_improve; // cycles since the working gap last halved
+  int since_recentre;
+  int b_int0;        // scratch flag of the certification kernel
+  int last_ring;     // ring slot holding the latest prox output (the iterate g_new belongs to)
 };
 
 constexpr int kRunning = -1;

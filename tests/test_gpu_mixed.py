@@ -1,0 +1,112 @@
+"""Batched mixed-precision engine (BF16 MFMA corrections, FP64 re-centring and certificate)
+against the oracle, and batched results against the same nodes solved alone."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_09502_amd import _lib, synth
+
+from gpu_util import ctx, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(d):
+    return _lib.Problem(ctx(), d.X_store, d.y, loss=d.loss, lam2=d.lam2, M=d.M, k=d.k)
+
+
+def _specs(prob, sets, **kw):
+    kw.setdefault("tol", 1e-6)
+    kw.setdefault("max_iter", 5000)
+    return [prob.node(Z0=z0, Z1=z1, precision="mixed", **kw) for z0, z1 in sets]
+
+
+def _check(d, res, z0, z1, ref=None, tol=1e-6):
+    ns = oracle.node_sets(d.p, z0, z1)
+    if ref is None:
+        ref = oracle.solve_node(d.X, d.y, d.loss, d.lam2, d.M, d.k, z0, z1, tol=1e-9)
+    assert res.status == "converged", res
+    assert res.gap_rel <= tol
+    assert rel(res.primal, ref.primal) <= 1e-6, (res.primal, ref.primal)
+    assert res.lower_bound <= ref.primal
+    Pb = oracle.primal_value(d.X, d.y, d.loss, d.lam2, d.M, d.k, ns, res.beta)
+    assert rel(Pb, res.primal) <= 1e-10
+
+
+@pytest.mark.parametrize("loss", ["ls", "logistic"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_small_batch_matches_oracle(loss, dtype):
+    d = synth.make_dataset(500, 200, 8, loss=loss, dtype=dtype, config_id=80)
+    prob = _problem(d)
+    sets = synth.node_sets(d.p, d.k, 6, 12, config_id=80)
+    res = prob.solve_batch(_specs(prob, sets))
+    for (z0, z1), r in zip(sets, res):
+        _check(d, r, z0, z1)
+
+
+def test_config1_mixed_root():
+    d = synth.make_config("c1")
+    prob = _problem(d)
+    r = prob.solve(precision="mixed", tol=1e-6, max_iter=5000)
+    _check(d, r, (), ())
+
+
+def test_batched_equals_alone_and_refill():
+    """More nodes than slots (continuous refill); each batched result equals the same node solved
+    alone within the tolerance."""
+    d = synth.make_dataset(400, 150, 6, config_id=81)
+    prob = _problem(d)
+    sets = synth.node_sets(d.p, d.k, 300, 15, config_id=81)
+    batched = prob.solve_batch(_specs(prob, sets))
+    assert all(r.status == "converged" and r.gap_rel <= 1e-6 for r in batched)
+    for i in (0, 7, 150, 299):
+        alone = prob.solve_batch(_specs(prob, [sets[i]]))[0]
+        assert rel(batched[i].primal, alone.primal) <= 2e-6
+        assert batched[i].lower_bound <= alone.primal + 1e-9 * abs(alone.primal)
+        assert alone.lower_bound <= batched[i].primal + 1e-9 * abs(alone.primal)
+    for i in (3, 250):
+        _check(d, batched[i], *sets[i])
+
+
+def test_mixed_edge_cases():
+    d = synth.make_dataset(150, 40, 4, config_id=82)
+    prob = _problem(d)
+    specs = [
+        prob.node(Z1=[0, 1, 2, 3, 4], precision="mixed"),             # infeasible
+        prob.node(Z0=np.arange(40), precision="mixed"),               # everything fixed to 0
+        prob.node(Z1=[3, 5, 7, 9], precision="mixed"),                # k' = 0
+        prob.node(precision="mixed", max_iter=2),                     # cap
+        prob.node(precision="mixed", max_iter=1),                     # no iteration at all
+    ]
+    r = prob.solve_batch(specs)
+    assert r[0].status == "infeasible" and r[0].lower_bound == math.inf
+    f0 = float(d.y @ d.y)
+    assert r[1].status == "converged" and rel(r[1].primal, f0) < 1e-12
+    ref = oracle.solve_node(d.X, d.y, "ls", d.lam2, d.M, d.k, (), [3, 5, 7, 9], tol=1e-10)
+    assert rel(r[2].primal, ref.primal) <= 1e-6 and r[2].lower_bound <= ref.primal
+    root = oracle.solve_node(d.X, d.y, "ls", d.lam2, d.M, d.k, tol=1e-10)
+    for q in (3, 4):
+        assert r[q].status == "not_converged" and r[q].lower_bound <= root.primal
+    with pytest.raises(_lib.CglError):
+        prob.solve_batch([prob.node(precision="mixed", warm_start=np.zeros(d.p))])
+
+
+def test_config4_subset_full_size():
+    """n = 20000, p = 10000, BF16 X: 16 nodes of the benchmark workload are certified to 1e-6;
+    the oracle re-evaluates each returned beta to the reported objective and certifies it with
+    its own dual point."""
+    d = synth.make_config("c4")
+    prob = _problem(d)
+    sets = synth.node_sets(d.p, d.k, 16, 20, config_id=4)
+    res = prob.solve_batch(_specs(prob, sets))
+    for (z0, z1), r in zip(sets, res):
+        assert r.status == "converged" and r.gap_rel <= 1e-6, r
+        ns = oracle.node_sets(d.p, z0, z1)
+        P = oracle.primal_value(d.X, d.y, "ls", d.lam2, d.M, d.k, ns, r.beta)
+        zeta = -2.0 * (d.X @ r.beta - d.y)
+        D = oracle.dual_value(d.X, d.y, "ls", d.lam2, d.M, d.k, ns, zeta)
+        assert rel(P, r.primal) <= 1e-10
+        assert (P - D) / abs(P) <= 2e-6
+        assert r.lower_bound <= P

@@ -33,7 +33,7 @@ void MixedWork::ensure(Problem& P) {
   hipStream_t s = P.ctx->stream;
   S = kSlots;
   S_pad = (int)round_up(S, 256);
-  n_pad = round_up(P.n, 64);
+  n_pad = round_up(P.n, 128);  // rows of X~: a multiple of the GEMM tile and of its k-chunk grain
   ldp = P.ldx;
   // BF16 design and its transpose
   Xb.alloc((size_t)n_pad * ldp * 2);
@@ -56,13 +56,23 @@ void MixedWork::ensure(Problem& P) {
   dop.alloc((size_t)S_pad * ldp * 2);
   gop.alloc((size_t)S_pad * n_pad * 2);
   dU.alloc(2 * (size_t)S_pad * n_pad * 4);
-  ksplit = ldp / 64 >= 256 ? 1 : 2;  // enough workgroups for the X^T pass
-  xt_kchunk = round_up((n_pad + ksplit - 1) / ksplit, 32);
+  // split-K so that each pass has about 3 workgroups per compute unit, each >= 16 k-steps
+  auto split_for = [](int64_t m_tiles, int64_t K) {
+    const int64_t want = (3 * 256 + m_tiles - 1) / m_tiles;
+    const int64_t cap = std::max<int64_t>(1, K / (32 * 16));
+    return (int)std::max<int64_t>(1, std::min(want, cap));
+  };
+  ksx = split_for(n_pad / 64, ldp);
+  x_kchunk = round_up((ldp + ksx - 1) / ksx, 128);
+  ksx = (int)((ldp + x_kchunk - 1) / x_kchunk);
+  dUp.alloc((size_t)ksx * S_pad * n_pad * 4);
+  ksplit = split_for(ldp / 64, n_pad);
+  xt_kchunk = round_up((n_pad + ksplit - 1) / ksplit, 128);
+  ksplit = (int)((n_pad + xt_kchunk - 1) / xt_kchunk);
   dH.alloc((size_t)ksplit * S_pad * ldp * 4);
-  nmt = (int)(n_pad / 64);
-  lpart.alloc((size_t)S * nmt * 8);
   rchunk = 2048;
   nrt = (int)((n_pad + rchunk - 1) / rchunk);
+  lpart.alloc((size_t)S * nrt * 8);
   fpart.alloc((size_t)S * nrt * 8);
   cycle.alloc(sizeof(int));
   CGL_HIP(hipMemsetAsync(cycle.ptr, 0, sizeof(int), s));
@@ -146,12 +156,15 @@ void MixedWork::ensure(Problem& P) {
   md.gop = gop.as<uint16_t>();
   md.dU = dU.as<float>();
   md.dU_ring = (int64_t)S_pad * n_pad;
+  md.dUp = dUp.as<float>();
+  md.dUp_split = (int64_t)S_pad * n_pad;
+  md.ksx = ksx;
+  md.x_kchunk = x_kchunk;
   md.dH = dH.as<float>();
   md.dH_split = (int64_t)S_pad * ldp;
   md.ksplit = ksplit;
   md.xt_kchunk = xt_kchunk;
   md.lpart = lpart.as<double>();
-  md.nmt = nmt;
   md.fpart = fpart.as<double>();
   md.nrt = nrt;
   md.rchunk = rchunk;
@@ -166,6 +179,7 @@ static void mixed_cycle(MixedWork& W, hipStream_t s, hipEvent_t* ev = nullptr) {
   if (ev) CGL_HIP(hipEventRecord(ev[0], s));
   launch_gemm_x(W.md, s);
   if (ev) CGL_HIP(hipEventRecord(ev[1], s));
+  launch_mixed_loss(W.md, s);
   launch_mixed_restart(W.md, s);
   launch_mixed_resid(W.md, s);
   if (ev) CGL_HIP(hipEventRecord(ev[2], s));

@@ -27,10 +27,11 @@ struct MixedWork {
   int64_t n_pad = 0, ldp = 0;
   int ksplit = 1;
   int64_t xt_kchunk = 0;
-  int nmt = 0, nrt = 0, ncchunk = 0;
+  int nrt = 0, ncchunk = 0, ksx = 1;
+  int64_t x_kchunk = 0;
   int64_t rchunk = 0, cchunk = 0;
   double f_cold = 0.0;
-  DevBuf Xb, Xbt, ypad, st, cls, bring, beta0, H0, base0, base1, bres, dop, gop, dU, dH, lpart,
+  DevBuf Xb, Xbt, ypad, st, cls, bring, beta0, H0, base0, base1, bres, dop, gop, dU, dUp, dH, lpart,
       fpart, cycle, B64, U64, R64, H64, cpart, list, H0_cold, base0_cold, base1_cold;
   NodeDev* st_host = nullptr;
   std::vector<uint8_t> cls_host;

@@ -13,20 +13,19 @@
 // correction, which shrinks as the iterate approaches the base; the base is re-centred in FP64
 // (and the bound certified, Sec. 3.4) when the working-precision gap stops improving.
 //
-// One iteration (cycle) for every active slot: k_gemm_x (loss epilogue) -> k_mixed_restart ->
-// k_mixed_resid -> k_gemm_xt -> k_mixed_node (prox) -> k_cycle_advance.
+// One iteration (cycle) for every active slot: k_gemm_x (split-K) -> k_mixed_loss ->
+// k_mixed_restart -> k_mixed_resid -> k_gemm_xt (split-K) -> k_mixed_node (prox) -> k_cycle_advance.
 #include <limits.h>
 
 #include "common.h"
 #include "kernels.h"
+#include "gemm_bf16.h"
 #include "mixed.h"
 #include "prox.h"
 #include "solver.h"
 
 namespace cgl {
 
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
-typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
 typedef __attribute__((__vector_size__(4 * sizeof(double)))) double doublex4;
 
 __device__ __forceinline__ double softplus_d(double t) {
@@ -45,117 +44,26 @@ __device__ __forceinline__ bool slot_running(const NodeDev* st) {
 }
 
 // =====================================================================================
-// BF16 MFMA GEMM: C[node][m] = sum_k A[m][k] * B[node][k]
-//   A: M x K bf16 row-major (lda), B: nodes x K bf16 row-major (ldb); M multiple of GT_M, K
-//   multiple of GT_K, node rows padded to a multiple of GT_N with zero rows.
-// Workgroup tile: 64 rows of A x 256 nodes; 4 waves, wave w covers nodes [64w, 64w + 64) with
-// 2 x 2 tiles of v_mfma_f32_32x32x16_bf16. Double-buffered LDS, one barrier per k-step.
+// BF16 MFMA product (see gemm_bf16.h), split-K partials stored node-major.
+// Element e of lane l in tile c: row i = (e % 4) + 4 (l / 32) + 8 (e / 4), node j = l % 32.
 // =====================================================================================
-
-constexpr int GT_M = 64;
-constexpr int GT_N = 256;
-constexpr int GT_K = 32;
-constexpr int GT_LD = GT_K + 8;  // LDS row pitch in bf16 (80 bytes)
-
-enum { EPI_STORE = 0, EPI_LOSS = 1 };
-
-struct GemmArgs {
-  const uint16_t* A;
-  int64_t lda;
-  const uint16_t* B;
-  int64_t ldb;
-  int64_t M, K;
-  int64_t kchunk;  // split-K chunk (multiple of GT_K)
-  float* C;
-  int64_t ldc;
-  int64_t c_split_stride;
-  int ring2;       // EPI_LOSS: C is a 2-slot ring selected by the cycle counter
-  int64_t c_ring_stride;
-};
-
-template <int EPI>
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, MixedDev md) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[2][GT_M * GT_LD];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][GT_N * GT_LD];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wid = tid >> 6;
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[2 * GT_M * GT_LD];
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
   const int64_t m0 = (int64_t)blockIdx.x * GT_M;
   const int64_t n0 = (int64_t)blockIdx.y * GT_N;
   const int64_t k0 = (int64_t)blockIdx.z * g.kchunk;
   const int64_t k1 = min(g.K, k0 + g.kchunk);
-
-  const int lrow = tid >> 2;       // 0..63
-  const int lk = (tid & 3) * 8;    // 0, 8, 16, 24
-  const uint16_t* ag = g.A + (m0 + lrow) * g.lda + lk;
-  const uint16_t* bg = g.B + (n0 + lrow) * g.ldb + lk;
-  uint4 ra, rb[4];
-  auto gload = [&](int64_t kk) {
-    ra = *reinterpret_cast<const uint4*>(ag + kk);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) rb[q] = *reinterpret_cast<const uint4*>(bg + (int64_t)q * 64 * g.ldb + kk);
-  };
-  auto lstore = [&](int buf) {
-    *reinterpret_cast<uint4*>(&As[buf][lrow * GT_LD + lk]) = ra;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      *reinterpret_cast<uint4*>(&Bs[buf][(lrow + 64 * q) * GT_LD + lk]) = rb[q];
-  };
-
   floatx16 acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.f;
-
-  if (k0 < k1) {
-    gload(k0);
-    lstore(0);
-  }
-  __syncthreads();
-  int buf = 0;
-  const int fr = lane & 31;
-  const int fk = (lane >> 5) * 8;
-  for (int64_t kk = k0; kk < k1; kk += GT_K) {
-    const bool more = kk + GT_K < k1;
-    if (more) gload(kk + GT_K);
-#pragma unroll
-    for (int ks = 0; ks < GT_K / 16; ++ks) {
-      bf16x8 af[2], bfr[2];
-#pragma unroll
-      for (int r = 0; r < 2; ++r)
-        af[r] = *reinterpret_cast<const bf16x8*>(&As[buf][(r * 32 + fr) * GT_LD + ks * 16 + fk]);
-#pragma unroll
-      for (int c = 0; c < 2; ++c)
-        bfr[c] = *reinterpret_cast<const bf16x8*>(
-            &Bs[buf][(wid * 64 + c * 32 + fr) * GT_LD + ks * 16 + fk]);
-#pragma unroll
-      for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-          acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[r], bfr[c], acc[r][c], 0, 0, 0);
-    }
-    if (more) lstore(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
-  }
-
-  // ---- epilogue. Element e of lane l in tile (r, c): row i = (e%4) + 4 (l/32) + 8 (e/4),
-  // node j = l % 32.
+  gemm_bf16_mainloop(g, m0, n0, k0, k1, As, acc);
+  float* C = g.C + (int64_t)blockIdx.z * g.c_split_stride;
   const int hi = lane >> 5;
-  float* Cbase = g.C + (int64_t)blockIdx.z * g.c_split_stride;
-  if (EPI == EPI_LOSS && g.ring2) {
-    const int cyc = *md.cycle;
-    Cbase += (int64_t)(cyc & 1) * g.c_ring_stride;
-  }
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const int64_t node = n0 + wid * 64 + c * 32 + (lane & 31);
-    double lsum = 0.0;
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int64_t m = m0 + r * 32 + 4 * hi + 8 * q;
@@ -164,27 +72,37 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, MixedDev md) {
         v.y = acc[r][c][4 * q + 1];
         v.z = acc[r][c][4 * q + 2];
         v.w = acc[r][c][4 * q + 3];
-        *reinterpret_cast<float4*>(Cbase + node * g.ldc + m) = v;
-        if (EPI == EPI_LOSS && node < md.slots) {
-          const float vv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int64_t mm = m + t;
-            if (mm < md.n) {
-              const double b0 = md.base0[node * md.n_pad + mm];
-              const double u = b0 + (double)vv[t];
-              if (md.loss == LOSS_LS) lsum += u * u;  // base0 holds e_0 = u_0 - y
-              else lsum += softplus_d(-md.y[mm] * u);  // base0 holds u_0
-            }
-          }
-        }
+        *reinterpret_cast<float4*>(C + node * g.ldc + m) = v;
       }
-    }
-    if (EPI == EPI_LOSS) {
-      lsum += __shfl_xor(lsum, 32, kWave);
-      if (hi == 0 && node < md.slots) md.lpart[node * md.nmt + blockIdx.x] = lsum;
+  }
+}
+
+// =====================================================================================
+// dU^{t+1} = sum of the X-pass split-K partials (into the ring slot of this cycle) and the loss
+// terms f_i(u_0 + dU) summed per chunk. grid: (chunks, slots); 256 threads.
+// =====================================================================================
+__global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
+  __shared__ double red[4];
+  const int slot = blockIdx.y;
+  const NodeDev* st = md.st + slot;
+  if (!slot_running(st)) return;
+  const int cyc = *md.cycle;
+  float* dun = md.dU + (int64_t)(cyc & 1) * md.dU_ring + (int64_t)slot * md.n_pad;
+  const int64_t i0 = (int64_t)blockIdx.x * md.rchunk;
+  const int64_t i1 = min(md.n_pad, i0 + md.rchunk);
+  double ls = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+    float du = 0.f;
+    for (int q = 0; q < md.ksx; ++q) du += md.dUp[(int64_t)q * md.dUp_split + (int64_t)slot * md.n_pad + i];
+    dun[i] = du;
+    if (i < md.n) {
+      const double u = md.base0[(int64_t)slot * md.n_pad + i] + (double)du;
+      if (md.loss == LOSS_LS) ls += u * u;  // base0 holds e_0 = u_0 - y
+      else ls += softplus_d(-md.y[i] * u);  // base0 holds u_0
     }
   }
+  ls = block_reduce(ls, red, OpAdd(), 0.0);
+  if (threadIdx.x == 0) md.lpart[(int64_t)slot * md.nrt + blockIdx.x] = ls;
 }
 
 // =====================================================================================
@@ -194,7 +112,7 @@ __global__ __launch_bounds__(64) void k_mixed_restart(MixedDev md) {
   NodeDev* st = md.st + blockIdx.x;
   if (!slot_running(st)) return;
   double a = 0.0;
-  for (int i = threadIdx.x; i < md.nmt; i += 64) a += md.lpart[(int64_t)blockIdx.x * md.nmt + i];
+  for (int i = threadIdx.x; i < md.nrt; i += 64) a += md.lpart[(int64_t)blockIdx.x * md.nrt + i];
   a = wave_sum(a);
   if (threadIdx.x == 0) {
     const double Lnew = a + 2.0 * md.lam2 * st->g_new;
@@ -680,14 +598,13 @@ void launch_gemm_x(const MixedDev& md, hipStream_t s) {
   g.ldb = md.ldp;
   g.M = md.n_pad;
   g.K = md.ldp;
-  g.kchunk = md.ldp;
-  g.C = md.dU;
+  g.kchunk = md.x_kchunk;
+  g.C = md.dUp;
   g.ldc = md.n_pad;
-  g.c_split_stride = 0;
-  g.ring2 = 1;
-  g.c_ring_stride = md.dU_ring;
-  dim3 grid((unsigned)(md.n_pad / GT_M), (unsigned)(md.S_pad / GT_N), 1);
-  hipLaunchKernelGGL(k_gemm_bf16<EPI_LOSS>, grid, dim3(256), 0, s, g, md);
+  g.c_split_stride = md.dUp_split;
+  g.c_ring_stride = 0;
+  dim3 grid((unsigned)(md.n_pad / GT_M), (unsigned)(md.S_pad / GT_N), (unsigned)md.ksx);
+  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, g);
 }
 
 void launch_gemm_xt(const MixedDev& md, hipStream_t s) {
@@ -702,10 +619,14 @@ void launch_gemm_xt(const MixedDev& md, hipStream_t s) {
   g.C = md.dH;
   g.ldc = md.ldp;
   g.c_split_stride = md.dH_split;
-  g.ring2 = 0;
   g.c_ring_stride = 0;
   dim3 grid((unsigned)(md.ldp / GT_M), (unsigned)(md.S_pad / GT_N), (unsigned)md.ksplit);
-  hipLaunchKernelGGL(k_gemm_bf16<EPI_STORE>, grid, dim3(256), 0, s, g, md);
+  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, g);
+}
+
+void launch_mixed_loss(const MixedDev& md, hipStream_t s) {
+  hipLaunchKernelGGL(k_mixed_loss, dim3((unsigned)md.nrt, (unsigned)md.slots), dim3(256), 0, s,
+                     md);
 }
 
 void launch_mixed_restart(const MixedDev& md, hipStream_t s) {

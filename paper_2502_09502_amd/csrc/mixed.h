@@ -34,12 +34,15 @@ struct MixedDev {
   uint16_t* gop;        // S_pad x n_pad: bf16(grad f(u_gamma) - r_0)
   float* dU;            // 2 rings x S_pad x n_pad
   int64_t dU_ring;
-  float* dH;            // ksplit x S_pad x ldp
+  float* dUp;           // ksx x S_pad x n_pad split-K partials of the X pass
+  int64_t dUp_split;
+  int ksx;
+  int64_t x_kchunk;
+  float* dH;            // ksplit x S_pad x ldp split-K partials of the X^T pass
   int64_t dH_split;
   int ksplit;
   int64_t xt_kchunk;
-  double* lpart;        // S x nmt loss partials (X pass epilogue)
-  int nmt;
+  double* lpart;        // S x nrt loss partials
   double* fpart;        // S x nrt F* partials (residual kernel)
   int nrt;
   int64_t rchunk;
@@ -50,6 +53,7 @@ void launch_make_bf16(int xtype, const void* X, int64_t ldx, int64_t n, int64_t 
                       int64_t ldp, uint16_t* Xb, uint16_t* Xbt, hipStream_t s);
 void launch_gemm_x(const MixedDev& md, hipStream_t s);
 void launch_gemm_xt(const MixedDev& md, hipStream_t s);
+void launch_mixed_loss(const MixedDev& md, hipStream_t s);
 void launch_mixed_restart(const MixedDev& md, hipStream_t s);
 void launch_mixed_resid(const MixedDev& md, hipStream_t s);
 void launch_mixed_node(const MixedDev& md, hipStream_t s);

@@ -349,8 +349,11 @@ __device__ double tail_root(const double (&u)[E], const bool (&tail)[E], const d
     const double m = acc[0], S = acc[1];
     if (!checked_start) {
       checked_start = true;
-      if (head_part(hu, kh, v, rho, M) - (S - m * v) > 0.0) {  // hint above v*: start at 0
-        v = 0.0;
+      if (head_part(hu, kh, v, rho, M) - (S - m * v) > 0.0) {
+        // hint above v*: the members at the hint are a subset of those at any v below it, so
+        // the root with this set fixed, searched from 0, is a lower bound on v* (and close to it
+        // when the hint is)
+        v = psi_root(hu, kh, 0.0, m, S, rho, M);
         continue;
       }
     }

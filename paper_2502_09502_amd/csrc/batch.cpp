@@ -56,17 +56,18 @@ void MixedWork::ensure(Problem& P) {
   dop.alloc((size_t)S_pad * ldp * 2);
   gop.alloc((size_t)S_pad * n_pad * 2);
   dU.alloc(2 * (size_t)S_pad * n_pad * 4);
-  // split-K so that each pass has about 3 workgroups per compute unit, each >= 16 k-steps
+  // split-K so that each pass has about 2 workgroups (128 rows x 256 nodes) per compute unit,
+  // each with >= 16 k-steps of 32
   auto split_for = [](int64_t m_tiles, int64_t K) {
-    const int64_t want = (3 * 256 + m_tiles - 1) / m_tiles;
+    const int64_t want = (2 * 256 + m_tiles - 1) / m_tiles;
     const int64_t cap = std::max<int64_t>(1, K / (32 * 16));
     return (int)std::max<int64_t>(1, std::min(want, cap));
   };
-  ksx = split_for(n_pad / 64, ldp);
+  ksx = split_for(n_pad / 128, ldp);
   x_kchunk = round_up((ldp + ksx - 1) / ksx, 128);
   ksx = (int)((ldp + x_kchunk - 1) / x_kchunk);
   dUp.alloc((size_t)ksx * S_pad * n_pad * 4);
-  ksplit = split_for(ldp / 64, n_pad);
+  ksplit = split_for(ldp / 128, n_pad);
   xt_kchunk = round_up((n_pad + ksplit - 1) / ksplit, 128);
   ksplit = (int)((n_pad + xt_kchunk - 1) / xt_kchunk);
   dH.alloc((size_t)ksplit * S_pad * ldp * 4);
@@ -87,6 +88,14 @@ void MixedWork::ensure(Problem& P) {
   H64.alloc(Sp * 8);
   CGL_HIP(hipMemsetAsync(H64.ptr, 0, Sp * 8, s));
   CGL_HIP(hipMemsetAsync(U64.ptr, 0, Sn * 8, s));
+  // split-K partials of the FP64 products (split x nodes <= 2 S)
+  part64_cap = 2 * (size_t)S * (size_t)std::max<int64_t>(n_pad, ldp) * 8;
+  part64.alloc(part64_cap);
+  // X^T in the stored precision for the FP64 X^T products (the BF16 transpose is exact for BF16)
+  if (P.xtype != XT_BF16) {
+    Xt.alloc((size_t)P.p * n_pad * (P.xtype == XT_F64 ? 8 : 4));
+    launch_transpose(P.xtype, P.X.ptr, P.ldx, P.n, P.p, n_pad, Xt.ptr, s);
+  }
   cchunk = 2048;
   ncchunk = (int)((n_pad + cchunk - 1) / cchunk);
   cpart.alloc((size_t)S * ncchunk * 16);
@@ -248,13 +257,14 @@ bool MixedWork::cert_round(Problem& P) {
   hipEvent_t e1 = ctx->profiling ? ctx->event(101) : nullptr;
   launch_cert_gather(md, list.as<int>(), nq, B64.as<double>(), s);
   if (e0) CGL_HIP(hipEventRecord(e0, s));
-  launch_gemm_f64(P.xtype, P.X.ptr, P.ldx, P.n, P.p, 0, B64.as<double>(), ldp, nq,
-                  U64.as<double>(), n_pad, s);
+  launch_gemm_f64(P.xtype, P.X.ptr, P.ldx, P.n, P.p, B64.as<double>(), ldp, nq, U64.as<double>(),
+                  n_pad, part64.as<double>(), part64_cap, s);
   if (e1) CGL_HIP(hipEventRecord(e1, s));
   launch_cert_resid(md, list.as<int>(), nq, U64.as<double>(), R64.as<double>(),
                     cpart.as<double>(), ncchunk, cchunk, s);
-  launch_gemm_f64(P.xtype, P.X.ptr, P.ldx, P.p, P.n, 1, R64.as<double>(), n_pad, nq,
-                  H64.as<double>(), ldp, s);
+  const void* xt = P.xtype == XT_BF16 ? Xbt.ptr : Xt.ptr;
+  launch_gemm_f64(P.xtype, xt, n_pad, P.p, P.n, R64.as<double>(), n_pad, nq, H64.as<double>(), ldp,
+                  part64.as<double>(), part64_cap, s);
   launch_cert_finish(md, list.as<int>(), nq, B64.as<double>(), H64.as<double>(),
                      cpart.as<double>(), ncchunk, s);
   CGL_HIP(hipMemcpyAsync(st_host, st.ptr, (size_t)S * sizeof(NodeDev), hipMemcpyDeviceToHost, s));

@@ -17,9 +17,12 @@
 // k_mixed_restart -> k_mixed_resid -> k_gemm_xt (split-K) -> k_mixed_node (prox) -> k_cycle_advance.
 #include <limits.h>
 
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 #include "gemm_bf16.h"
+#include "gemm_f64.h"
 #include "mixed.h"
 #include "prox.h"
 #include "solver.h"
@@ -47,6 +50,9 @@ __device__ __forceinline__ bool slot_running(const NodeDev* st) {
 // BF16 MFMA product (see gemm_bf16.h), split-K partials stored node-major.
 // Element e of lane l in tile c: row i = (e % 4) + 4 (l / 32) + 8 (e / 4), node j = l % 32.
 // =====================================================================================
+// PASS only names the instantiation (0: X~ (beta - beta_0), 1: X~^T (grad - r_0)) so that
+// profiles report the two products separately.
+template <int PASS>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) uint16_t As[2 * GT_M * GT_LD];
   const int lane = threadIdx.x & 63;
@@ -55,7 +61,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   const int64_t n0 = (int64_t)blockIdx.y * GT_N;
   const int64_t k0 = (int64_t)blockIdx.z * g.kchunk;
   const int64_t k1 = min(g.K, k0 + g.kchunk);
-  floatx16 acc[2][2];
+  floatx16 acc[GT_RT][2];
   gemm_bf16_mainloop(g, m0, n0, k0, k1, As, acc);
   float* C = g.C + (int64_t)blockIdx.z * g.c_split_stride;
   const int hi = lane >> 5;
@@ -63,7 +69,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   for (int c = 0; c < 2; ++c) {
     const int64_t node = n0 + wid * 64 + c * 32 + (lane & 31);
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int r = 0; r < GT_RT; ++r)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int64_t m = m0 + r * 32 + 4 * hi + 8 * q;
@@ -167,7 +173,7 @@ __global__ __launch_bounds__(256) void k_mixed_resid(MixedDev md) {
         gv = float_to_bf16((float)(r - md.base1[(int64_t)slot * md.n_pad + i]));
       }
     }
-    md.gop[(int64_t)slot * md.n_pad + i] = gv;
+    md.gop[frag_index(slot, i, md.S_pad >> 5)] = gv;
   }
   fs = block_reduce(fs, red, OpAdd(), 0.0);
   if (threadIdx.x == 0) md.fpart[(int64_t)slot * md.nrt + blockIdx.x] = fs;
@@ -220,7 +226,7 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
     const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
     if (j < p) {
       bout[j] = br[s];
-      md.dop[(int64_t)slot * md.ldp + j] = float_to_bf16((float)(br[s] - b0[j]));
+      md.dop[frag_index(slot, j, md.S_pad >> 5)] = float_to_bf16((float)(br[s] - b0[j]));
     }
   }
   // dual monitor at gamma: D = -F*(-zeta) - 2 lambda2 g_node*(-grad F(gamma) / (2 lambda2))
@@ -274,91 +280,25 @@ __global__ void k_cycle_advance(int* cycle) {
 }
 
 // =====================================================================================
-// FP64 batched products for re-centring and certification:
-//   C[q][m] = sum_k A(m, k) B[q][k],  A(m, k) = X[m][k] (TRANS = 0) or X[k][m] (TRANS = 1),
-// X in its stored precision (converted exactly to FP64), B FP64 node-major. v_mfma_f64_16x16x4.
-// Workgroup tile 64 (m) x 64 (q), k-step 16; wave w: rows 32 (w % 2) .. +32, nodes 32 (w / 2)
-// .. +32 as 2 x 2 MFMA tiles.
+// Native-precision transposed copy of X for the FP64 X^T products of certification
+// (BF16 designs use the BF16 transpose, which is exact for them).
 // =====================================================================================
 
-constexpr int FT_M = 64, FT_Q = 64, FT_K = 16;
-
-template <typename XT, int TRANS>
-__global__ __launch_bounds__(256) void k_gemm_f64(const XT* __restrict__ X, int64_t ldx,
-                                                  int64_t M, int64_t K,
-                                                  const double* __restrict__ B, int64_t ldb,
-                                                  int Q, double* __restrict__ C, int64_t ldc) {
-  __shared__ double As[FT_K][FT_M + 1];
-  __shared__ double Bs[FT_K][FT_Q + 1];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wid = tid >> 6;
-  const int64_t m0 = (int64_t)blockIdx.x * FT_M;
-  const int q0 = blockIdx.y * FT_Q;
-  doublex4 acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) acc[a][b][e] = 0.0;
-  const int wm = (wid & 1) * 32, wq = (wid >> 1) * 32;
-  for (int64_t k0 = 0; k0 < K; k0 += FT_K) {
-    // A tile (64 x 16): 1024 values, 4 per thread
-    if (TRANS == 0) {
-      const int r = tid >> 2, kk = (tid & 3) * 4;
-      const int64_t m = m0 + r;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int64_t k = k0 + kk + t;
-        As[kk + t][r] = (m < M && k < K) ? XLoad<XT>::get(X, (size_t)(m * ldx + k)) : 0.0;
-      }
-    } else {
-      const int kk = tid >> 4, mm = (tid & 15) * 4;
-      const int64_t k = k0 + kk;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int64_t m = m0 + mm + t;
-        As[kk][mm + t] = (m < M && k < K) ? XLoad<XT>::get(X, (size_t)(k * ldx + m)) : 0.0;
-      }
-    }
-    {  // B tile (64 nodes x 16): 4 per thread
-      const int q = tid >> 2, kk = (tid & 3) * 4;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int64_t k = k0 + kk + t;
-        Bs[kk + t][q] = (q0 + q < Q && k < K) ? B[(int64_t)(q0 + q) * ldb + k] : 0.0;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < FT_K / 4; ++ks) {
-      double af[2], bf[2];
-#pragma unroll
-      for (int r = 0; r < 2; ++r) af[r] = As[ks * 4 + (lane >> 4)][wm + r * 16 + (lane & 15)];
-#pragma unroll
-      for (int c = 0; c < 2; ++c) bf[c] = Bs[ks * 4 + (lane >> 4)][wq + c * 16 + (lane & 15)];
-#pragma unroll
-      for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-          acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[r], bf[c], acc[r][c], 0, 0, 0);
-    }
-    __syncthreads();
+template <typename XT>
+__global__ __launch_bounds__(256) void k_transpose(const XT* __restrict__ X, int64_t ldx, int64_t n,
+                                                   int64_t p, int64_t n_pad, XT* __restrict__ Xt) {
+  __shared__ XT tile[32][33];
+  const int64_t j0 = (int64_t)blockIdx.x * 32, i0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = i0 + r, j = j0 + tx;
+    tile[r][tx] = (i < n && j < p) ? X[i * ldx + j] : (XT)0;
   }
-  // C[i][j]: lane j + 16 (i % 4), element i / 4
-#pragma unroll
-  for (int r = 0; r < 2; ++r)
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int i = (lane >> 4) + 4 * e;
-        const int j = lane & 15;
-        const int64_t m = m0 + wm + r * 16 + i;
-        const int q = q0 + wq + c * 16 + j;
-        if (m < M && q < Q) C[(int64_t)q * ldc + m] = acc[r][c][e];
-      }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t j = j0 + r, i = i0 + tx;
+    if (j < p && i < n_pad) Xt[j * n_pad + i] = tile[tx][r];
+  }
 }
 
 // =====================================================================================
@@ -499,7 +439,7 @@ __global__ __launch_bounds__(1024) void k_cert_finish(MixedDev md, const int* li
       md.H0[(int64_t)slot * md.ldp + j] = H64[(int64_t)q * md.ldp + j];
       for (int r = 0; r < 3; ++r) md.bring[(int64_t)r * md.bring_stride + (int64_t)slot * md.ldp + j] = bj;
     }
-    md.dop[(int64_t)slot * md.ldp + j] = 0;
+    md.dop[frag_index(slot, j, md.S_pad >> 5)] = 0;
   }
   if (!done) {
     for (int64_t i = threadIdx.x; i < md.n_pad; i += blockDim.x) {
@@ -525,7 +465,7 @@ __global__ __launch_bounds__(256) void k_admit(MixedDev md, const int* list, int
     md.beta0[o] = 0.0;
     md.bres[o] = 0.0;
     md.H0[o] = H0_cold[j];
-    md.dop[o] = 0;
+    md.dop[frag_index(slot, j, md.S_pad >> 5)] = 0;
   }
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < md.n_pad; i += stride) {
     const int64_t o = (int64_t)slot * md.n_pad + i;
@@ -533,7 +473,7 @@ __global__ __launch_bounds__(256) void k_admit(MixedDev md, const int* list, int
     if (md.loss != LOSS_LS) md.base1[o] = base1_cold[i];
     md.dU[o] = 0.f;
     md.dU[md.dU_ring + o] = 0.f;
-    md.gop[o] = 0;
+    md.gop[frag_index(slot, i, md.S_pad >> 5)] = 0;
   }
 }
 
@@ -546,9 +486,9 @@ void launch_admit(const MixedDev& md, const int* list, int nq, const double* H0_
 // Zero a slot's operand rows (retired or empty slots must not contribute to the products).
 __global__ __launch_bounds__(256) void k_slot_clear(MixedDev md, int slot) {
   for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < md.ldp; j += (int64_t)gridDim.x * 256)
-    md.dop[(int64_t)slot * md.ldp + j] = 0;
+    md.dop[frag_index(slot, j, md.S_pad >> 5)] = 0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < md.n_pad; i += (int64_t)gridDim.x * 256) {
-    md.gop[(int64_t)slot * md.n_pad + i] = 0;
+    md.gop[frag_index(slot, i, md.S_pad >> 5)] = 0;
     md.dU[(int64_t)slot * md.n_pad + i] = 0.f;
     md.dU[md.dU_ring + (int64_t)slot * md.n_pad + i] = 0.f;
   }
@@ -595,16 +535,15 @@ void launch_gemm_x(const MixedDev& md, hipStream_t s) {
   g.A = md.Xb;
   g.lda = md.ldp;
   g.B = md.dop;
-  g.ldb = md.ldp;
+  g.nb = md.S_pad / 32;
   g.M = md.n_pad;
   g.K = md.ldp;
   g.kchunk = md.x_kchunk;
   g.C = md.dUp;
   g.ldc = md.n_pad;
   g.c_split_stride = md.dUp_split;
-  g.c_ring_stride = 0;
   dim3 grid((unsigned)(md.n_pad / GT_M), (unsigned)(md.S_pad / GT_N), (unsigned)md.ksx);
-  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, g);
+  hipLaunchKernelGGL(k_gemm_bf16<0>, grid, dim3(256), 0, s, g);
 }
 
 void launch_gemm_xt(const MixedDev& md, hipStream_t s) {
@@ -612,16 +551,15 @@ void launch_gemm_xt(const MixedDev& md, hipStream_t s) {
   g.A = md.Xbt;
   g.lda = md.n_pad;
   g.B = md.gop;
-  g.ldb = md.n_pad;
+  g.nb = md.S_pad / 32;
   g.M = md.ldp;
   g.K = md.n_pad;
   g.kchunk = md.xt_kchunk;
   g.C = md.dH;
   g.ldc = md.ldp;
   g.c_split_stride = md.dH_split;
-  g.c_ring_stride = 0;
   dim3 grid((unsigned)(md.ldp / GT_M), (unsigned)(md.S_pad / GT_N), (unsigned)md.ksplit);
-  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, g);
+  hipLaunchKernelGGL(k_gemm_bf16<1>, grid, dim3(256), 0, s, g);
 }
 
 void launch_mixed_loss(const MixedDev& md, hipStream_t s) {
@@ -658,16 +596,46 @@ void launch_cycle_advance(const MixedDev& md, hipStream_t s) {
   hipLaunchKernelGGL(k_cycle_advance, dim3(1), dim3(64), 0, s, md.cycle);
 }
 
-void launch_gemm_f64(int xtype, const void* X, int64_t ldx, int64_t M, int64_t K, int trans,
-                     const double* B, int64_t ldb, int Q, double* C, int64_t ldc, hipStream_t s) {
-  dim3 grid((unsigned)((M + FT_M - 1) / FT_M), (unsigned)((Q + FT_Q - 1) / FT_Q));
-#define CGL_F64_CALL(T)                                                                          \
-  if (trans) hipLaunchKernelGGL((k_gemm_f64<T, 1>), grid, dim3(256), 0, s, (const T*)X, ldx, M, K, B, ldb, Q, C, ldc); \
-  else hipLaunchKernelGGL((k_gemm_f64<T, 0>), grid, dim3(256), 0, s, (const T*)X, ldx, M, K, B, ldb, Q, C, ldc);
+void launch_transpose(int xtype, const void* X, int64_t ldx, int64_t n, int64_t p, int64_t n_pad,
+                      void* Xt, hipStream_t s) {
+  dim3 grid((unsigned)((p + 31) / 32), (unsigned)((n_pad + 31) / 32));
+  if (xtype == XT_F64)
+    hipLaunchKernelGGL(k_transpose<double>, grid, dim3(256), 0, s, (const double*)X, ldx, n, p, n_pad, (double*)Xt);
+  else if (xtype == XT_F32)
+    hipLaunchKernelGGL(k_transpose<float>, grid, dim3(256), 0, s, (const float*)X, ldx, n, p, n_pad, (float*)Xt);
+  else
+    hipLaunchKernelGGL(k_transpose<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)X, ldx, n, p, n_pad, (uint16_t*)Xt);
+}
+
+void launch_gemm_f64(int xtype, const void* A, int64_t lda, int64_t M, int64_t K,
+                     const double* B, int64_t ldb, int Q, double* C, int64_t ldc, double* part,
+                     size_t part_cap, hipStream_t s) {
+  if (Q <= 0 || M <= 0) return;
+  // node tile: 32 when that pads Q no further than 16 would, else 16
+  const int nt = ((Q + 31) / 32 * 32 == (Q + 15) / 16 * 16) ? 2 : 1;
+  const int64_t mblocks = (M + 127) / 128;
+  const int64_t qblocks = (Q + 16 * nt - 1) / (16 * nt);
+  const int64_t steps = std::max<int64_t>(1, (K + 15) / 16);
+  // split K until there are about 4 workgroups per compute unit, each chunk >= 32 steps
+  int64_t ks = (1024 + mblocks * qblocks - 1) / (mblocks * qblocks);
+  ks = std::min<int64_t>(ks, std::max<int64_t>(1, steps / 32));
+  ks = std::min<int64_t>(ks, (int64_t)(part_cap / ((size_t)Q * M * sizeof(double))));
+  ks = std::max<int64_t>(ks, 1);
+  const int64_t chunk = (steps + ks - 1) / ks * 16;
+  ks = std::max<int64_t>(1, (K + chunk - 1) / chunk);
+  F64GemmArgs g{A, lda, B, ldb, M, K, Q, chunk, ks > 1 ? part : C, ks > 1 ? M : ldc};
+  dim3 grid((unsigned)mblocks, (unsigned)qblocks, (unsigned)ks);
+#define CGL_F64_CALL(T)                                                            \
+  if (nt == 2) hipLaunchKernelGGL((k_gemm_f64<T, 2>), grid, dim3(256), 0, s, g); \
+  else hipLaunchKernelGGL((k_gemm_f64<T, 1>), grid, dim3(256), 0, s, g);
   if (xtype == XT_F64) { CGL_F64_CALL(double) }
   else if (xtype == XT_F32) { CGL_F64_CALL(float) }
   else { CGL_F64_CALL(uint16_t) }
 #undef CGL_F64_CALL
+  if (ks > 1) {
+    dim3 rg((unsigned)std::min<int64_t>((M + 255) / 256, 64), (unsigned)Q);
+    hipLaunchKernelGGL(k_gemm_f64_reduce, rg, dim3(256), 0, s, part, (int)ks, Q, M, C, ldc);
+  }
 }
 
 void launch_cert_gather(const MixedDev& md, const int* list, int nq, double* B64, hipStream_t s) {

@@ -58,8 +58,14 @@ void launch_mixed_restart(const MixedDev& md, hipStream_t s);
 void launch_mixed_resid(const MixedDev& md, hipStream_t s);
 void launch_mixed_node(const MixedDev& md, hipStream_t s);
 void launch_cycle_advance(const MixedDev& md, hipStream_t s);
-void launch_gemm_f64(int xtype, const void* X, int64_t ldx, int64_t M, int64_t K, int trans,
-                     const double* B, int64_t ldb, int Q, double* C, int64_t ldc, hipStream_t s);
+// C[q][m] = sum_k A[m][k] B[q][k] in FP64 (A row-major in the design's stored precision);
+// part: split-K scratch of part_cap bytes (the split is limited to what fits).
+void launch_gemm_f64(int xtype, const void* A, int64_t lda, int64_t M, int64_t K,
+                     const double* B, int64_t ldb, int Q, double* C, int64_t ldc, double* part,
+                     size_t part_cap, hipStream_t s);
+// Xt (p x n_pad) = X^T in the stored precision, zero in columns n .. n_pad.
+void launch_transpose(int xtype, const void* X, int64_t ldx, int64_t n, int64_t p, int64_t n_pad,
+                      void* Xt, hipStream_t s);
 void launch_cert_gather(const MixedDev& md, const int* list, int nq, double* B64, hipStream_t s);
 void launch_cert_resid(const MixedDev& md, const int* list, int nq, const double* U64,
                        double* R64, double* part, int nchunk, int64_t chunk, hipStream_t s);

@@ -200,45 +200,57 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
   const uint8_t* cl = md.cls + (int64_t)slot * md.ldp;
   const double c = st->c;
   const double invL = 1.0 / md.L;
-  double wr[E], hg[E], b1[E];
-  uint8_t cr[E];
-#pragma unroll
-  for (int s = 0; s < E; ++s) {
-    const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
-    if (j < p) {
-      double h = H0[j];
-      for (int q = 0; q < md.ksplit; ++q)
-        h += (double)md.dH[(int64_t)q * md.dH_split + (int64_t)slot * md.ldp + j];
-      const double x1 = bt1[j];
-      const double gam = x1 + c * (x1 - bt0[j]);
-      hg[s] = h;
-      b1[s] = x1;
-      wr[s] = gam - h * invL;
-      cr[s] = cl[j];
-    } else {
-      hg[s] = 0.0; b1[s] = 0.0; wr[s] = 0.0; cr[s] = CLS_PAD;
-    }
-  }
-  double br[E];
-  const ProxOut po = node_prox<E>(wr, cr, st->kp, st->nfree, md.rho, md.M, st->vstar, br, sm);
-#pragma unroll
-  for (int s = 0; s < E; ++s) {
-    const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
-    if (j < p) {
-      bout[j] = br[s];
-      md.dop[frag_index(slot, j, md.S_pad >> 5)] = float_to_bf16((float)(br[s] - b0[j]));
-    }
-  }
-  // dual monitor at gamma: D = -F*(-zeta) - 2 lambda2 g_node*(-grad F(gamma) / (2 lambda2))
   const int iter = st->iter;
   const bool check = (iter % st->check_every) == 0;
-  double gs = 0.0;
-  if (check) {
-    double a[E];
+  // H at gamma (FP64 base + BF16-product corrections) into the per-thread value slice
+  __shared__ double vbuf[ProxVals<E>::lds ? E * kProxThreads : 1];
+  ProxVals<E> pv;
+  pv.sl = vbuf;
+  uint64_t cb = 0;
 #pragma unroll
-    for (int s = 0; s < E; ++s) a[s] = -hg[s] / (2.0 * md.lam2);
-    gs = gstar_node<E>(a, cr, st->kp, st->nfree, md.M, sm);
+  for (int s = 0; s < E; ++s) {
+    const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
+    double h = 0.0;
+    int cs = CLS_PAD;
+    if (j < p) {
+      h = H0[j];
+      for (int q = 0; q < md.ksplit; ++q)
+        h += (double)md.dH[(int64_t)q * md.dH_split + (int64_t)slot * md.ldp + j];
+      cs = cl[j];
+    }
+    pv.set(s, h);
+    cb |= (uint64_t)cs << (2 * s);
   }
+  // dual monitor at gamma: D = -F*(-zeta) - 2 lambda2 g_node*(-grad F(gamma) / (2 lambda2))
+  double gs = 0.0;
+  if (check)
+    gs = gstar_node<E>([&](int s) { return fabs(pv.get(s)); }, 2.0 * md.lam2, cb, st->kp,
+                       st->nfree, md.M, sm);
+  // gradient step w = gamma - H / L; the slice then holds u = rho |w|, the signs a mask
+  uint32_t neg = 0;
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
+    double w = 0.0;
+    if (j < p) {
+      const double x1 = bt1[j];
+      const double gam = x1 + c * (x1 - bt0[j]);
+      w = gam - pv.get(s) * invL;
+    }
+    neg |= (w < 0.0 ? 1u : 0u) << s;
+    pv.set(s, md.rho * fabs(w));
+  }
+  const int64_t nbk = md.S_pad >> 5;
+  const ProxOut po = node_prox<E>(
+      [&](int s) { return pv.get(s); }, neg, cb, st->kp, st->nfree, md.rho, md.M, st->vstar,
+      [&](int s, double b) {
+        const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
+        if (j < p) {
+          bout[j] = b;
+          md.dop[frag_index(slot, j, nbk)] = float_to_bf16((float)(b - b0[j]));
+        }
+      },
+      sm);
   double fs = 0.0;
   if (check) {
     for (int i = threadIdx.x; i < md.nrt; i += blockDim.x)
@@ -375,20 +387,23 @@ __global__ __launch_bounds__(1024) void k_cert_finish(MixedDev md, const int* li
   NodeDev* st = md.st + slot;
   const int64_t p = md.p;
   const uint8_t* cl = md.cls + (int64_t)slot * md.ldp;
-  double a[E];
-  uint8_t cr[E];
+  __shared__ double vbuf[ProxVals<E>::lds ? E * kProxThreads : 1];
+  ProxVals<E> hv;
+  hv.sl = vbuf;
+  uint64_t cb = 0;
 #pragma unroll
   for (int s = 0; s < E; ++s) {
     const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
     if (j < p) {
-      a[s] = -H64[(int64_t)q * md.ldp + j] / (2.0 * md.lam2);
-      cr[s] = cl[j];
+      hv.set(s, fabs(H64[(int64_t)q * md.ldp + j]));
+      cb |= (uint64_t)cl[j] << (2 * s);
     } else {
-      a[s] = 0.0;
-      cr[s] = CLS_PAD;
+      hv.set(s, 0.0);
+      cb |= (uint64_t)CLS_PAD << (2 * s);
     }
   }
-  const double gs = gstar_node<E>(a, cr, st->kp, st->nfree, md.M, sm);
+  const double gs = gstar_node<E>([&](int s) { return hv.get(s); }, 2.0 * md.lam2, cb, st->kp,
+                                  st->nfree, md.M, sm);
   double acc[2] = {0.0, 0.0};
   for (int i = threadIdx.x; i < nchunk; i += blockDim.x) {
     acc[0] += part[((int64_t)q * nchunk + i) * 2];

@@ -296,33 +296,39 @@ __global__ __launch_bounds__(1024) void k_prox(const double* __restrict__ w, int
   const int iter = st->iter;
   const double* wn = w + (int64_t)node * w_ld;
   const uint8_t* cls_n = cls_all + (int64_t)node * cls_ld;
-  double wr[E];
-  uint8_t cr[E];
+  __shared__ double vbuf[ProxVals<E>::lds ? E * kProxThreads : 1];
+  ProxVals<E> pv;
+  pv.sl = vbuf;
+  uint64_t cb = 0;
+  uint32_t neg = 0;
 #pragma unroll
   for (int s = 0; s < E; ++s) {
     const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
-    if (j < p) { wr[s] = wn[j]; cr[s] = cls_n[j]; }
-    else { wr[s] = 0.0; cr[s] = CLS_PAD; }
+    double w = 0.0;
+    int cs = CLS_PAD;
+    if (j < p) { w = wn[j]; cs = cls_n[j]; }
+    neg |= (w < 0.0 ? 1u : 0u) << s;
+    pv.set(s, rho * fabs(w));
+    cb |= (uint64_t)cs << (2 * s);
   }
-  double br[E];
-  const ProxOut po = node_prox<E>(wr, cr, st->kp, st->nfree, rho, M, st->vstar, br, sm);
   double* bout = slot_ptr(b_base + (int64_t)node * b_node_stride, b_stride, iter, 1);
-#pragma unroll
-  for (int s = 0; s < E; ++s) {
-    const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
-    if (j < p) bout[j] = br[s];
-  }
+  const ProxOut po = node_prox<E>(
+      [&](int s) { return pv.get(s); }, neg, cb, st->kp, st->nfree, rho, M, st->vstar,
+      [&](int s, double b) {
+        const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
+        if (j < p) bout[j] = b;
+      },
+      sm);
   const bool check = ((iter % st->check_every) == 0) || (iter >= st->max_iter);
   double gs = 0.0;
   if (check && h != nullptr) {
     const double* hn = h + (int64_t)node * h_ld;
-    double a[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) {
       const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
-      a[s] = (j < p) ? -hn[j] / two_l2 : 0.0;
+      pv.set(s, (j < p) ? fabs(hn[j]) : 0.0);
     }
-    gs = gstar_node<E>(a, cr, st->kp, st->nfree, M, sm);
+    gs = gstar_node<E>([&](int s) { return pv.get(s); }, two_l2, cb, st->kp, st->nfree, M, sm);
   }
   if (threadIdx.x == 0) {
     st->g_new = po.gval;
@@ -579,27 +585,29 @@ __global__ __launch_bounds__(1024) void k_g_gstar(const double* __restrict__ bet
   const NodeDev* st = st_all + node;
   const int kp = st->kp, nfree = st->nfree;
   const uint8_t* cl = cls_all + (int64_t)node * cls_ld;
-  double b[E], a[E];
-  uint8_t cr[E];
-  bool freeb[E];
-  uint64_t key[E];
+  // |beta| first (Alg. 2), then |h| (the conjugate) in the per-thread value slice
+  __shared__ double vbuf[ProxVals<E>::lds ? E * kProxThreads : 1];
+  ProxVals<E> pv;
+  pv.sl = vbuf;
+  uint64_t cb = 0;
+  uint32_t fm = 0;
   double absF = 0.0, sq1 = 0.0, mx = 0.0;
   int bad = 0;
 #pragma unroll
   for (int s = 0; s < E; ++s) {
     const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
+    int c = CLS_PAD;
+    double bj = 0.0;
     if (j < p) {
-      b[s] = beta[(int64_t)node * b_ld + j];
-      a[s] = -h[(int64_t)node * h_ld + j] / two_l2;
-      cr[s] = cl[j];
-    } else {
-      b[s] = 0.0; a[s] = 0.0; cr[s] = CLS_PAD;
+      bj = beta[(int64_t)node * b_ld + j];
+      c = cl[j];
     }
-    freeb[s] = cr[s] == CLS_FREE;
-    key[s] = dbits(fabs(b[s]));
-    if (cr[s] == CLS_ZERO && b[s] != 0.0) bad = 1;
-    if (cr[s] == CLS_ONE) { sq1 += b[s] * b[s]; if (fabs(b[s]) > M * (1.0 + 1e-12)) bad = 1; }
-    if (freeb[s]) { absF += fabs(b[s]); mx = fmax(mx, fabs(b[s])); }
+    pv.set(s, fabs(bj));
+    cb |= (uint64_t)c << (2 * s);
+    if (c == CLS_FREE) fm |= 1u << s;
+    if (c == CLS_ZERO && bj != 0.0) bad = 1;
+    if (c == CLS_ONE) { sq1 += bj * bj; if (fabs(bj) > M * (1.0 + 1e-12)) bad = 1; }
+    if (c == CLS_FREE) { absF += fabs(bj); mx = fmax(mx, fabs(bj)); }
   }
   absF = bsum(absF, sm);
   sq1 = bsum(sq1, sm);
@@ -613,20 +621,22 @@ __global__ __launch_bounds__(1024) void k_g_gstar(const double* __restrict__ bet
     if (kp >= nfree) {
       double sq = 0.0;
 #pragma unroll
-      for (int s = 0; s < E; ++s) if (freeb[s]) sq += b[s] * b[s];
+      for (int s = 0; s < E; ++s) if ((fm >> s) & 1u) sq += pv.get(s) * pv.get(s);
       g = 0.5 * bsum(sq, sm);
     } else {
       // top-kp magnitudes of beta_F, sorted decreasingly, then Alg. 2
-      const Select sel = radix_select_desc<E>(key, freeb, kp, sm);
+      auto K = [&](int s) { return dbits(pv.get(s)); };
+      const Select sel = radix_select_desc<E>(K, fm, kp, sm);
       if (threadIdx.x == 0) { sm.head_fill = 0; sm.ties_left = sel.exact ? sel.take : 0; }
       __syncthreads();
 #pragma unroll
       for (int s = 0; s < E; ++s) {
-        if (!freeb[s]) continue;
-        bool hsel = !sel.exact ? key[s] >= sel.lo
-                               : (key[s] > sel.lo || (key[s] == sel.lo &&
-                                                      atomicSub(&sm.ties_left, 1) > 0));
-        if (hsel) sm.hu[atomicAdd(&sm.head_fill, 1)] = fabs(b[s]);
+        if (!((fm >> s) & 1u)) continue;
+        const uint64_t ks = K(s);
+        bool hsel = !sel.exact ? ks >= sel.lo
+                               : (ks > sel.lo || (ks == sel.lo &&
+                                                  atomicSub(&sm.ties_left, 1) > 0));
+        if (hsel) sm.hu[atomicAdd(&sm.head_fill, 1)] = pv.get(s);
       }
       __syncthreads();
       sort_head_desc(kp, sm);
@@ -635,8 +645,13 @@ __global__ __launch_bounds__(1024) void k_g_gstar(const double* __restrict__ bet
       g = sm.b_dbl[3];
     }
   }
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
+    pv.set(s, (j < p) ? fabs(h[(int64_t)node * h_ld + j]) : 0.0);
+  }
   const double gn = 0.5 * sq1 + g;
-  const double gs = gstar_node<E>(a, cr, kp, nfree, M, sm);
+  const double gs = gstar_node<E>([&](int s) { return pv.get(s); }, two_l2, cb, kp, nfree, M, sm);
   if (threadIdx.x == 0) {
     out[2 * node] = gn;
     out[2 * node + 1] = gs;

@@ -49,6 +49,7 @@ struct ProxSmem {
   double cand_v[kProxWaves * kWaveSel];  // per-wave winners
   int cand_i[kProxWaves * kWaveSel];
   double hu[kMaxHead + 1];  // sorted head u values; hu[k'] = largest tail value
+  double hb[kMaxHead];      // head breakpoints huber_prox(rho, hu_i, M)
   int hidx[kMaxHead + 1];
   double tmp[kMaxHead];
   double redd[kProxWaves * 4];
@@ -114,37 +115,46 @@ __device__ __forceinline__ T wave_suffix_incl(T v) {
 
 // Wave-wide argmax of (value, index): larger value wins, ties go to the smaller index. Every
 // lane receives the winner.
-__device__ __forceinline__ void wave_argmax(double& v, int& i) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ov = __shfl_xor(v, off, kWave);
-    const int oi = __shfl_xor(i, off, kWave);
-    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+struct ArgMax {
+  double v;
+  int i;
+  int pad;
+};
+struct OpArgMax {
+  __device__ __forceinline__ ArgMax operator()(ArgMax a, ArgMax b) const {
+    return (b.v > a.v || (b.v == a.v && b.i < a.i)) ? b : a;
   }
+};
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+  const ArgMax r = wave_reduce(ArgMax{v, i, 0}, ArgMax{-HUGE_VAL, INT_MAX, 0}, OpArgMax());
+  v = r.v;
+  i = r.i;
 }
 
 // The K largest active keys (K <= kWaveSel, K <= number of active keys), sorted decreasingly
-// (ties: smaller index first), into sm.hu[0..K) / sm.hidx[0..K). Element s of thread t has index
-// s * kProxThreads + t.
-template <int E>
-__device__ void block_topk(const double (&key)[E], const bool (&act)[E], int K, ProxSmem& sm) {
+// (ties: smaller index first), into sm.hu[0..K) / sm.hidx[0..K). key(s) is the key of this
+// thread's element s (index s * kProxThreads + tid), act bit s whether it takes part; keys are
+// recomputed from the caller's registers on every scan instead of being held in another array.
+template <int E, typename KeyF>
+__device__ void block_topk(KeyF key, uint32_t act, int K, ProxSmem& sm) {
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  uint32_t taken = 0;
+  uint32_t avail = act;
   for (int r = 0; r < K; ++r) {
     double bv = -1.0;  // keys are >= 0
     int bi = INT_MAX;
 #pragma unroll
     for (int s = 0; s < E; ++s) {
-      const int j = s * kProxThreads + (int)threadIdx.x;
-      if (act[s] && !((taken >> s) & 1u) && (key[s] > bv || (key[s] == bv && j < bi))) {
-        bv = key[s];
-        bi = j;
+      const double ks = key(s);
+      // elements are visited in increasing index, so a strict > keeps the smaller index on ties
+      if (((avail >> s) & 1u) && ks > bv) {
+        bv = ks;
+        bi = s * kProxThreads + (int)threadIdx.x;
       }
     }
     wave_argmax(bv, bi);
     if (bi != INT_MAX && (bi & (kProxThreads - 1)) == (int)threadIdx.x)
-      taken |= 1u << (bi / kProxThreads);
+      avail &= ~(1u << (bi / kProxThreads));
     if (lane == 0) {
       sm.cand_v[wid * kWaveSel + r] = bv;
       sm.cand_i[wid * kWaveSel + r] = bi;
@@ -152,42 +162,33 @@ __device__ void block_topk(const double (&key)[E], const bool (&act)[E], int K, 
   }
   __syncthreads();
   if (wid == 0) {
-    // lane l holds the candidates of waves l / 4 ... : slot q covers wave (q * 4 + l / 16)
-    // simpler: candidate c = q * 64 + lane over the flattened list of kProxWaves * K entries
-    const int total = kProxWaves * K;
-    double cv[kProxWaves];
-    int ci[kProxWaves];
-#pragma unroll
-    for (int q = 0; q < kProxWaves; ++q) {
-      const int c = q * 64 + lane;
-      if (c < total) {
-        const int w = c / K, r = c % K;
-        cv[q] = sm.cand_v[w * kWaveSel + r];
-        ci[q] = sm.cand_i[w * kWaveSel + r];
-      } else {
-        cv[q] = -1.0;
-        ci[q] = INT_MAX;
-      }
+    // each wave's K candidates are sorted (value desc, index asc): merge the kProxWaves lists,
+    // lane q holding the current head of list q (element indices are unique across waves)
+    const int q = lane;
+    int pos = 0;
+    double hv = -1.0;
+    int hi = INT_MAX;
+    if (q < kProxWaves) {
+      hv = sm.cand_v[q * kWaveSel];
+      hi = sm.cand_i[q * kWaveSel];
     }
-    uint32_t tk = 0;
     for (int r = 0; r < K; ++r) {
-      double bv = -1.0;
-      int bi = INT_MAX, bq = -1;
-#pragma unroll
-      for (int q = 0; q < kProxWaves; ++q) {
-        if (!((tk >> q) & 1u) && (cv[q] > bv || (cv[q] == bv && ci[q] < bi))) {
-          bv = cv[q];
-          bi = ci[q];
-          bq = q;
-        }
-      }
-      double wv = bv;
-      int wi = bi;
+      double wv = hv;
+      int wi = hi;
       wave_argmax(wv, wi);
-      if (bq >= 0 && bi == wi && wi != INT_MAX) tk |= 1u << bq;
       if (lane == 0) {
         sm.hu[r] = wv;
         sm.hidx[r] = wi;
+      }
+      if (q < kProxWaves && wi != INT_MAX && hi == wi) {
+        ++pos;
+        if (pos < K) {
+          hv = sm.cand_v[q * kWaveSel + pos];
+          hi = sm.cand_i[q * kWaveSel + pos];
+        } else {
+          hv = -1.0;
+          hi = INT_MAX;
+        }
       }
     }
   }
@@ -203,13 +204,12 @@ struct Select {
 };
 
 // need-th largest among active keys (1 <= need <= number of active keys). Byte-wise radix.
-template <int E>
-__device__ Select radix_select_desc(const uint64_t (&key)[E], const bool (&act)[E], int need,
-                                    ProxSmem& sm) {
+template <int E, typename KeyF>
+__device__ Select radix_select_desc(KeyF key, uint32_t act, int need, ProxSmem& sm) {
   uint64_t o = 0, a = ~(uint64_t)0;
 #pragma unroll
   for (int s = 0; s < E; ++s)
-    if (act[s]) { o |= key[s]; a &= key[s]; }
+    if ((act >> s) & 1u) { o |= key(s); a &= key(s); }
   o = bor(o, sm);
   a = band(a, sm);
   const uint64_t diff = o ^ a;
@@ -225,8 +225,9 @@ __device__ Select radix_select_desc(const uint64_t (&key)[E], const bool (&act)[
     const int hs = shift + 8;
 #pragma unroll
     for (int s = 0; s < E; ++s) {
-      if (act[s] && (hs >= 64 || (key[s] >> hs) == (prefix >> hs)))
-        atomicAdd(&sm.cnt[(key[s] >> shift) & 255], 1u);
+      const uint64_t ks = key(s);
+      if (((act >> s) & 1u) && (hs >= 64 || (ks >> hs) == (prefix >> hs)))
+        atomicAdd(&sm.cnt[(ks >> shift) & 255], 1u);
     }
     __syncthreads();
     if (threadIdx.x < 64) {
@@ -244,8 +245,7 @@ __device__ Select radix_select_desc(const uint64_t (&key)[E], const bool (&act)[
         run = incl;
       }
       int cand = best;  // highest bin whose suffix count reaches `remaining`
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) cand = max(cand, __shfl_xor(cand, off, kWave));
+      cand = wave_reduce(cand, INT_MIN, OpMax());
       if (best == cand && best >= 0) {
         sm.b_int[0] = best;
         sm.b_int[1] = above;
@@ -294,15 +294,16 @@ __device__ __forceinline__ double head_part(const double* hu, int kh, double v, 
 }
 
 // Root of psi(v) = H(v) - (S - m v) on [vlo, inf) (psi increasing, psi(vlo) <= 0). Breakpoints
-// of H: huber_prox(rho, hu_i, M) and M. Every wave evaluates it (no barrier needed).
-__device__ double psi_root(const double* hu, int kh, double vlo, double m, double S, double rho,
-                           double M) {
+// of H: hb_i = huber_prox(rho, hu_i, M) (precomputed) and M. Every wave evaluates it (no
+// barrier needed).
+__device__ double psi_root(const double* hu, const double* hb, int kh, double vlo, double m,
+                           double S, double rho, double M) {
   const int lane = threadIdx.x & 63;
   double a = vlo, b = HUGE_VAL;
   for (int base = 0; base <= kh; base += 64) {
     const int i = base + lane;
     if (i <= kh) {
-      const double pt = (i < kh) ? huber_prox(rho, hu[i], M) : M;
+      const double pt = (i < kh) ? hb[i] : M;
       if (pt > vlo) {
         const double ps = head_part(hu, kh, pt, rho, M) - (S - m * pt);
         if (ps <= 0.0) a = fmax(a, pt);
@@ -310,16 +311,13 @@ __device__ double psi_root(const double* hu, int kh, double vlo, double m, doubl
       }
     }
   }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    a = fmax(a, __shfl_xor(a, off, kWave));
-    b = fmin(b, __shfl_xor(b, off, kWave));
-  }
+  a = wave_reduce(a, -HUGE_VAL, OpMax());
+  b = wave_reduce(b, HUGE_VAL, OpMin());
   // membership of the head and the regime of min(v, M) are constant on (a, b)
   const double mid = isinf(b) ? a + fmax(1.0, fabs(a)) : 0.5 * (a + b);
   double nh = 0.0, sh = 0.0;
   for (int i = 0; i < kh; ++i) {
-    if (huber_prox(rho, hu[i], M) < mid) { nh += 1.0; sh += hu[i]; }
+    if (hb[i] < mid) { nh += 1.0; sh += hu[i]; }
   }
   double v;
   if (mid <= M) {
@@ -333,9 +331,9 @@ __device__ double psi_root(const double* hu, int kh, double vlo, double m, doubl
 }
 
 // v* over the tail (see the file comment). hu[0..kh): sorted head values. v0: a hint.
-template <int E>
-__device__ double tail_root(const double (&u)[E], const bool (&tail)[E], const double* hu,
-                           int kh, double v0, double rho, double M, ProxSmem& sm) {
+template <int E, typename UF>
+__device__ double tail_root(UF u, uint32_t tail, const double* hu, const double* hb, int kh,
+                           double v0, double rho, double M, ProxSmem& sm) {
   double v = v0 > 0.0 ? v0 : 0.0;
   double m_prev = -1.0;
   bool checked_start = v == 0.0;
@@ -343,7 +341,8 @@ __device__ double tail_root(const double (&u)[E], const bool (&tail)[E], const d
     double acc[2] = {0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < E; ++s) {
-      if (tail[s] && u[s] > v) { acc[0] += 1.0; acc[1] += u[s]; }
+      const double us = u(s);
+      if (((tail >> s) & 1u) && us > v) { acc[0] += 1.0; acc[1] += us; }
     }
     block_sum_n<2>(acc, sm);
     const double m = acc[0], S = acc[1];
@@ -353,12 +352,12 @@ __device__ double tail_root(const double (&u)[E], const bool (&tail)[E], const d
         // hint above v*: the members at the hint are a subset of those at any v below it, so
         // the root with this set fixed, searched from 0, is a lower bound on v* (and close to it
         // when the hint is)
-        v = psi_root(hu, kh, 0.0, m, S, rho, M);
+        v = psi_root(hu, hb, kh, 0.0, m, S, rho, M);
         continue;
       }
     }
     if (m == m_prev) break;  // the member set did not change: v is the root
-    v = psi_root(hu, kh, v, m, S, rho, M);
+    v = psi_root(hu, hb, kh, v, m, S, rho, M);
     m_prev = m;
   }
   return v;
@@ -386,158 +385,183 @@ struct ProxOut {
   double vstar;  // pooled value (warm start of the next call)
 };
 
-// Node prox in registers. w: element s of this thread is index j = s * kProxThreads + tid.
-// cls: CLS_*; kp = k - |Z1| (>= 0); nfree = |F|; vhint: previous v* (0 if none).
+// Class codes of a thread's E elements, 2 bits each (element s at bits 2s, 2s + 1).
+__device__ __forceinline__ int cls_at(uint64_t cb, int s) { return (int)((cb >> (2 * s)) & 3u); }
 template <int E>
-__device__ ProxOut node_prox(const double (&w)[E], const uint8_t (&cls)[E], int kp, int nfree,
-                             double rho, double M, double vhint, double (&beta)[E],
-                             ProxSmem& sm) {
-  double u[E];
-  bool freeb[E];
-  double z1sq = 0.0;
+__device__ __forceinline__ uint32_t cls_mask(uint64_t cb, int c) {
+  uint32_t m = 0;
 #pragma unroll
-  for (int s = 0; s < E; ++s) {
-    u[s] = rho * fabs(w[s]);
-    freeb[s] = cls[s] == CLS_FREE;
-    beta[s] = 0.0;
-    if (cls[s] == CLS_ONE) {
-      double b = rho * w[s] / (1.0 + rho);
-      b = fmin(fmax(b, -M), M);
-      beta[s] = b;
-      z1sq += b * b;
-    }
-  }
-  ProxOut out;
-  out.vstar = 0.0;
-  if (kp <= 0 || nfree == 0) {  // F pinned to zero (no budget left) or empty
-    out.gval = 0.5 * bsum(z1sq, sm);
-    return out;
-  }
-  if (kp >= nfree) {  // every free coordinate can take z = 1: ridge-and-clip, g = 1/2 ||beta||^2
-    double sq = z1sq;
+  for (int s = 0; s < E; ++s) m |= (cls_at(cb, s) == c ? 1u : 0u) << s;
+  return m;
+}
+
+// Node prox. U(s): u = rho |w| of this thread's element s (index s * kProxThreads + tid), read
+// from wherever the caller keeps it (registers, or a per-thread LDS slice); neg bit s: w < 0.
+// cb: packed class codes (CLS_*); kp = k - |Z1| (>= 0); nfree = |F|; vhint: previous v* (0 if
+// none). The result is handed to out(s, beta_s) once, element by element, at the end.
+template <int E, typename UF, typename OutF>
+__device__ ProxOut node_prox(UF U, uint32_t neg, uint64_t cb, int kp, int nfree, double rho,
+                             double M, double vhint, OutF out, ProxSmem& sm) {
+  const uint32_t fm = cls_mask<E>(cb, CLS_FREE);
+  auto sgn = [&](int s, double mag) { return ((neg >> s) & 1u) ? -mag : mag; };
+  // Z1 coordinates: ridge-and-clip rho w / (1 + rho) clipped to [-M, M]
+  auto z1beta = [&](int s) { return sgn(s, fmin(U(s) / (1.0 + rho), M)); };
+  ProxOut res;
+  res.vstar = 0.0;
+  if (kp <= 0 || nfree == 0 || kp >= nfree) {
+    // F pinned to zero (no budget left) or empty; or every free coordinate can take z = 1
+    // (ridge-and-clip, g = 1/2 ||beta||^2)
+    const bool all_in = kp > 0 && nfree > 0;
+    double sq = 0.0;
 #pragma unroll
     for (int s = 0; s < E; ++s) {
-      if (freeb[s] && w[s] != 0.0) {
-        const double b = copysign(fmin(u[s] / (1.0 + rho), M), w[s]);
-        beta[s] = b;
-        sq += b * b;
-      }
+      const int c = cls_at(cb, s);
+      double b = 0.0;
+      if (c == CLS_ONE || (c == CLS_FREE && all_in)) b = z1beta(s);
+      out(s, b);
+      sq += b * b;
     }
-    out.gval = 0.5 * bsum(sq, sm);
-    return out;
+    res.gval = 0.5 * bsum(sq, sm);
+    return res;
   }
   // ---- head: the kp largest u over F (sorted into sm.hu), and the largest tail value
-  bool head[E];
+  uint32_t head = 0;
   double umax_tail;
   if (kp + 1 <= kWaveSel) {
-    block_topk<E>(u, freeb, kp + 1, sm);
+    block_topk<E>(U, fm, kp + 1, sm);
     const double tv = sm.hu[kp - 1];
     const int ti = sm.hidx[kp - 1];
 #pragma unroll
     for (int s = 0; s < E; ++s) {
       const int j = s * kProxThreads + (int)threadIdx.x;
-      head[s] = freeb[s] && (u[s] > tv || (u[s] == tv && j <= ti));
+      const double us = U(s);
+      head |= (((fm >> s) & 1u) && (us > tv || (us == tv && j <= ti)) ? 1u : 0u) << s;
     }
     umax_tail = sm.hu[kp];
   } else {
-    uint64_t key[E];
-#pragma unroll
-    for (int s = 0; s < E; ++s) key[s] = dbits(u[s]);
-    const Select sel = radix_select_desc<E>(key, freeb, kp, sm);
+    auto K = [&](int s) { return dbits(U(s)); };
+    const Select sel = radix_select_desc<E>(K, fm, kp, sm);
     if (threadIdx.x == 0) { sm.head_fill = 0; sm.ties_left = sel.exact ? sel.take : 0; }
     __syncthreads();
     double tmax = -1.0;
 #pragma unroll
     for (int s = 0; s < E; ++s) {
-      bool h = false;
-      if (freeb[s]) {
-        if (!sel.exact) h = key[s] >= sel.lo;
-        else if (key[s] > sel.lo) h = true;
-        else if (key[s] == sel.lo) h = atomicSub(&sm.ties_left, 1) > 0;
+      if (!((fm >> s) & 1u)) continue;
+      const uint64_t ks = K(s);
+      bool h;
+      if (!sel.exact) h = ks >= sel.lo;
+      else if (ks > sel.lo) h = true;
+      else if (ks == sel.lo) h = atomicSub(&sm.ties_left, 1) > 0;
+      else h = false;
+      if (h) {
+        head |= 1u << s;
+        sm.hu[atomicAdd(&sm.head_fill, 1)] = U(s);
+      } else {
+        tmax = fmax(tmax, U(s));
       }
-      head[s] = h;
-      if (h) sm.hu[atomicAdd(&sm.head_fill, 1)] = u[s];
-      else if (freeb[s]) tmax = fmax(tmax, u[s]);
     }
     __syncthreads();
     sort_head_desc(kp, sm);
     umax_tail = bmax(tmax, sm);
   }
-  // ---- v*
-  bool tail[E];
-#pragma unroll
-  for (int s = 0; s < E; ++s) tail[s] = freeb[s] && !head[s];
+  // ---- v*: head breakpoints huber_prox(rho, hu_i, M) once, then the root search
+  for (int i = threadIdx.x; i < kp; i += blockDim.x) sm.hb[i] = huber_prox(rho, sm.hu[i], M);
+  __syncthreads();
+  const uint32_t tail = fm & ~head;
   double vstar;
-  if (huber_prox(rho, sm.hu[kp - 1], M) >= umax_tail) {
+  if (sm.hb[kp - 1] >= umax_tail) {
     vstar = umax_tail;  // no isotonic violation at the junction: no pooled block
   } else {
-    vstar = tail_root<E>(u, tail, sm.hu, kp, vhint, rho, M, sm);
+    vstar = tail_root<E>(U, tail, sm.hu, sm.hb, kp, vhint, rho, M, sm);
   }
-  out.vstar = vstar;
+  res.vstar = vstar;
   // ---- assemble beta; |beta_F| total and Z1 squares in one reduction
-  double acc[2] = {0.0, z1sq};
+  double acc[2] = {0.0, 0.0};
 #pragma unroll
   for (int s = 0; s < E; ++s) {
-    if (freeb[s]) {
-      const double c = head[s] ? huber_prox(rho, u[s], M) : 0.0;
-      const double t = u[s] - fmax(c, vstar);
+    double b = 0.0;
+    if ((fm >> s) & 1u) {
+      const double us = U(s);
+      const double c = ((head >> s) & 1u) ? huber_prox(rho, us, M) : 0.0;
+      const double t = us - fmax(c, vstar);
       const double mag = t > 0.0 ? t / rho : 0.0;
-      beta[s] = mag > 0.0 ? copysign(mag, w[s]) : 0.0;
+      b = mag > 0.0 ? sgn(s, mag) : 0.0;
       acc[0] += mag;
+    } else if (cls_at(cb, s) == CLS_ONE) {
+      b = z1beta(s);
+      acc[1] += b * b;
     }
+    out(s, b);
   }
   // head magnitudes in sorted order (|beta| is monotone in u)
   for (int i = threadIdx.x; i < kp; i += blockDim.x) {
     const double uh = sm.hu[i];
-    const double t = uh - fmax(huber_prox(rho, uh, M), vstar);
+    const double t = uh - fmax(sm.hb[i], vstar);
     sm.tmp[i] = t > 0.0 ? t / rho : 0.0;
   }
   block_sum_n<2>(acc, sm);
   if (threadIdx.x == 0) sm.b_dbl[3] = alg2_from_sorted(sm.tmp, kp, kp, acc[0]);
   __syncthreads();
-  out.gval = 0.5 * acc[1] + sm.b_dbl[3];
+  res.gval = 0.5 * acc[1] + sm.b_dbl[3];
   __syncthreads();
-  return out;
+  return res;
 }
 
-// g_node*(a) = sum_{Z1} H_M(a_j) + TopSum_{kp}(H_M(a_F))  (Lemma 2, separable sum rule).
-template <int E>
-__device__ double gstar_node(const double (&a)[E], const uint8_t (&cls)[E], int kp, int nfree,
-                             double M, ProxSmem& sm) {
+// g_node*(a) = sum_{Z1} H_M(a_j) + TopSum_{kp}(H_M(a_F))  (Lemma 2, separable sum rule), with
+// |a_j| = A(j) / div (A(s): the magnitude of this thread's element s before the division).
+// H_M is increasing in |a| and the division is monotone, so the top kp of H_M(a_F) are found
+// on A directly and only the selected values are divided.
+template <int E, typename AF>
+__device__ double gstar_node(AF A, double div, uint64_t cb, int kp, int nfree, double M,
+                             ProxSmem& sm) {
+  const uint32_t fm = cls_mask<E>(cb, CLS_FREE);
   double z1 = 0.0;
-  bool freeb[E];
-  double mag[E];
 #pragma unroll
-  for (int s = 0; s < E; ++s) {
-    freeb[s] = cls[s] == CLS_FREE;
-    mag[s] = fabs(a[s]);
-    if (cls[s] == CLS_ONE) z1 += huber(a[s], M);
-  }
+  for (int s = 0; s < E; ++s)
+    if (cls_at(cb, s) == CLS_ONE) z1 += huber(A(s) / div, M);
   double top = 0.0;
   if (kp > 0 && nfree > 0) {
     if (kp >= nfree) {
 #pragma unroll
       for (int s = 0; s < E; ++s)
-        if (freeb[s]) top += huber(a[s], M);
+        if ((fm >> s) & 1u) top += huber(A(s) / div, M);
     } else if (kp <= kWaveSel) {
-      block_topk<E>(mag, freeb, kp, sm);
+      block_topk<E>(A, fm, kp, sm);
       if (threadIdx.x == 0)
-        for (int r = 0; r < kp; ++r) top += huber(sm.hu[r], M);
+        for (int r = 0; r < kp; ++r) top += huber(sm.hu[r] / div, M);
     } else {
-      uint64_t key[E];
-#pragma unroll
-      for (int s = 0; s < E; ++s) key[s] = dbits(mag[s]);
-      const Select sel = radix_select_desc<E>(key, freeb, kp, sm);
+      auto K = [&](int s) { return dbits(A(s)); };
+      const Select sel = radix_select_desc<E>(K, fm, kp, sm);
 #pragma unroll
       for (int s = 0; s < E; ++s) {
-        if (!freeb[s]) continue;
-        if (!sel.exact ? key[s] >= sel.lo : key[s] > sel.lo) top += huber(a[s], M);
+        if (!((fm >> s) & 1u)) continue;
+        const uint64_t ks = K(s);
+        if (!sel.exact ? ks >= sel.lo : ks > sel.lo) top += huber(A(s) / div, M);
       }
       if (sel.exact && sel.take > 0 && threadIdx.x == 0)
-        top += (double)sel.take * huber(bitsd(sel.lo), M);
+        top += (double)sel.take * huber(bitsd(sel.lo) / div, M);
     }
   }
   return bsum(z1 + top, sm);
 }
+
+// Per-thread working values of the prox kernels: element s of thread t at s * kProxThreads + t
+// of an LDS array (private to the thread: no barrier needed) when E <= kLdsElems, else in
+// registers. Keeps register pressure low enough for 1024-thread workgroups.
+constexpr int kLdsElems = 16;
+template <int E>
+struct ProxVals {
+  static constexpr bool lds = E <= kLdsElems;
+  double* sl;           // LDS slice base (lds)
+  double reg[lds ? 1 : E];
+  __device__ __forceinline__ void set(int s, double v) {
+    if constexpr (lds) sl[s * kProxThreads + threadIdx.x] = v;
+    else reg[s] = v;
+  }
+  __device__ __forceinline__ double get(int s) const {
+    if constexpr (lds) return sl[s * kProxThreads + threadIdx.x];
+    else return reg[s];
+  }
+};
 
 }  // namespace cgl

@@ -56,12 +56,12 @@ void MixedWork::ensure(Problem& P) {
   dop.alloc((size_t)S_pad * ldp * 2);
   gop.alloc((size_t)S_pad * n_pad * 2);
   dU.alloc(2 * (size_t)S_pad * n_pad * 4);
-  // split-K so that each pass has about 2 workgroups (128 rows x 256 nodes) per compute unit,
-  // each with >= 16 k-steps of 32
+  // split-K: two 128-row workgroups fit on a compute unit at once (512 on the chip); take the
+  // largest split that still runs in one round of 512 (a second, mostly idle round costs more
+  // than the longer k-range per workgroup), each chunk keeping >= 16 k-steps of 32
   auto split_for = [](int64_t m_tiles, int64_t K) {
-    const int64_t want = (2 * 256 + m_tiles - 1) / m_tiles;
-    const int64_t cap = std::max<int64_t>(1, K / (32 * 16));
-    return (int)std::max<int64_t>(1, std::min(want, cap));
+    const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(16, K / (32 * 16)));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(cap, 512 / std::max<int64_t>(1, m_tiles)));
   };
   ksx = split_for(n_pad / 128, ldp);
   x_kchunk = round_up((ldp + ksx - 1) / ksx, 128);

@@ -52,18 +52,26 @@ __device__ __forceinline__ bool slot_running(const NodeDev* st) {
 // =====================================================================================
 // PASS only names the instantiation (0: X~ (beta - beta_0), 1: X~^T (grad - r_0)) so that
 // profiles report the two products separately.
+//
+// 1D grid, XCD-aware: workgroups are dispatched round-robin over the 8 XCDs by linear id, so the
+// (row tile, k-chunk) pairs, ordered k-chunk-major, are cut into 8 contiguous ranges and range x
+// is given to the ids that land on XCD x. The workgroups of one XCD then share one or two
+// k-chunks of B in that XCD's L2. Node tiles (blockIdx.y) are outermost.
 template <int PASS>
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int mtiles, int ks, int per_xcd) {
   __shared__ __attribute__((aligned(16))) uint16_t As[2 * GT_M * GT_LD];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const int64_t m0 = (int64_t)blockIdx.x * GT_M;
+  const int pair = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (pair >= mtiles * ks) return;  // padding of the last range (no barrier reached yet)
+  const int z = pair / mtiles;
+  const int64_t m0 = (int64_t)(pair % mtiles) * GT_M;
   const int64_t n0 = (int64_t)blockIdx.y * GT_N;
-  const int64_t k0 = (int64_t)blockIdx.z * g.kchunk;
+  const int64_t k0 = (int64_t)z * g.kchunk;
   const int64_t k1 = min(g.K, k0 + g.kchunk);
   floatx16 acc[GT_RT][2];
   gemm_bf16_mainloop(g, m0, n0, k0, k1, As, acc);
-  float* C = g.C + (int64_t)blockIdx.z * g.c_split_stride;
+  float* C = g.C + (int64_t)z * g.c_split_stride;
   const int hi = lane >> 5;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
@@ -557,8 +565,9 @@ void launch_gemm_x(const MixedDev& md, hipStream_t s) {
   g.C = md.dUp;
   g.ldc = md.n_pad;
   g.c_split_stride = md.dUp_split;
-  dim3 grid((unsigned)(md.n_pad / GT_M), (unsigned)(md.S_pad / GT_N), (unsigned)md.ksx);
-  hipLaunchKernelGGL(k_gemm_bf16<0>, grid, dim3(256), 0, s, g);
+  const int mt = (int)(md.n_pad / GT_M), per = (mt * md.ksx + 7) / 8;
+  dim3 grid((unsigned)(8 * per), (unsigned)(md.S_pad / GT_N));
+  hipLaunchKernelGGL(k_gemm_bf16<0>, grid, dim3(256), 0, s, g, mt, md.ksx, per);
 }
 
 void launch_gemm_xt(const MixedDev& md, hipStream_t s) {
@@ -573,8 +582,9 @@ void launch_gemm_xt(const MixedDev& md, hipStream_t s) {
   g.C = md.dH;
   g.ldc = md.ldp;
   g.c_split_stride = md.dH_split;
-  dim3 grid((unsigned)(md.ldp / GT_M), (unsigned)(md.S_pad / GT_N), (unsigned)md.ksplit);
-  hipLaunchKernelGGL(k_gemm_bf16<1>, grid, dim3(256), 0, s, g);
+  const int mt = (int)(md.ldp / GT_M), per = (mt * md.ksplit + 7) / 8;
+  dim3 grid((unsigned)(8 * per), (unsigned)(md.S_pad / GT_N));
+  hipLaunchKernelGGL(k_gemm_bf16<1>, grid, dim3(256), 0, s, g, mt, md.ksplit, per);
 }
 
 void launch_mixed_loss(const MixedDev& md, hipStream_t s) {

@@ -271,3 +271,61 @@ def prox_node_batch(ctx: Context, W, rho, M, k, sets=None):
     check(ctx.lib.cgl_prox_node_batch(ctx.h, float(rho), float(M), int(k), arr, _dptr(W), count,
                                       p, _dptr(beta), _dptr(g)))
     return beta, g
+
+
+class Server:
+    """Continuous-batching request server over resident problems (cgl_server_*).
+
+    submit() copies the node and returns a ticket; poll() runs one scheduling round and returns
+    the finished requests as (ticket, Result with beta, latency seconds)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, max_slots: int = 256):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.h = C.c_void_p()
+        check(self.lib.cgl_server_create(ctx.h, int(hbm_budget_bytes), int(max_slots),
+                                          C.byref(self.h)))
+        self._pmax = 0
+        self._p = {}
+
+    def submit(self, prob: "Problem", spec: NodeSpec) -> int:
+        t = C.c_uint64()
+        check(self.lib.cgl_server_submit(self.h, prob.h, C.byref(spec.c), C.byref(t)))
+        self._pmax = max(self._pmax, prob.p)
+        self._p[t.value] = prob.p
+        return t.value
+
+    def poll(self, max_results: int = 256):
+        tickets = (C.c_uint64 * max_results)()
+        res = (CglResult * max_results)()
+        stride = max(self._pmax, 1)
+        betas = np.empty((max_results, stride))
+        lat = np.empty(max_results)
+        got = C.c_int32()
+        check(self.lib.cgl_server_poll(self.h, max_results, tickets, res, _dptr(betas), stride,
+                                       _dptr(lat), C.byref(got)))
+        out = []
+        for i in range(got.value):
+            t = int(tickets[i])
+            p = self._p.pop(t, stride)
+            out.append((t, _result(res[i], betas[i, :p].copy()), float(lat[i])))
+        return out
+
+    def cancel(self, ticket: int) -> None:
+        check(self.lib.cgl_server_cancel(self.h, C.c_uint64(ticket)))
+
+    def stats(self):
+        q, r, d = C.c_int32(), C.c_int32(), C.c_int32()
+        check(self.lib.cgl_server_stats(self.h, C.byref(q), C.byref(r), C.byref(d)))
+        return {"queued": q.value, "running": r.value, "done": d.value}
+
+    def close(self) -> None:
+        if self.h:
+            check(self.lib.cgl_server_destroy(self.h))
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

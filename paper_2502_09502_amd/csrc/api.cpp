@@ -34,10 +34,6 @@ namespace cgl {
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-struct InvalidArg {
-  std::string msg;
-};
-
 [[noreturn]] void invalid(const std::string& m) { throw InvalidArg{m}; }
 
 DevBuf::~DevBuf() { reset(); }
@@ -367,30 +363,6 @@ void certify_host_beta(Problem& P, const NodeHost& nh, const double* beta, doubl
 using namespace cgl;
 
 // ====================================================================== C ABI
-
-#define CGL_API_BEGIN try {
-#define CGL_API_END                                                       \
-  }                                                                       \
-  catch (const InvalidArg& e) {                                           \
-    set_error(e.msg);                                                     \
-    return CGL_E_INVAL;                                                   \
-  }                                                                       \
-  catch (const HipError& e) {                                             \
-    set_error(std::string(e.what) + ": " + hipGetErrorString(e.err));     \
-    return e.err == hipErrorOutOfMemory ? CGL_E_NOMEM : CGL_E_DEVICE;     \
-  }                                                                       \
-  catch (const std::bad_alloc&) {                                         \
-    set_error("allocation failed");                                       \
-    return CGL_E_NOMEM;                                                   \
-  }                                                                       \
-  catch (const std::exception& e) {                                       \
-    set_error(e.what());                                                  \
-    return CGL_E_INTERNAL;                                                \
-  }                                                                       \
-  catch (...) {                                                           \
-    set_error("unknown error");                                           \
-    return CGL_E_INTERNAL;                                                \
-  }
 
 extern "C" {
 

@@ -279,6 +279,16 @@ bool MixedWork::cert_round(Problem& P) {
   return true;
 }
 
+size_t MixedWork::device_bytes() const {
+  const DevBuf* bufs[] = {&Xb, &Xbt, &ypad, &st, &cls, &bring, &beta0, &H0, &base0, &base1,
+                          &bres, &dop, &gop, &dU, &dUp, &dH, &lpart, &fpart, &cycle, &B64,
+                          &U64, &R64, &H64, &cpart, &list, &H0_cold, &base0_cold, &base1_cold,
+                          &Xt, &part64};
+  size_t b = 0;
+  for (const DevBuf* d : bufs) b += d->bytes;
+  return b;
+}
+
 int MixedWork::free_slots() const {
   int c = 0;
   for (int o : slot_owner) c += o < 0 ? 1 : 0;
@@ -350,6 +360,8 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
   if (!P.mixed) P.mixed = new MixedWork();
   MixedWork& W = *P.mixed;
   W.ensure(P);
+  if (W.free_slots() != W.S)
+    invalid("the problem's batched engine is in use by a server; solve through the server");
   hipStream_t s = P.ctx->stream;
   std::vector<NodeHost> hosts;
   hosts.reserve((size_t)count);

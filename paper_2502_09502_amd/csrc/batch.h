@@ -50,6 +50,7 @@ struct MixedWork {
   void retire(Problem& P, int slot, cgl_result* res, double* beta_out);
   void push_states(Problem& P);
   int free_slots() const;
+  size_t device_bytes() const;  // device memory held by this engine
   ~MixedWork();
 };
 

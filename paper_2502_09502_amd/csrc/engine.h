@@ -26,6 +26,9 @@ struct cgl_ctx {
 
 namespace cgl {
 
+struct InvalidArg {
+  std::string msg;
+};
 [[noreturn]] void invalid(const std::string& m);
 
 // Owning device allocation.
@@ -83,6 +86,7 @@ struct Problem {
   DevBuf y;  // n doubles
   PlainWork plain;
   MixedWork* mixed = nullptr;  // created on first mixed solve
+  size_t mixed_bytes = 0;      // its device footprint, once known
   ~Problem();
 };
 
@@ -94,3 +98,29 @@ void certify_host_beta(Problem& P, const NodeHost& nh, const double* beta, doubl
                        double* dual);
 
 }  // namespace cgl
+
+// Every extern "C" entry point body sits between these: C++ exceptions become status codes
+// (with the detail string for cgl_last_error) and never cross the ABI.
+#define CGL_API_BEGIN try {
+#define CGL_API_END                                                       \
+  }                                                                       \
+  catch (const ::cgl::InvalidArg& e) {                                           \
+    ::cgl::set_error(e.msg);                                                     \
+    return CGL_E_INVAL;                                                   \
+  }                                                                       \
+  catch (const ::cgl::HipError& e) {                                             \
+    ::cgl::set_error(std::string(e.what) + ": " + hipGetErrorString(e.err));     \
+    return e.err == hipErrorOutOfMemory ? CGL_E_NOMEM : CGL_E_DEVICE;     \
+  }                                                                       \
+  catch (const std::bad_alloc&) {                                         \
+    ::cgl::set_error("allocation failed");                                       \
+    return CGL_E_NOMEM;                                                   \
+  }                                                                       \
+  catch (const std::exception& e) {                                       \
+    ::cgl::set_error(e.what());                                                  \
+    return CGL_E_INTERNAL;                                                \
+  }                                                                       \
+  catch (...) {                                                           \
+    ::cgl::set_error("unknown error");                                           \
+    return CGL_E_INTERNAL;                                                \
+  }

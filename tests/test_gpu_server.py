@@ -1,0 +1,145 @@
+"""Request server (continuous batching): every request gets the result it would get alone,
+cancellation, the device-memory budget and ticket errors."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2502_09502_amd import _lib, synth
+
+from gpu_util import ctx, rel
+
+pytestmark = pytest.mark.gpu
+
+MAX_ROUNDS = 20000
+
+
+def _drain(srv, expect):
+    out = {}
+    for _ in range(MAX_ROUNDS):
+        for t, r, lat in srv.poll(64):
+            out[t] = (r, lat)
+        if len(out) >= expect:
+            return out
+    raise AssertionError(f"server did not finish: {len(out)} of {expect}, {srv.stats()}")
+
+
+def _problems():
+    a = synth.make_config("c1")
+    b = synth.make_config("c1", loss="logistic")
+    pa = _lib.Problem(ctx(), a.X_store, a.y, loss=a.loss, lam2=a.lam2, M=a.M, k=a.k)
+    pb = _lib.Problem(ctx(), b.X_store, b.y, loss=b.loss, lam2=b.lam2, M=b.M, k=b.k)
+    return a, pa, b, pb
+
+
+def _same(r, ref):
+    assert r.status == ref.status, (r, ref)
+    if r.status == "infeasible":
+        assert math.isinf(r.lower_bound)
+        return
+    assert r.gap_rel <= 1e-6
+    assert rel(r.primal, ref.primal) <= 1e-6, (r.primal, ref.primal)
+    # both bounds are certified and within the gap of each other
+    assert abs(r.lower_bound - ref.lower_bound) <= 2e-6 * max(abs(ref.primal), 1.0)
+
+
+def test_server_mix_matches_alone():
+    a, pa, b, pb = _problems()
+    sets_a = synth.node_sets(a.p, a.k, 24, 8, config_id=1)
+    sets_b = synth.node_sets(b.p, b.k, 24, 8, config_id=2)
+    srv = _lib.Server(ctx(), 0, 256)
+    jobs = []  # (ticket, prob, spec)
+    for i in range(24):
+        for prob, sets in ((pa, sets_a), (pb, sets_b)):
+            prec = "f64" if i % 8 == 3 else "mixed"
+            spec = prob.node(Z0=sets[i][0], Z1=sets[i][1], tol=1e-6, max_iter=5000, precision=prec)
+            jobs.append((srv.submit(prob, spec), prob, spec))
+    # an infeasible node (|Z1| > k) finishes at submit
+    zin = list(range(a.k + 1))
+    spec = pa.node(Z1=zin, precision="mixed")
+    jobs.append((srv.submit(pa, spec), pa, spec))
+    out = _drain(srv, len(jobs))
+    assert srv.stats() == {"queued": 0, "running": 0, "done": 0}
+    srv.close()
+    for t, prob, spec in jobs:
+        r, lat = out[t]
+        assert lat >= 0.0
+        ref = prob.solve_batch([spec])[0]
+        _same(r, ref)
+        if r.status == "converged":
+            assert r.beta is not None and r.beta.shape == (prob.p,)
+
+
+def test_server_cancel_and_tickets():
+    a, pa, _, _ = _problems()
+    sets = synth.node_sets(a.p, a.k, 12, 8, config_id=3)
+    srv = _lib.Server(ctx(), 0, 2)  # two slots: most requests wait in the queue
+    tickets = [srv.submit(pa, pa.node(Z0=z0, Z1=z1, precision="mixed", max_iter=5000))
+               for z0, z1 in sets]
+    srv.poll(0)  # admits two, runs one chunk
+    st = srv.stats()
+    assert st["running"] == 2 and st["queued"] == 10
+    srv.cancel(tickets[-1])  # queued
+    srv.cancel(tickets[0])   # running
+    with pytest.raises(_lib.CglError):
+        srv.cancel(10**9)
+    out = _drain(srv, len(tickets))
+    assert out[tickets[-1]][0].status == "cancelled"
+    assert out[tickets[0]][0].status == "cancelled"
+    for t in tickets[1:-1]:
+        assert out[t][0].status == "converged"
+    with pytest.raises(_lib.CglError):
+        srv.cancel(tickets[1])  # finished
+    srv.close()
+
+
+def test_server_budget_one_engine_at_a_time():
+    a, pa, b, pb = _problems()
+    sets = synth.node_sets(a.p, a.k, 6, 8, config_id=4)
+    srv = _lib.Server(ctx(), 1, 256)  # a 1-byte budget: engines take turns
+    jobs = []
+    for z0, z1 in sets:
+        for prob in (pa, pb):
+            spec = prob.node(Z0=z0, Z1=z1, precision="mixed", max_iter=5000)
+            jobs.append((srv.submit(prob, spec), prob, spec))
+    out = {}
+    for _ in range(MAX_ROUNDS):
+        for t, r, lat in srv.poll(64):
+            out[t] = r
+        st = srv.stats()
+        # never two problems running at once
+        assert st["running"] <= len(sets)
+        if len(out) == len(jobs):
+            break
+    assert len(out) == len(jobs)
+    for t, prob, spec in jobs:
+        _same(out[t], prob.solve_batch([spec])[0])
+    srv.close()
+
+
+def test_server_holds_engine_against_direct_solves():
+    a, pa, _, _ = _problems()
+    sets = synth.node_sets(a.p, a.k, 4, 8, config_id=5)
+    srv = _lib.Server(ctx(), 0, 256)
+    specs = [pa.node(Z0=z0, Z1=z1, precision="mixed", max_iter=5000) for z0, z1 in sets]
+    for s in specs:
+        srv.submit(pa, s)
+    srv.poll(0)
+    if srv.stats()["running"] > 0:
+        with pytest.raises(_lib.CglError):
+            pa.solve_batch(specs[:1])
+    _drain(srv, len(specs))
+    srv.close()
+    pa.solve_batch(specs[:1])  # free again
+
+
+def test_server_rejects_bad_arguments():
+    a, pa, _, _ = _problems()
+    with pytest.raises(_lib.CglError):
+        _lib.Server(ctx(), 0, 0)
+    srv = _lib.Server(ctx(), 0, 8)
+    with pytest.raises(_lib.CglError):
+        srv.submit(pa, pa.node(Z0=[0], Z1=[0]))  # overlapping sets
+    with pytest.raises(_lib.CglError):
+        srv.submit(pa, pa.node(precision="mixed", warm_start=np.zeros(pa.p)))
+    srv.close()

@@ -94,6 +94,101 @@ def cpu_baseline(d, node_set, L, gpu_iters):
                        f"{gpu_iters} iterations node 0 takes to certify 1e-6 on the GPU")}
 
 
+SERVE_WORKLOAD = ("serving: Poisson stream (mean 2000/s) of node relaxations over 3 resident "
+                  "datasets p in {1000, 5000, 20000}, n = 2p, FP32 X (BF16 copies on the device), "
+                  "least squares and logistic 50/50, |Z0|~U[0,30], |Z1|~U[0,10], k=10, M=2, "
+                  "lambda2=1e-3, FP64-certified rel. gap 1e-6")
+
+
+def serve(args):
+    """Continuous-batching server under a Poisson request stream; latency is completion time
+    minus arrival time (including the wait for the polling loop to pick the request up)."""
+    sizes = [int(v) for v in args.serve_sizes.split(",")]
+    ctx = _lib.Context(0)
+    t_setup = time.perf_counter()
+    probs = []
+    for p in sizes:
+        X32, y_ls, y_log = synth.serving_dataset(p)
+        for loss, y in (("ls", y_ls), ("logistic", y_log)):
+            probs.append((p, loss, _lib.Problem(ctx, X32, y, loss=loss, lam2=1e-3, M=2.0, k=10)))
+        del X32
+    print(f"# serving setup {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
+    N = args.requests
+    rng = np.random.default_rng([3, 5])
+    which = rng.integers(0, len(probs), size=N)
+    sets = {p: synth.node_sets(p, 10, N, 30, config_id=5) for p in sizes}
+    specs = []
+    for i in range(N):
+        p, loss, prob = probs[int(which[i])]
+        z0, z1 = sets[p][i]
+        specs.append((prob, prob.node(Z0=z0, Z1=z1, tol=1e-6, max_iter=5000, precision="mixed")))
+    arrivals = synth.poisson_arrivals(N, args.rate)
+    # warm the engines (setup of the BF16 copies and of the graphs is not request latency)
+    srv = _lib.Server(ctx, 0, 256)
+    for prob_i in range(len(probs)):
+        prob = probs[prob_i][2]
+        srv.submit(prob, prob.node(tol=1e-6, precision="mixed"))
+    got = 0
+    while got < len(probs):
+        got += len(srv.poll(256))
+    arrival_of = {}
+    lat = []
+    statuses = {}
+    i = 0
+    t0 = time.perf_counter()
+    t_last = t0
+    while len(lat) < N:
+        now = time.perf_counter() - t0
+        while i < N and arrivals[i] <= now:
+            prob, spec = specs[i]
+            arrival_of[srv.submit(prob, spec)] = arrivals[i]
+            i += 1
+        for t, r, _ in srv.poll(256):
+            done_t = time.perf_counter() - t0
+            lat.append(done_t - arrival_of.pop(t))
+            statuses[r.status] = statuses.get(r.status, 0) + 1
+            t_last = time.perf_counter()
+        if i < N and not srv.stats()["running"] and not srv.stats()["queued"]:
+            time.sleep(max(0.0, arrivals[i] - (time.perf_counter() - t0)))
+    elapsed = t_last - t0
+    srv.close()
+    lat_ms = 1e3 * np.asarray(lat)
+    out = {
+        "metric": "node relaxations solved/sec at 1e-6 gap, batched vs plain; p50/p99 latency",
+        "value": round(N / elapsed, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": round(1e3 * elapsed, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16-mfma/fp32-acc + fp64 bound",
+        "data": "synthetic",
+        "config": {"workload": SERVE_WORKLOAD, "requests": N, "rate_per_s": args.rate,
+                   "sizes": sizes, "engine": "server"},
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 3),
+                       "max": round(float(lat_ms.max()), 3)},
+        "statuses": statuses,
+        "offered_rate_per_s": args.rate,
+    }
+    print(json.dumps(out))
+
+
+def copy_calibration(nbytes: int) -> None:
+    """One plain device-to-device copy of a known size (reference for traffic counters)."""
+    import torch
+
+    a = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"# copy calibration: {nbytes} bytes", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,12 +199,25 @@ def main():
                     help="nodes of the plain FP64 per-node comparator")
     ap.add_argument("--mode", choices=["auto", "batched", "plain"], default="auto")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", choices=["batched", "serve"], default="batched",
+                    help="batched: the 256-node step (default); serve: the request stream")
+    ap.add_argument("--requests", type=int, default=600, help="serve: number of requests")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve: mean arrivals per second")
+    ap.add_argument("--serve-sizes", default="1000,5000,20000", help="serve: dataset p values")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="after the run, one device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (nodes shard "
               "across GPUs with no per-iteration communication; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "serve":
+        serve(args)
+        if args.copy_bytes > 0:
+            copy_calibration(args.copy_bytes)
+        return
 
     t_setup = time.perf_counter()
     d = synth.make_config("c4")
@@ -194,6 +302,8 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(d, sets[0], L, results[0].iters)
     print(json.dumps(out))
+    if args.copy_bytes > 0:
+        copy_calibration(args.copy_bytes)
 
 
 if __name__ == "__main__":

@@ -146,6 +146,20 @@ def make_config(name: str, seed: int = 0, **overrides) -> Dataset:
     return make_dataset(seed=seed, name=name, **cfg)
 
 
+def serving_dataset(p: int, k: int = 10, seed: int = 0, config_id: int = 5):
+    """One resident dataset of the serving workload: n = 2p, FP32 design, and two label vectors
+    (least squares, logistic) drawn from the same design. Returns (X_f32, y_ls, y_logistic)."""
+    n = 2 * p
+    rng = np.random.default_rng([seed, config_id, p, LOSS_ID["ls"]])
+    X64 = design_matrix(n, p, rng)
+    bs = beta_star(p, k)
+    y_ls = labels(X64, bs, "ls", rng)
+    y_log = labels(X64, bs, "logistic", np.random.default_rng([seed, config_id, p, LOSS_ID["logistic"]]))
+    X32 = X64.astype(np.float32)
+    del X64
+    return X32, y_ls, y_log
+
+
 def node_sets(p: int, k: int, count: int, zero_cap: int, seed: int = 1, config_id: int = 0):
     """Branch-and-bound node sets: |Z0| ~ U{0..zero_cap}, |Z1| ~ U{0..min(zero_cap, k)}, disjoint
     uniform-random index subsets (sorted, 0-based)."""

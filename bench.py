@@ -295,6 +295,14 @@ def main():
     elapsed = t1 - t0
     value = args.steps * len(step_specs) / elapsed
     roof = roofline(ctx, d.n, d.p, 2, len(step_specs), 2 if mode == "batched" else 0)
+    phases = None
+    if mode == "batched":
+        phases = {}
+        for w, name in ((3, "x_pass_kernel"), (2, "xt_pass_kernel"), (4, "fp64_pass_kernel"),
+                        (5, "iteration_chunks"), (6, "certification_rounds"),
+                        (7, "admission_retirement")):
+            ms, cnt = ctx.kernel_stats(w)
+            phases[name] = {"ms_per_step": round(ms / args.steps, 3), "count_per_step": cnt / args.steps}
     ok = all(r.status == "converged" and r.gap_rel <= 1e-6 for r in results)
     iters = [r.iters for r in results]
     print(f"# {mode}: {value:.2f} solves/s, all certified: {ok}, iterations median "
@@ -335,6 +343,8 @@ def main():
                        "max": max(iters)},
         "roofline": roof,
     }
+    if phases is not None:
+        out["phases"] = phases
     if mode == "plain":
         out["latency_ms"] = {"note": "per-node solve time on the plain path, sequential",
                              "p50": round(1e3 * elapsed / args.steps / len(step_specs), 3)}

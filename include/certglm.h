@@ -121,10 +121,12 @@ int cgl_ctx_create(int device, void* hip_stream, cgl_ctx** out);
 int cgl_ctx_destroy(cgl_ctx* ctx);
 
 /* Kernel timing (measurement support). While on, solves on this context bracket every launch of
- * the listed kernels with HIP events on the context's stream (the plain path then launches
- * without graph capture) and accumulate the elapsed time of launches that did work.
+ * the listed kernels with HIP events on the context's stream (both paths then launch without
+ * graph capture) and accumulate the elapsed time of launches that did work.
  * which: 0 = X^T pass of the plain path (k_xt), 1 = X pass of the plain path (k_xb),
- *        2 = batched BF16 MFMA X^T pass, 3 = batched BF16 MFMA X pass, 4 = batched FP64 pass.
+ *        2 = batched BF16 MFMA X^T pass, 3 = batched BF16 MFMA X pass, 4 = batched FP64 pass;
+ *        and host wall time of the batched engine's phases (launch to completion):
+ *        5 = iteration chunks, 6 = certification rounds, 7 = admission and retirement.
  * cgl_ctx_kernel_stats returns the totals since the last reset (reset = 1 clears them). */
 int cgl_ctx_set_profiling(cgl_ctx* ctx, int32_t on);
 int cgl_ctx_kernel_stats(cgl_ctx* ctx, int32_t which, int32_t reset, double* total_ms,

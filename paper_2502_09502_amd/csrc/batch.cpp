@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -31,6 +32,7 @@ static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 void MixedWork::ensure(Problem& P) {
   if (ready) return;
   hipStream_t s = P.ctx->stream;
+  std::fill(want_since, want_since + kSlots, (int64_t)-1);
   S = kSlots;
   S_pad = (int)round_up(S, 256);
   n_pad = round_up(P.n, 128);  // rows of X~: a multiple of the GEMM tile and of its k-chunk grain
@@ -206,13 +208,15 @@ static bool mixed_graphs() {
 void MixedWork::run_chunk(Problem& P) {
   hipStream_t s = P.ctx->stream;
   cgl_ctx* ctx = P.ctx;
-  if (ctx->profiling) {
+  // with profiling on, each cycle's two products are bracketed by HIP events on the stream (HIP
+  // cannot time events recorded inside a graph, so the cycles are then launched one by one)
+  if (ctx->profiling || !mixed_graphs()) {
     for (int i = 0; i < kChunk; ++i) {
-      hipEvent_t ev[4] = {ctx->event(4 * i), ctx->event(4 * i + 1), ctx->event(4 * i + 2),
-                          ctx->event(4 * i + 3)};
-      mixed_cycle(*this, s, ev);
+      hipEvent_t ev[4];
+      for (int e = 0; e < 4; ++e) ev[e] = ctx->event((size_t)(4 * i + e));
+      mixed_cycle(*this, s, ctx->profiling ? ev : nullptr);
     }
-  } else if (mixed_graphs()) {
+  } else {
     if (!graph_exec) {
       hipGraph_t graph;
       CGL_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -222,16 +226,14 @@ void MixedWork::run_chunk(Problem& P) {
       CGL_HIP(hipGraphDestroy(graph));
     }
     CGL_HIP(hipGraphLaunch(graph_exec, s));
-  } else {
-    for (int i = 0; i < kChunk; ++i) mixed_cycle(*this, s);
   }
   CGL_HIP(hipMemcpyAsync(st_host, st.ptr, (size_t)S * sizeof(NodeDev), hipMemcpyDeviceToHost, s));
   CGL_HIP(hipStreamSynchronize(s));
   if (ctx->profiling) {
     for (int i = 0; i < kChunk; ++i) {
       float a = 0.f, b = 0.f;
-      CGL_HIP(hipEventElapsedTime(&a, ctx->event(4 * i), ctx->event(4 * i + 1)));
-      CGL_HIP(hipEventElapsedTime(&b, ctx->event(4 * i + 2), ctx->event(4 * i + 3)));
+      CGL_HIP(hipEventElapsedTime(&a, ctx->event((size_t)(4 * i)), ctx->event((size_t)(4 * i + 1))));
+      CGL_HIP(hipEventElapsedTime(&b, ctx->event((size_t)(4 * i + 2)), ctx->event((size_t)(4 * i + 3))));
       ctx->kt_ms[3] += a;  // X pass
       ctx->kt_ms[2] += b;  // X^T pass
       ctx->kt_n[3] += 1;
@@ -242,16 +244,33 @@ void MixedWork::run_chunk(Problem& P) {
 }
 
 bool MixedWork::cert_round(Problem& P) {
+  // Batch the FP64 rounds: a node that asks for certification keeps iterating until enough
+  // nodes ask (kCertBatch), the oldest request has waited kCertWait chunks, or every active node
+  // is waiting, so each round's FP64 products are shared by more nodes.
   std::vector<int> want;
+  int active = 0;
+  int64_t oldest = cycles;
   for (int sl = 0; sl < S; ++sl) {
     const NodeDev& d = st_host[sl];
-    if (slot_owner[(size_t)sl] >= 0 && d.active && !d.done && d.want_cert) want.push_back(sl);
+    if (slot_owner[(size_t)sl] < 0 || !d.active || d.done) {
+      want_since[sl] = -1;
+      continue;
+    }
+    ++active;
+    if (!d.want_cert) {
+      want_since[sl] = -1;
+      continue;
+    }
+    if (want_since[sl] < 0) want_since[sl] = cycles;
+    oldest = std::min(oldest, want_since[sl]);
+    want.push_back(sl);
   }
   if (want.empty()) return false;
+  const int nq = (int)want.size();
+  if (nq < kCertBatch && nq < active && cycles - oldest < (int64_t)kCertWait * kChunk) return false;
   hipStream_t s = P.ctx->stream;
   cgl_ctx* ctx = P.ctx;
-  const int nq = (int)want.size();
-  for (int sl : want) st_host[sl].L_work = st_host[sl].L_work;  // keep the working value
+  for (int sl : want) want_since[sl] = -1;
   CGL_HIP(hipMemcpyAsync(list.ptr, want.data(), (size_t)nq * sizeof(int), hipMemcpyHostToDevice, s));
   hipEvent_t e0 = ctx->profiling ? ctx->event(100) : nullptr;
   hipEvent_t e1 = ctx->profiling ? ctx->event(101) : nullptr;
@@ -391,22 +410,33 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
     }
     W.admit(P, adm);
   };
-  fill();
+  cgl_ctx* ctx = P.ctx;
+  auto phase = [&](int which, auto&& fn) {
+    if (!ctx->profiling) return fn();
+    const auto t0 = std::chrono::steady_clock::now();
+    fn();
+    ctx->kt_ms[which] +=
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    ctx->kt_n[which] += 1;
+  };
+  phase(7, [&] { fill(); });
   while (finished < count) {
-    W.run_chunk(P);
-    W.cert_round(P);
-    bool changed = false;
-    for (int sl = 0; sl < W.S; ++sl) {
-      const int owner = W.slot_owner[(size_t)sl];
-      if (owner < 0 || !W.st_host[sl].done) continue;
-      W.retire(P, sl, &res[owner], beta_out ? beta_out + (int64_t)owner * P.p : nullptr);
-      ++finished;
-      changed = true;
-    }
-    if (changed) {
-      W.push_states(P);
-      fill();
-    }
+    phase(5, [&] { W.run_chunk(P); });
+    phase(6, [&] { W.cert_round(P); });
+    phase(7, [&] {
+      bool changed = false;
+      for (int sl = 0; sl < W.S; ++sl) {
+        const int owner = W.slot_owner[(size_t)sl];
+        if (owner < 0 || !W.st_host[sl].done) continue;
+        W.retire(P, sl, &res[owner], beta_out ? beta_out + (int64_t)owner * P.p : nullptr);
+        ++finished;
+        changed = true;
+      }
+      if (changed) {
+        W.push_states(P);
+        fill();
+      }
+    });
     // a run with nothing active and work pending would spin: guard
     if (finished < count && W.free_slots() == W.S && next >= count) break;
   }

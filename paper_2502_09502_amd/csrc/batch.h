@@ -13,6 +13,8 @@ namespace cgl {
 
 constexpr int kSlots = 256;  // node slots per problem
 constexpr int kChunk = 4;    // iterations per graph launch between host checks
+constexpr int kCertBatch = 32;  // certification requests that trigger a round at once
+constexpr int kCertWait = 2;    // chunks the oldest request may wait for others
 
 struct Admission {
   int slot;
@@ -38,9 +40,10 @@ struct MixedWork {
   std::vector<uint8_t> cls_host;
   std::vector<int> slot_owner;
   int64_t admitted_at[kSlots] = {0};
+  int64_t want_since[kSlots];  // cycle at which a slot's certification request was first seen
   int64_t cycles = 0;
   int64_t cert_rounds = 0;
-  hipGraphExec_t graph_exec = nullptr;
+  hipGraphExec_t graph_exec = nullptr;  // kChunk cycles
   MixedDev md{};
 
   void ensure(Problem& P);

@@ -58,21 +58,16 @@ void MixedWork::ensure(Problem& P) {
   dop.alloc((size_t)S_pad * ldp * 2);
   gop.alloc((size_t)S_pad * n_pad * 2);
   dU.alloc(2 * (size_t)S_pad * n_pad * 4);
-  // split-K: two 128-row workgroups fit on a compute unit at once (512 on the chip); take the
-  // largest split that still runs in one round of 512 (a second, mostly idle round costs more
-  // than the longer k-range per workgroup), each chunk keeping >= 16 k-steps of 32
-  auto split_for = [](int64_t m_tiles, int64_t K) {
-    const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(16, K / (32 * 16)));
-    return (int)std::max<int64_t>(1, std::min<int64_t>(cap, 512 / std::max<int64_t>(1, m_tiles)));
-  };
-  ksx = split_for(n_pad / 128, ldp);
-  x_kchunk = round_up((ldp + ksx - 1) / ksx, 128);
-  ksx = (int)((ldp + x_kchunk - 1) / x_kchunk);
-  dUp.alloc((size_t)ksx * S_pad * n_pad * 4);
-  ksplit = split_for(ldp / 128, n_pad);
-  xt_kchunk = round_up((n_pad + ksplit - 1) / ksplit, 128);
-  ksplit = (int)((n_pad + xt_kchunk - 1) / xt_kchunk);
-  dH.alloc((size_t)ksplit * S_pad * ldp * 4);
+  // split-K of the two products: the candidates keep >= 16 k-steps of 32 per chunk and at most
+  // two rounds of 512 workgroups (two 128-row workgroups fit on a compute unit at once); the
+  // partial buffers are sized for the largest candidate and the choice is made by timing
+  // (tune_splits) once the buffers exist
+  split_cands_x = split_candidates(n_pad / 128, ldp);
+  split_cands_xt = split_candidates(ldp / 128, n_pad);
+  set_split_x(split_cands_x.front());
+  set_split_xt(split_cands_xt.front());
+  dUp.alloc((size_t)split_cands_x.back() * S_pad * n_pad * 4);
+  dH.alloc((size_t)split_cands_xt.back() * S_pad * ldp * 4);
   rchunk = 2048;
   nrt = (int)((n_pad + rchunk - 1) / rchunk);
   lpart.alloc((size_t)S * nrt * 8);
@@ -82,7 +77,7 @@ void MixedWork::ensure(Problem& P) {
   CGL_HIP(hipMemsetAsync(dop.ptr, 0, (size_t)S_pad * ldp * 2, s));
   CGL_HIP(hipMemsetAsync(gop.ptr, 0, (size_t)S_pad * n_pad * 2, s));
   CGL_HIP(hipMemsetAsync(dU.ptr, 0, 2 * (size_t)S_pad * n_pad * 4, s));
-  CGL_HIP(hipMemsetAsync(dH.ptr, 0, (size_t)ksplit * S_pad * ldp * 4, s));
+  CGL_HIP(hipMemsetAsync(dH.ptr, 0, dH.bytes, s));
   // certification buffers
   B64.alloc(Sp * 8);
   U64.alloc(Sn * 8);
@@ -181,7 +176,81 @@ void MixedWork::ensure(Problem& P) {
   md.rchunk = rchunk;
   md.cycle = cycle.as<int>();
   CGL_HIP(hipStreamSynchronize(s));
+  tune_splits(P);
   ready = true;
+}
+
+std::vector<int> MixedWork::split_candidates(int64_t m_tiles, int64_t K) {
+  std::vector<int> c;
+  const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(16, K / (32 * 16)));
+  for (int64_t ks = 1; ks <= cap; ++ks) {
+    if (m_tiles * ks > 1024) break;
+    const int64_t chunk = round_up((K + ks - 1) / ks, 128);
+    if ((K + chunk - 1) / chunk == ks) c.push_back((int)ks);  // distinct chunkings only
+  }
+  if (c.empty()) c.push_back(1);
+  return c;
+}
+
+void MixedWork::set_split_x(int ks) {
+  x_kchunk = round_up((ldp + ks - 1) / ks, 128);
+  ksx = (int)((ldp + x_kchunk - 1) / x_kchunk);
+  md.ksx = ksx;
+  md.x_kchunk = x_kchunk;
+}
+
+void MixedWork::set_split_xt(int ks) {
+  xt_kchunk = round_up((n_pad + ks - 1) / ks, 128);
+  ksplit = (int)((n_pad + xt_kchunk - 1) / xt_kchunk);
+  md.ksplit = ksplit;
+  md.xt_kchunk = xt_kchunk;
+}
+
+// Autotuner of the split-K of both products: every candidate is launched on the engine's own
+// buffers (the operands are still zero, the partials are scratch) and timed with HIP events;
+// the fastest wins (a larger split must be 2% faster to be taken, since its partial sums cost
+// the next kernel). Results are kept on the context per (pass, rows, k-length, nodes);
+// CGL_AUTOTUNE=0 keeps the first candidate that fills the chip in one round.
+void MixedWork::tune_splits(Problem& P) {
+  cgl_ctx* ctx = P.ctx;
+  hipStream_t s = ctx->stream;
+  const char* env = std::getenv("CGL_AUTOTUNE");
+  const bool tune = !(env && env[0] == '0');
+  for (int pass = 0; pass < 2; ++pass) {
+    const std::vector<int>& cand = pass == 0 ? split_cands_x : split_cands_xt;
+    const int64_t m_tiles = pass == 0 ? n_pad / 128 : ldp / 128;
+    const std::array<int64_t, 4> key = {pass, pass == 0 ? n_pad : ldp, pass == 0 ? ldp : n_pad,
+                                        (int64_t)S_pad};
+    auto set = [&](int ks) { pass == 0 ? set_split_x(ks) : set_split_xt(ks); };
+    auto launch = [&]() { pass == 0 ? launch_gemm_x(md, s) : launch_gemm_xt(md, s); };
+    auto hit = ctx->tuned_split.find(key);
+    if (hit != ctx->tuned_split.end()) {
+      set(hit->second);
+      continue;
+    }
+    int choice = cand.back();
+    for (int ks : cand)  // without timing: the largest split that runs in one round
+      if (m_tiles * ks <= 512) choice = ks;
+    if (tune && cand.size() > 1) {
+      double best = HUGE_VAL;
+      for (int ks : cand) {
+        set(ks);
+        launch();  // warm-up
+        CGL_HIP(hipEventRecord(ctx->event(0), s));
+        for (int r = 0; r < 3; ++r) launch();
+        CGL_HIP(hipEventRecord(ctx->event(1), s));
+        CGL_HIP(hipEventSynchronize(ctx->event(1)));
+        float ms = 0.f;
+        CGL_HIP(hipEventElapsedTime(&ms, ctx->event(0), ctx->event(1)));
+        if (ms < best * 0.98) {
+          best = ms;
+          choice = ks;
+        }
+      }
+    }
+    set(choice);
+    ctx->tuned_split[key] = choice;
+  }
 }
 
 // One iteration of Alg. 3 for every running slot; ev (optional): events around the two MFMA

@@ -46,6 +46,11 @@ struct MixedWork {
   hipGraphExec_t graph_exec = nullptr;  // kChunk cycles
   MixedDev md{};
 
+  std::vector<int> split_cands_x, split_cands_xt;
+  static std::vector<int> split_candidates(int64_t m_tiles, int64_t K);
+  void set_split_x(int ks);
+  void set_split_xt(int ks);
+  void tune_splits(Problem& P);
   void ensure(Problem& P);
   void run_chunk(Problem& P);
   bool cert_round(Problem& P);

@@ -5,6 +5,8 @@
 #include <stdint.h>
 
 #include <string>
+#include <array>
+#include <map>
 #include <vector>
 
 #include "../../include/certglm.h"
@@ -21,6 +23,8 @@ struct cgl_ctx {
   int64_t kt_n[8] = {0};
   std::vector<hipEvent_t> events;  // pool, grown on demand
   hipEvent_t event(size_t i);
+  // split-K choices of the batched products found by timing, by (pass, M, K, nodes)
+  std::map<std::array<int64_t, 4>, int> tuned_split;
   ~cgl_ctx();
 };
 

@@ -74,6 +74,8 @@ void MixedWork::ensure(Problem& P) {
   fpart.alloc((size_t)S * nrt * 8);
   cycle.alloc(sizeof(int));
   CGL_HIP(hipMemsetAsync(cycle.ptr, 0, sizeof(int), s));
+  prevsel.alloc((size_t)2 * S * 65 * sizeof(int));
+  CGL_HIP(hipMemsetAsync(prevsel.ptr, 0, prevsel.bytes, s));
   CGL_HIP(hipMemsetAsync(dop.ptr, 0, (size_t)S_pad * ldp * 2, s));
   CGL_HIP(hipMemsetAsync(gop.ptr, 0, (size_t)S_pad * n_pad * 2, s));
   CGL_HIP(hipMemsetAsync(dU.ptr, 0, 2 * (size_t)S_pad * n_pad * 4, s));
@@ -175,6 +177,8 @@ void MixedWork::ensure(Problem& P) {
   md.nrt = nrt;
   md.rchunk = rchunk;
   md.cycle = cycle.as<int>();
+  md.prevhead = prevsel.as<int>();
+  md.prevtop = prevsel.as<int>() + (size_t)S * 65;
   CGL_HIP(hipStreamSynchronize(s));
   tune_splits(P);
   ready = true;
@@ -369,7 +373,7 @@ bool MixedWork::cert_round(Problem& P) {
 
 size_t MixedWork::device_bytes() const {
   const DevBuf* bufs[] = {&Xb, &Xbt, &ypad, &st, &cls, &bring, &beta0, &H0, &base0, &base1,
-                          &bres, &dop, &gop, &dU, &dUp, &dH, &lpart, &fpart, &cycle, &B64,
+                          &bres, &dop, &gop, &dU, &dUp, &dH, &lpart, &fpart, &cycle, &prevsel, &B64,
                           &U64, &R64, &H64, &cpart, &list, &H0_cold, &base0_cold, &base1_cold,
                           &Xt, &part64};
   size_t b = 0;

@@ -34,7 +34,7 @@ struct MixedWork {
   int64_t rchunk = 0, cchunk = 0;
   double f_cold = 0.0;
   DevBuf Xb, Xbt, ypad, st, cls, bring, beta0, H0, base0, base1, bres, dop, gop, dU, dUp, dH, lpart,
-      fpart, cycle, B64, U64, R64, H64, cpart, list, H0_cold, base0_cold, base1_cold, Xt, part64;
+      fpart, cycle, prevsel, B64, U64, R64, H64, cpart, list, H0_cold, base0_cold, base1_cold, Xt, part64;
   size_t part64_cap = 0;
   NodeDev* st_host = nullptr;
   std::vector<uint8_t> cls_host;

@@ -230,10 +230,12 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
     cb |= (uint64_t)cs << (2 * s);
   }
   // dual monitor at gamma: D = -F*(-zeta) - 2 lambda2 g_node*(-grad F(gamma) / (2 lambda2))
+  // element-indexed view of the LDS slice for the warm-started selections
+  const double* slice = ProxVals<E>::lds ? vbuf : nullptr;
   double gs = 0.0;
   if (check)
     gs = gstar_node<E>([&](int s) { return fabs(pv.get(s)); }, 2.0 * md.lam2, cb, st->kp,
-                       st->nfree, md.M, sm);
+                       st->nfree, md.M, sm, slice, md.prevtop + (int64_t)slot * 65);
   // gradient step w = gamma - H / L; the slice then holds u = rho |w|, the signs a mask
   uint32_t neg = 0;
 #pragma unroll
@@ -258,7 +260,7 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
           md.dop[frag_index(slot, j, nbk)] = float_to_bf16((float)(b - b0[j]));
         }
       },
-      sm);
+      sm, slice, md.prevhead + (int64_t)slot * 65);
   double fs = 0.0;
   if (check) {
     for (int i = threadIdx.x; i < md.nrt; i += blockDim.x)
@@ -482,6 +484,10 @@ __global__ __launch_bounds__(256) void k_admit(MixedDev md, const int* list, int
   if (q >= nq) return;
   const int slot = list[q];
   const int64_t stride = (int64_t)gridDim.x * 256;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {  // no selection history for a new node
+    md.prevhead[(int64_t)slot * 65] = 0;
+    md.prevtop[(int64_t)slot * 65] = 0;
+  }
   for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < md.ldp; j += stride) {
     const int64_t o = (int64_t)slot * md.ldp + j;
     for (int r = 0; r < 3; ++r) md.bring[(int64_t)r * md.bring_stride + o] = 0.0;

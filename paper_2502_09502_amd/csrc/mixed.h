@@ -47,6 +47,8 @@ struct MixedDev {
   int nrt;
   int64_t rchunk;
   int* cycle;           // global cycle counter
+  int* prevhead;        // S x 65: last prox head selection (count, indices) per slot
+  int* prevtop;         // S x 65: last top-k' selection of the dual monitor per slot
 };
 
 void launch_make_bf16(int xtype, const void* X, int64_t ldx, int64_t n, int64_t p, int64_t n_pad,

@@ -195,6 +195,71 @@ __device__ void block_topk(KeyF key, uint32_t act, int K, ProxSmem& sm) {
   __syncthreads();
 }
 
+// Warm-started selection of the K largest (the same order as block_topk: value desc, index asc)
+// from the K winners of the previous call on this node (prev[0] = K, prev[1..K] = indices). Their
+// current values give a threshold tau = min over them, and at least K elements have a value
+// >= tau, so the K largest all lie in {value >= tau}; those candidates (at most kWarmCap) are
+// ranked exactly. uv[j]: the value of element j (ABS: its magnitude) for every j < E *
+// kProxThreads (an LDS array indexed by element). Returns false, having written nothing in
+// sm.hu / sm.hidx, when there is no usable history or too many candidates; the caller then runs
+// block_topk. On success the winners are stored back into prev for the next call.
+constexpr int kWarmCap = 256;
+template <int E, bool ABS>
+__device__ __noinline__ bool block_topk_warm(const double* uv, uint32_t act, int K, int* prev, ProxSmem& sm) {
+  if (prev == nullptr || prev[0] != K) return false;  // uniform: every thread reads the same word
+  const int tid = threadIdx.x;
+  auto val = [&](int j) { return ABS ? fabs(uv[j]) : uv[j]; };
+  if (tid < 64) {
+    double t = tid < K ? val(prev[1 + tid]) : HUGE_VAL;
+    t = wave_reduce(t, HUGE_VAL, OpMin());
+    if (tid == 0) {
+      sm.b_dbl[0] = t;
+      sm.b_int[0] = 0;
+    }
+  }
+  __syncthreads();
+  const double tau = sm.b_dbl[0];
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const int j = s * kProxThreads + tid;
+    if (!((act >> s) & 1u)) continue;
+    const double v = val(j);
+    if (v >= tau) {
+      const int slot = atomicAdd(&sm.b_int[0], 1);
+      if (slot < kWarmCap) {
+        sm.cand_v[slot] = v;
+        sm.cand_i[slot] = j;
+      }
+    }
+  }
+  __syncthreads();
+  const int c = sm.b_int[0];
+  if (c > kWarmCap || c < K) return false;  // uniform
+  for (int q = tid; q < c; q += blockDim.x) {
+    const double v = sm.cand_v[q];
+    const int i = sm.cand_i[q];
+    int rank = 0;
+    for (int r = 0; r < c; ++r) {
+      const double w = sm.cand_v[r];
+      rank += (w > v || (w == v && sm.cand_i[r] < i)) ? 1 : 0;
+    }
+    if (rank < K) {
+      sm.hu[rank] = v;
+      sm.hidx[rank] = i;
+    }
+  }
+  __syncthreads();
+  if (tid < K) prev[1 + tid] = sm.hidx[tid];
+  return true;
+}
+
+// Record the K winners of a block_topk call for the next warm start.
+__device__ __forceinline__ void topk_remember(int* prev, int K, const ProxSmem& sm) {
+  if (prev == nullptr) return;
+  if (threadIdx.x < K) prev[1 + threadIdx.x] = sm.hidx[threadIdx.x];
+  if (threadIdx.x == 0) prev[0] = K;
+}
+
 // Result of a descending radix selection: selected = key > lo, plus `take` of the keys == lo
 // when `exact`; when !exact, selected = key >= lo (and the count is exactly the requested one).
 struct Select {
@@ -401,7 +466,8 @@ __device__ __forceinline__ uint32_t cls_mask(uint64_t cb, int c) {
 // none). The result is handed to out(s, beta_s) once, element by element, at the end.
 template <int E, typename UF, typename OutF>
 __device__ ProxOut node_prox(UF U, uint32_t neg, uint64_t cb, int kp, int nfree, double rho,
-                             double M, double vhint, OutF out, ProxSmem& sm) {
+                             double M, double vhint, OutF out, ProxSmem& sm,
+                             const double* uv = nullptr, int* prev = nullptr) {
   const uint32_t fm = cls_mask<E>(cb, CLS_FREE);
   auto sgn = [&](int s, double mag) { return ((neg >> s) & 1u) ? -mag : mag; };
   // Z1 coordinates: ridge-and-clip rho w / (1 + rho) clipped to [-M, M]
@@ -428,7 +494,11 @@ __device__ ProxOut node_prox(UF U, uint32_t neg, uint64_t cb, int kp, int nfree,
   uint32_t head = 0;
   double umax_tail;
   if (kp + 1 <= kWaveSel) {
-    block_topk<E>(U, fm, kp + 1, sm);
+    // uv: the u values indexed by element (for the warm start); prev: the last call's winners
+    if (uv == nullptr || !block_topk_warm<E, false>(uv, fm, kp + 1, prev, sm)) {
+      block_topk<E>(U, fm, kp + 1, sm);
+      topk_remember(prev, kp + 1, sm);
+    }
     const double tv = sm.hu[kp - 1];
     const int ti = sm.hidx[kp - 1];
 #pragma unroll
@@ -513,7 +583,7 @@ __device__ ProxOut node_prox(UF U, uint32_t neg, uint64_t cb, int kp, int nfree,
 // on A directly and only the selected values are divided.
 template <int E, typename AF>
 __device__ double gstar_node(AF A, double div, uint64_t cb, int kp, int nfree, double M,
-                             ProxSmem& sm) {
+                             ProxSmem& sm, const double* av = nullptr, int* prev = nullptr) {
   const uint32_t fm = cls_mask<E>(cb, CLS_FREE);
   double z1 = 0.0;
 #pragma unroll
@@ -526,7 +596,11 @@ __device__ double gstar_node(AF A, double div, uint64_t cb, int kp, int nfree, d
       for (int s = 0; s < E; ++s)
         if ((fm >> s) & 1u) top += huber(A(s) / div, M);
     } else if (kp <= kWaveSel) {
-      block_topk<E>(A, fm, kp, sm);
+      // av: signed values indexed by element (A = |av|) for the warm start
+      if (av == nullptr || !block_topk_warm<E, true>(av, fm, kp, prev, sm)) {
+        block_topk<E>(A, fm, kp, sm);
+        topk_remember(prev, kp, sm);
+      }
       if (threadIdx.x == 0)
         for (int r = 0; r < kp; ++r) top += huber(sm.hu[r] / div, M);
     } else {

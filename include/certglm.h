@@ -88,7 +88,9 @@ typedef struct cgl_node {
   int32_t max_iter;     /* iteration cap (>= 1) */
   int32_t check_every;  /* dual monitor period in iterations (>= 1) */
   int32_t precision;    /* enum cgl_precision */
-  const double* warm_start; /* NULL, or p host doubles: the first iterate */
+  const double* warm_start; /* NULL, or p host doubles: the first iterate (fixed-zero entries
+                                are set to 0); with CGL_PREC_MIXED the FP64 base point is
+                                computed there before the first iteration */
   double incumbent;     /* +inf for none; else the early-termination rules of Sec. 4.3 apply */
 } cgl_node;
 

@@ -340,7 +340,10 @@ bool MixedWork::cert_round(Problem& P) {
   }
   if (want.empty()) return false;
   const int nq = (int)want.size();
-  if (nq < kCertBatch && nq < active && cycles - oldest < (int64_t)kCertWait * kChunk) return false;
+  bool parked = false;  // a warm start waiting for its base point cannot wait for others
+  for (int sl : want) parked = parked || st_host[sl].need_base;
+  if (!parked && nq < kCertBatch && nq < active && cycles - oldest < (int64_t)kCertWait * kChunk)
+    return false;
   hipStream_t s = P.ctx->stream;
   cgl_ctx* ctx = P.ctx;
   for (int sl : want) want_since[sl] = -1;
@@ -406,6 +409,13 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
     d.L_prev = HUGE_VAL;
     d.g_new = 0.0;  // g(0)
     if (d.iter >= d.max_iter) d.want_cert = 1;  // no iteration allowed: certify the start
+    if (a.node.warm_start) {
+      // parked until the next FP64 round evaluates the bound at the start and moves the base
+      // point there; its g is not evaluated, so the start never counts as a best primal value
+      d.need_base = 1;
+      d.want_cert = 1;
+      d.g_new = HUGE_VAL;
+    }
     st_host[sl] = d;
     std::copy(a.host.cls.begin(), a.host.cls.end(), cls_host.begin() + (int64_t)sl * ldp);
     std::fill(cls_host.begin() + (int64_t)sl * ldp + P.p, cls_host.begin() + (int64_t)(sl + 1) * ldp,
@@ -415,6 +425,23 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
   CGL_HIP(hipMemcpyAsync(list.ptr, slots.data(), slots.size() * sizeof(int), hipMemcpyHostToDevice, s));
   launch_admit(md, list.as<int>(), (int)slots.size(), H0_cold.as<double>(),
                base0_cold.as<double>(), base1_cold.as<double>(), s);
+  // warm starts (fixed-zero coordinates set to 0) into the iterate ring, the base and the best
+  std::vector<std::vector<double>> starts;
+  for (const Admission& a : adm) {
+    if (!a.node.warm_start) continue;
+    starts.emplace_back(a.node.warm_start, a.node.warm_start + P.p);
+    std::vector<double>& ws = starts.back();
+    for (int64_t j = 0; j < P.p; ++j)
+      if (a.host.cls[(size_t)j] == CLS_ZERO) ws[(size_t)j] = 0.0;
+    const int64_t o = (int64_t)a.slot * ldp;
+    for (int r = 0; r < 3; ++r)
+      CGL_HIP(hipMemcpyAsync(bring.as<double>() + (int64_t)r * S * ldp + o, ws.data(),
+                             (size_t)P.p * 8, hipMemcpyHostToDevice, s));
+    CGL_HIP(hipMemcpyAsync(beta0.as<double>() + o, ws.data(), (size_t)P.p * 8,
+                           hipMemcpyHostToDevice, s));
+    CGL_HIP(hipMemcpyAsync(bres.as<double>() + o, ws.data(), (size_t)P.p * 8,
+                           hipMemcpyHostToDevice, s));
+  }
   CGL_HIP(hipMemcpyAsync(cls.ptr, cls_host.data(), cls_host.size(), hipMemcpyHostToDevice, s));
   CGL_HIP(hipMemcpyAsync(st.ptr, st_host, (size_t)S * sizeof(NodeDev), hipMemcpyHostToDevice, s));
   CGL_HIP(hipStreamSynchronize(s));
@@ -458,8 +485,6 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
   std::vector<NodeHost> hosts;
   hosts.reserve((size_t)count);
   for (int32_t i = 0; i < count; ++i) {
-    if (nodes[i].warm_start)
-      invalid("warm starts are not supported with CGL_PREC_MIXED; use CGL_PREC_F64");
     hosts.push_back(make_node_host(nodes[i], P.p, P.k));
   }
   int32_t next = 0, finished = 0;

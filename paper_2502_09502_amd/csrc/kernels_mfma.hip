@@ -43,7 +43,7 @@ __device__ __forceinline__ double sigmoid_d(double t) {
 // A slot advances while it holds a node that is not finished and has iterations left (a slot at
 // its cap waits for the certification that ends it).
 __device__ __forceinline__ bool slot_running(const NodeDev* st) {
-  return st->active != 0 && st->done == 0 && st->iter < st->max_iter;
+  return st->active != 0 && st->done == 0 && st->need_base == 0 && st->iter < st->max_iter;
 }
 
 // =====================================================================================
@@ -451,6 +451,7 @@ __global__ __launch_bounds__(1024) void k_cert_finish(MixedDev md, const int* li
       st->since_recentre = 0;
     }
     st->want_cert = 0;
+    st->need_base = 0;
   }
   __syncthreads();
   const bool improve = st->b_int0 != 0;

@@ -46,6 +46,7 @@ struct NodeDev {
   int since_recentre;
   int b_int0;        // scratch flag of the certification kernel
   int last_ring;     // ring slot holding the latest prox output (the iterate g_new belongs to)
+  int need_base;     // warm start admitted: parked until an FP64 round sets its base point
 };
 
 constexpr int kRunning = -1;

@@ -89,8 +89,6 @@ def test_mixed_edge_cases():
     root = oracle.solve_node(d.X, d.y, "ls", d.lam2, d.M, d.k, tol=1e-10)
     for q in (3, 4):
         assert r[q].status == "not_converged" and r[q].lower_bound <= root.primal
-    with pytest.raises(_lib.CglError):
-        prob.solve_batch([prob.node(precision="mixed", warm_start=np.zeros(d.p))])
 
 
 def test_config4_subset_full_size():
@@ -110,3 +108,34 @@ def test_config4_subset_full_size():
         assert rel(P, r.primal) <= 1e-10
         assert (P - D) / abs(P) <= 2e-6
         assert r.lower_bound <= P
+
+
+def test_mixed_warm_start_parent_and_incumbent():
+    """Warm starts in the batched engine (the parent's solution, the optimum itself, a random
+    vector outside the domain) reach the same certified objective as the cold solve; incumbent
+    rules stop a node early with a valid bound."""
+    d = synth.make_config("c1")
+    prob = _problem(d)
+    z0, z1 = [2, 11, 30], [4, 44]
+    ref = oracle.solve_node(d.X, d.y, d.loss, d.lam2, d.M, d.k, z0, z1, tol=1e-10)
+    parent = oracle.solve_node(d.X, d.y, d.loss, d.lam2, d.M, d.k, [2], [4], tol=1e-10)
+    rng = np.random.default_rng(7)
+    starts = [ref.beta, parent.beta, 3.0 * rng.standard_normal(d.p)]
+    cold = prob.solve_batch(_specs(prob, [(z0, z1)]))[0]
+    specs = [prob.node(Z0=z0, Z1=z1, tol=1e-6, max_iter=5000, precision="mixed", warm_start=w)
+             for w in starts]
+    res = prob.solve_batch(specs)
+    for r in res:
+        _check(d, r, z0, z1, ref=ref)
+        assert abs(r.primal - cold.primal) <= 2e-6 * max(abs(cold.primal), 1.0)
+    # from the optimum itself the node certifies in far fewer iterations than cold
+    assert res[0].iters < cold.iters
+    # incumbent below the bound: pruned; incumbent above the primal: stop and branch
+    lo = ref.primal * (1.0 - 1e-3)
+    hi = ref.primal * (1.0 + 1e-1)
+    rp, rb = prob.solve_batch([
+        prob.node(Z0=z0, Z1=z1, tol=1e-9, max_iter=5000, precision="mixed", incumbent=lo),
+        prob.node(Z0=z0, Z1=z1, tol=1e-9, max_iter=5000, precision="mixed", incumbent=hi)])
+    assert rp.status == "pruned" and lo < rp.lower_bound <= ref.primal
+    assert rb.status in ("below_incumbent", "converged") and rb.primal < hi
+    assert rb.lower_bound <= ref.primal

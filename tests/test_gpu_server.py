@@ -140,6 +140,8 @@ def test_server_rejects_bad_arguments():
     srv = _lib.Server(ctx(), 0, 8)
     with pytest.raises(_lib.CglError):
         srv.submit(pa, pa.node(Z0=[0], Z1=[0]))  # overlapping sets
-    with pytest.raises(_lib.CglError):
-        srv.submit(pa, pa.node(precision="mixed", warm_start=np.zeros(pa.p)))
+    # a warm-started request is served like any other
+    t = srv.submit(pa, pa.node(precision="mixed", max_iter=5000, warm_start=np.zeros(pa.p)))
+    out = _drain(srv, 1)
+    assert out[t][0].status == "converged"
     srv.close()

@@ -208,6 +208,70 @@ def serve(args):
     print(json.dumps(out))
 
 
+PROX_WORKLOAD = ("standalone prox of g (Fig. 1 setting): gamma ~ N(0, I_p), k=10, M=1, rho=1, "
+                 "p = 100 * 2^i, a batch of vectors per size")
+
+
+def prox_workload(args):
+    """The prox kernel alone (Alg. 1 through the Moreau identity): per-vector latency (one
+    vector per launch) and batched throughput, kernel time from HIP events; the oracle's prox on
+    five seeds per size as the CPU baseline."""
+    ctx = _lib.Context(0)
+    sizes = [100 * 2 ** i for i in range(args.prox_max_i + 1)]
+    batch = args.prox_batch
+    rows = []
+    cpu_s = 0.0
+    cpu_n = 0
+    for p in sizes:
+        W = np.stack([np.random.default_rng([4, p, s]).standard_normal(p) for s in range(batch)])
+        _lib.prox_node_batch(ctx, W[:1], 1.0, 1.0, 10)  # warm-up
+        ctx.set_profiling(True)
+        ctx.kernel_stats(8, reset=True)
+        for _ in range(5):
+            _lib.prox_node_batch(ctx, W[:1], 1.0, 1.0, 10)
+        ms1, n1 = ctx.kernel_stats(8, reset=True)
+        for _ in range(3):
+            _lib.prox_node_batch(ctx, W, 1.0, 1.0, 10)
+        msb, nb = ctx.kernel_stats(8, reset=True)
+        ctx.set_profiling(False)
+        row = {"p": p, "gpu_us_one_vector": round(1e3 * ms1 / n1, 2),
+               "gpu_us_per_vector_batched": round(1e3 * msb / nb / batch, 3),
+               "gpu_vectors_per_s_batched": round(nb * batch / (msb / 1e3), 1)}
+        if not args.no_cpu:
+            import oracle
+            t0 = time.perf_counter()
+            for s in range(5):
+                oracle.prox_g(W[s], 1.0, 1.0, 10)
+            t = time.perf_counter() - t0
+            cpu_s += t
+            cpu_n += 5
+            row["oracle_ms_per_vector"] = round(1e3 * t / 5, 3)
+        rows.append(row)
+    last = rows[-1]
+    out = {
+        "metric": "prox evaluations per second (standalone prox workload)",
+        "value": last["gpu_vectors_per_s_batched"],
+        "unit": "prox/s",
+        "n_gpus": 1,
+        "steps": 3,
+        "warmup": 1,
+        "ms_per_step": round(last["gpu_us_per_vector_batched"] * batch / 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": PROX_WORKLOAD, "batch": batch, "p_max": sizes[-1]},
+        "sizes": rows,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = {"value": round(cpu_n / cpu_s, 3), "unit": "prox/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"oracle prox (stack PAVA) on 5 seeds per size, all sizes "
+                                         f"pooled: {cpu_n} vectors in {cpu_s:.2f} s"}
+    print(json.dumps(out))
+
+
 def copy_calibration(nbytes: int) -> None:
     """One plain device-to-device copy of a known size through the HIP runtime's copy kernel
     (the reference for the traffic counters)."""
@@ -241,8 +305,12 @@ def main():
                     help="nodes of the plain FP64 per-node comparator")
     ap.add_argument("--mode", choices=["auto", "batched", "plain"], default="auto")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=["batched", "serve"], default="batched",
-                    help="batched: the 256-node step (default); serve: the request stream")
+    ap.add_argument("--workload", choices=["batched", "serve", "prox"], default="batched",
+                    help="batched: the 256-node step (default); serve: the request stream; "
+                         "prox: the standalone prox workload")
+    ap.add_argument("--prox-batch", type=int, default=256, help="prox: vectors per launch")
+    ap.add_argument("--prox-max-i", type=int, default=8,
+                    help="prox: sizes p = 100 * 2^i for i = 0..this (the kernel takes p <= 32768)")
     ap.add_argument("--requests", type=int, default=600, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: mean arrivals per second")
     ap.add_argument("--serve-sizes", default="1000,5000,20000", help="serve: dataset p values")
@@ -255,6 +323,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "prox":
+        prox_workload(args)
+        return
     if args.workload == "serve":
         serve(args)
         if args.copy_bytes > 0:

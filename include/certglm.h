@@ -128,7 +128,8 @@ int cgl_ctx_destroy(cgl_ctx* ctx);
  * which: 0 = X^T pass of the plain path (k_xt), 1 = X pass of the plain path (k_xb),
  *        2 = batched BF16 MFMA X^T pass, 3 = batched BF16 MFMA X pass, 4 = batched FP64 pass;
  *        and host wall time of the batched engine's phases (launch to completion):
- *        5 = iteration chunks, 6 = certification rounds, 7 = admission and retirement.
+ *        5 = iteration chunks, 6 = certification rounds, 7 = admission and retirement;
+ *        8 = the prox kernel of cgl_prox_node_batch (one launch per call).
  * cgl_ctx_kernel_stats returns the totals since the last reset (reset = 1 clears them). */
 int cgl_ctx_set_profiling(cgl_ctx* ctx, int32_t on);
 int cgl_ctx_kernel_stats(cgl_ctx* ctx, int32_t which, int32_t reset, double* total_ms,

@@ -436,7 +436,7 @@ int cgl_ctx_kernel_stats(cgl_ctx* ctx, int32_t which, int32_t reset, double* tot
                          int64_t* launches) {
   CGL_API_BEGIN
   if (!ctx) invalid("ctx is NULL");
-  if (which < 0 || which >= 8) invalid("which out of range");
+  if (which < 0 || which >= 16) invalid("which out of range");
   if (total_ms) *total_ms = ctx->kt_ms[which];
   if (launches) *launches = ctx->kt_n[which];
   if (reset) {
@@ -662,12 +662,20 @@ int cgl_prox_node_batch(cgl_ctx* ctx, double rho, double M, int32_t k, const cgl
   CGL_HIP(hipMemcpyAsync(dC.ptr, cls.data(), (size_t)count * p, hipMemcpyHostToDevice, s));
   CGL_HIP(hipMemcpyAsync(dS.ptr, st.data(), (size_t)count * sizeof(NodeDev),
                          hipMemcpyHostToDevice, s));
+  if (ctx->profiling) CGL_HIP(hipEventRecord(ctx->event(0), s));
   launch_prox(count, dW.as<double>(), p, nullptr, 0, dC.as<uint8_t>(), p, p, rho, M, 1.0,
               dS.as<NodeDev>(), dB.as<double>(), 0, p, s);
+  if (ctx->profiling) CGL_HIP(hipEventRecord(ctx->event(1), s));
   CGL_HIP(hipMemcpyAsync(beta_out, dB.ptr, (size_t)count * p * 8, hipMemcpyDeviceToHost, s));
   CGL_HIP(hipMemcpyAsync(st.data(), dS.ptr, (size_t)count * sizeof(NodeDev),
                          hipMemcpyDeviceToHost, s));
   CGL_HIP(hipStreamSynchronize(s));
+  if (ctx->profiling) {
+    float ms = 0.f;
+    CGL_HIP(hipEventElapsedTime(&ms, ctx->event(0), ctx->event(1)));
+    ctx->kt_ms[8] += ms;
+    ctx->kt_n[8] += 1;
+  }
   if (gval_out)
     for (int32_t i = 0; i < count; ++i)
       gval_out[i] = infeasible[(size_t)i] ? HUGE_VAL : st[(size_t)i].g_new;

@@ -19,8 +19,8 @@ struct cgl_ctx {
   bool own_stream = false;
   // kernel timing (cgl_ctx_set_profiling)
   bool profiling = false;
-  double kt_ms[8] = {0};
-  int64_t kt_n[8] = {0};
+  double kt_ms[16] = {0};
+  int64_t kt_n[16] = {0};
   std::vector<hipEvent_t> events;  // pool, grown on demand
   hipEvent_t event(size_t i);
   // split-K choices of the batched products found by timing, by (pass, M, K, nodes)

@@ -68,3 +68,11 @@ def test_prox_rejects_head_beyond_capacity():
     W = np.zeros((1, 3000))
     with pytest.raises(_lib.CglError):
         _lib.prox_node_batch(ctx(), W, 1.0, 1.0, 257)
+
+
+@pytest.mark.parametrize("p", [100, 800, 6400, 25600])
+def test_prox_standalone_workload_distribution(p):
+    """The standalone prox workload's inputs (Fig. 1 setting: gamma ~ N(0, I_p), k = 10, M = 1,
+    rho = 1), five seeds per size, element by element against the oracle."""
+    W = np.stack([np.random.default_rng([4, p, s]).standard_normal(p) for s in range(5)])
+    _check(W, 1.0, 1.0, 10)

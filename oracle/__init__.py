@@ -9,6 +9,7 @@ from .core import (  # noqa: F401
     NOT_CONVERGED,
     LeastSquares,
     Logistic,
+    SquaredHinge,
     NodeResult,
     NodeSets,
     brute_force_mip,

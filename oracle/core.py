@@ -314,6 +314,35 @@ class Logistic:
         return 0.25
 
 
+class SquaredHinge:
+    """f(u, y) = sum max(0, 1 - y_i u_i)^2, y in {-1, +1};
+    F*(-zeta) = sum h(-y_i zeta_i) with h(z) = z + z^2/4 for z <= 0 and +inf for z > 0
+    (App. D.1). The derivative -2 y max(0, 1 - y u) is 2-Lipschitz in u."""
+
+    name = "sqhinge"
+
+    @staticmethod
+    def f(u, y):
+        m = np.maximum(0.0, 1.0 - y * np.asarray(u, dtype=np.float64))
+        return float(m @ m)
+
+    @staticmethod
+    def grad(u, y):
+        return -2.0 * y * np.maximum(0.0, 1.0 - y * np.asarray(u, dtype=np.float64))
+
+    @staticmethod
+    def conj_neg(zeta, y, slack=1e-15):
+        z = -y * np.asarray(zeta, dtype=np.float64)
+        if np.any(z > slack):
+            return math.inf
+        z = np.minimum(z, 0.0)
+        return float(np.sum(z + 0.25 * z * z))
+
+    @staticmethod
+    def lipschitz_factor():
+        return 2.0
+
+
 def _sigmoid(t):
     t = np.asarray(t, dtype=np.float64)
     out = np.empty_like(t)
@@ -324,7 +353,7 @@ def _sigmoid(t):
     return out
 
 
-LOSSES = {"ls": LeastSquares, "logistic": Logistic}
+LOSSES = {"ls": LeastSquares, "logistic": Logistic, "sqhinge": SquaredHinge}
 
 
 def get_loss(loss):
@@ -527,18 +556,17 @@ def _box_ridge_ls(XS, y, lam2, M):
     return best
 
 
-def _box_ridge_logistic(XS, y, lam2, M):
+def _box_ridge_smooth(XS, y, lam2, M, loss):
+    """min_{|b|_inf <= M} f(XS b) + lambda2 ||b||^2 for a smooth loss (L-BFGS-B with bounds)."""
     from scipy.optimize import minimize
 
     s = XS.shape[1]
     if s == 0:
-        return float(np.sum(np.logaddexp(0.0, 0.0 * y))), np.zeros(0)
+        return loss.f(np.zeros(len(y)), y), np.zeros(0)
 
     def fun(b):
         u = XS @ b
-        val = np.sum(np.logaddexp(0.0, -y * u)) + lam2 * b @ b
-        g = XS.T @ (-y * _sigmoid(-y * u)) + 2 * lam2 * b
-        return val, g
+        return loss.f(u, y) + lam2 * b @ b, XS.T @ loss.grad(u, y) + 2 * lam2 * b
 
     res = minimize(fun, np.zeros(s), jac=True, method="L-BFGS-B", bounds=[(-M, M)] * s,
                    options={"ftol": 1e-15, "gtol": 1e-12, "maxiter": 10000})
@@ -555,7 +583,8 @@ def brute_force_mip(X, y, loss, lam2, M, k, Z0=(), Z1=()):
     ns = node_sets(p, Z0, Z1)
     if ns.one.size > k:
         return math.inf
-    solver = _box_ridge_ls if loss is LeastSquares else _box_ridge_logistic
+    solver = _box_ridge_ls if loss is LeastSquares else (
+        lambda XS, yy, l2, MM: _box_ridge_smooth(XS, yy, l2, MM, loss))
     best = math.inf
     for extra in range(0, k - ns.one.size + 1):
         for comb in itertools.combinations(ns.free.tolist(), extra):

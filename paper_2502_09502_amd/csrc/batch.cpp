@@ -15,6 +15,7 @@
 #include "common.h"
 #include "engine.h"
 #include "kernels.h"
+#include "losses.h"
 #include "mixed.h"
 #include "prox.h"
 
@@ -114,13 +115,13 @@ void MixedWork::ensure(Problem& P) {
     std::vector<double> h((size_t)ldp), yv((size_t)P.n);
     CGL_HIP(hipMemcpy(h.data(), H0_cold.ptr, (size_t)ldp * 8, hipMemcpyDeviceToHost));
     CGL_HIP(hipMemcpy(yv.data(), P.y.ptr, (size_t)P.n * 8, hipMemcpyDeviceToHost));
-    const double f = P.loss == LOSS_LS ? -2.0 : -0.5;
+    const double f = loss_grad0_factor(P.loss);  // r_0 = grad f(0) = f * y
     for (auto& v : h) v *= f;
     CGL_HIP(hipMemcpy(H0_cold.ptr, h.data(), (size_t)ldp * 8, hipMemcpyHostToDevice));
     std::vector<double> b0((size_t)n_pad, 0.0), b1((size_t)n_pad, 0.0);
     for (int64_t i = 0; i < P.n; ++i) {
       if (P.loss == LOSS_LS) b0[(size_t)i] = -yv[(size_t)i];  // e_0 = 0 - y
-      else b1[(size_t)i] = -0.5 * yv[(size_t)i];              // r_0 = -y sigmoid(0)
+      else b1[(size_t)i] = f * yv[(size_t)i];                 // r_0, with u_0 = 0
     }
     base0_cold.alloc((size_t)n_pad * 8);
     base1_cold.alloc((size_t)n_pad * 8);
@@ -128,7 +129,7 @@ void MixedWork::ensure(Problem& P) {
     CGL_HIP(hipMemcpy(base1_cold.ptr, b1.data(), (size_t)n_pad * 8, hipMemcpyHostToDevice));
     double f0 = 0.0;
     for (int64_t i = 0; i < P.n; ++i)
-      f0 += P.loss == LOSS_LS ? yv[(size_t)i] * yv[(size_t)i] : std::log(2.0);
+      f0 += loss_at0(P.loss, yv[(size_t)i]);
     f_cold = f0;
   }
   CGL_HIP(hipHostMalloc(&st_host, (size_t)S * sizeof(NodeDev), hipHostMallocDefault));

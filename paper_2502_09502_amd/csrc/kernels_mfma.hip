@@ -23,6 +23,7 @@
 #include "kernels.h"
 #include "gemm_bf16.h"
 #include "gemm_f64.h"
+#include "losses.h"
 #include "mixed.h"
 #include "prox.h"
 #include "solver.h"
@@ -31,14 +32,7 @@ namespace cgl {
 
 typedef __attribute__((__vector_size__(4 * sizeof(double)))) double doublex4;
 
-__device__ __forceinline__ double softplus_d(double t) {
-  return t > 0.0 ? t + log1p(exp(-t)) : log1p(exp(t));
-}
-__device__ __forceinline__ double sigmoid_d(double t) {
-  if (t >= 0.0) return 1.0 / (1.0 + exp(-t));
-  const double e = exp(t);
-  return e / (1.0 + e);
-}
+
 
 // A slot advances while it holds a node that is not finished and has iterations left (a slot at
 // its cap waits for the certification that ends it).
@@ -111,8 +105,8 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
     dun[i] = du;
     if (i < md.n) {
       const double u = md.base0[(int64_t)slot * md.n_pad + i] + (double)du;
-      if (md.loss == LOSS_LS) ls += u * u;  // base0 holds e_0 = u_0 - y
-      else ls += softplus_d(-md.y[i] * u);  // base0 holds u_0
+      if (md.loss == LOSS_LS) ls += u * u;      // base0 holds e_0 = u_0 - y
+      else ls += loss_val(md.loss, u, md.y[i]);  // base0 holds u_0
     }
   }
   ls = block_reduce(ls, red, OpAdd(), 0.0);
@@ -172,12 +166,10 @@ __global__ __launch_bounds__(256) void k_mixed_resid(MixedDev md) {
         const double r = 2.0 * e;
         fs += 0.25 * r * r + y * r;  // F*(-zeta), zeta = -r: ||zeta||^2/4 - y.zeta
         gv = float_to_bf16((float)(2.0 * dg));
-      } else {
+      } else {  // base0 holds u_0, base1 holds r_0 = grad f(u_0)
         const double u = md.base0[(int64_t)slot * md.n_pad + i] + dg;
-        const double t = -y * u;
-        const double q = sigmoid_d(t);
-        const double r = -y * q;
-        fs += -q * softplus_d(-t) - (1.0 - q) * softplus_d(t);
+        const double r = loss_grad(md.loss, u, y);
+        fs += fstar_term(md.loss, u, y);
         gv = float_to_bf16((float)(r - md.base1[(int64_t)slot * md.n_pad + i]));
       }
     }
@@ -362,11 +354,9 @@ __global__ __launch_bounds__(256) void k_cert_resid(MixedDev md, const int* list
         fs += 0.25 * r * r + y * r;
         b0 = e;
       } else {
-        const double t = -y * u;
-        const double qq = sigmoid_d(t);
-        r = -y * qq;
-        ls += softplus_d(t);
-        fs += -qq * softplus_d(-t) - (1.0 - qq) * softplus_d(t);
+        r = loss_grad(md.loss, u, y);
+        ls += loss_val(md.loss, u, y);
+        fs += fstar_term(md.loss, u, y);
         b0 = u;
         b1 = r;
       }

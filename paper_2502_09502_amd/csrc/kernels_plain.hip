@@ -8,42 +8,11 @@
 // X gamma is never formed: by linearity X gamma = u^t + c (u^t - u^{t-1}).
 #include "common.h"
 #include "kernels.h"
+#include "losses.h"
 #include "prox.h"
 #include "solver.h"
 
 namespace cgl {
-
-// ------------------------------------------------------------------ elementwise loss maths
-
-__device__ __forceinline__ double softplus(double t) {
-  return t > 0.0 ? t + log1p(exp(-t)) : log1p(exp(t));
-}
-__device__ __forceinline__ double sigmoid(double t) {
-  if (t >= 0.0) return 1.0 / (1.0 + exp(-t));
-  const double e = exp(t);
-  return e / (1.0 + e);
-}
-// f_i(u) (problem (1); App. D.1)
-__device__ __forceinline__ double loss_val(int loss, double u, double y) {
-  if (loss == LOSS_LS) { const double r = u - y; return r * r; }
-  return softplus(-y * u);
-}
-// d f_i / du
-__device__ __forceinline__ double loss_grad(int loss, double u, double y) {
-  if (loss == LOSS_LS) return 2.0 * (u - y);
-  return -y * sigmoid(-y * u);
-}
-// F_i*(-zeta_i) at zeta_i = -grad f_i(u) (App. D.1): least squares 1/4 zeta^2 - y zeta;
-// logistic q log q + (1 - q) log(1 - q) with q = y zeta = sigmoid(-y u), written with softplus.
-__device__ __forceinline__ double fstar_term(int loss, double u, double y) {
-  if (loss == LOSS_LS) {
-    const double z = -2.0 * (u - y);
-    return 0.25 * z * z - y * z;
-  }
-  const double t = -y * u;
-  const double q = sigmoid(t);
-  return -q * softplus(-t) - (1.0 - q) * softplus(t);
-}
 
 // ------------------------------------------------------------------ vector loads of X
 

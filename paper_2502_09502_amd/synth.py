@@ -9,7 +9,7 @@ paper's experimental setup (App. B.2) with these readings:
 * beta* has k ones at the 0-based positions m * (p // k) - 1, m = 1..k (the paper's
   "j mod (p/k) = 0" in 1-based indexing);
 * least squares: y = X beta* + sigma * eps with sigma^2 = ||X beta*||^2 / (n * SNR), SNR = 5;
-* logistic: y_i = +1 with probability sigmoid(x_i^T beta*), else -1;
+* logistic and squared hinge: y_i = +1 with probability sigmoid(x_i^T beta*), else -1;
 * lower-precision storage: FP32 = round-to-nearest-even of the FP64 values, BF16 = RNE of the
   FP32 values. When a problem is stored in FP32 or BF16, those rounded values ARE the problem.
 
@@ -22,7 +22,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-LOSS_ID = {"ls": 0, "logistic": 1}
+LOSS_ID = {"ls": 0, "logistic": 1, "sqhinge": 2}
 
 
 # ---------------------------------------------------------------------------------------------
@@ -76,7 +76,7 @@ def labels(X: np.ndarray, b_star: np.ndarray, loss: str, rng: np.random.Generato
     if loss == "ls":
         sigma = np.sqrt(float(u @ u) / (n * snr))
         return u + sigma * rng.standard_normal(n)
-    if loss == "logistic":
+    if loss in ("logistic", "sqhinge"):  # classification labels in {-1, +1}
         prob = 1.0 / (1.0 + np.exp(-u))
         return np.where(rng.random(n) < prob, 1.0, -1.0)
     raise ValueError(loss)

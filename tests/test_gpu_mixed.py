@@ -35,7 +35,7 @@ def _check(d, res, z0, z1, ref=None, tol=1e-6):
     assert rel(Pb, res.primal) <= 1e-10
 
 
-@pytest.mark.parametrize("loss", ["ls", "logistic"])
+@pytest.mark.parametrize("loss", ["ls", "logistic", "sqhinge"])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_small_batch_matches_oracle(loss, dtype):
     d = synth.make_dataset(500, 200, 8, loss=loss, dtype=dtype, config_id=80)

@@ -39,7 +39,7 @@ def test_lipschitz_power_iteration():
     assert ref <= prob.L <= ref * 1.0025
 
 
-@pytest.mark.parametrize("loss", ["ls", "logistic"])
+@pytest.mark.parametrize("loss", ["ls", "logistic", "sqhinge"])
 def test_certify_matches_oracle(loss):
     d = synth.make_dataset(300, 90, 5, loss=loss, config_id=71)
     prob = _problem(d)
@@ -66,10 +66,10 @@ def _compare(d, res, ref, ns, tol=1e-6):
     assert rel(Pb, res.primal) <= 1e-10
 
 
-@pytest.mark.parametrize("loss", ["ls", "logistic"])
+@pytest.mark.parametrize("loss", ["ls", "logistic", "sqhinge"])
 def test_config1_root(loss):
     d = synth.make_config("c1") if loss == "ls" else synth.make_dataset(
-        200, 50, 5, loss="logistic", config_id=1)
+        200, 50, 5, loss=loss, config_id=1)
     ref = oracle.solve_node(d.X, d.y, loss, d.lam2, d.M, d.k, tol=1e-9)
     res = _problem(d).solve(tol=1e-6)
     _compare(d, res, ref, oracle.node_sets(d.p))

@@ -18,7 +18,7 @@ def _tiny(n=20, p=8, loss="ls", seed=0):
 # ------------------------------------------------------------------------------- losses
 
 
-@pytest.mark.parametrize("loss", ["ls", "logistic"])
+@pytest.mark.parametrize("loss", ["ls", "logistic", "sqhinge"])
 def test_loss_gradient_finite_difference(loss):
     rng = np.random.default_rng(1)
     y = rng.normal(size=7) if loss == "ls" else rng.choice([-1.0, 1.0], size=7)
@@ -32,7 +32,7 @@ def test_loss_gradient_finite_difference(loss):
         assert g[i] == pytest.approx(fd, rel=1e-6, abs=1e-8)
 
 
-@pytest.mark.parametrize("loss", ["ls", "logistic"])
+@pytest.mark.parametrize("loss", ["ls", "logistic", "sqhinge"])
 def test_loss_conjugate_fenchel_young_and_sup(loss):
     """F(u) + F*(s) = s^T u at s = grad F(u); F*(s) = sup_u s^T u - F(u) (coordinatewise)."""
     rng = np.random.default_rng(2)
@@ -62,7 +62,7 @@ def test_logistic_conjugate_domain():
 # ------------------------------------------------------------------------------- dual bound
 
 
-@pytest.mark.parametrize("loss", ["ls", "logistic"])
+@pytest.mark.parametrize("loss", ["ls", "logistic", "sqhinge"])
 def test_weak_duality_random_points(loss):
     d = _tiny(loss=loss)
     ns = oracle.node_sets(d.p, Z0=[1], Z1=[4])
@@ -72,8 +72,10 @@ def test_weak_duality_random_points(loss):
         P = oracle.primal_value(d.X, d.y, loss, d.lam2, d.M, d.k, ns, beta)
         if loss == "ls":
             zeta = rng.normal(size=d.n) * 2
-        else:
+        elif loss == "logistic":
             zeta = d.y * rng.uniform(0, 1, size=d.n)
+        else:  # squared hinge: -y zeta <= 0
+            zeta = d.y * rng.uniform(0, 3, size=d.n)
         D = oracle.dual_value(d.X, d.y, loss, d.lam2, d.M, d.k, ns, zeta)
         assert D <= P + 1e-9
 
@@ -155,7 +157,7 @@ def _l1_relaxation(X, y, loss, lam2, M, k, Z0=()):
     return float(res.fun)
 
 
-@pytest.mark.parametrize("loss", ["ls", "logistic"])
+@pytest.mark.parametrize("loss", ["ls", "logistic", "sqhinge"])
 @pytest.mark.parametrize("seed", range(4))
 def test_bound_sandwich_brute_force(loss, seed):
     """P_l1 <= P_conv ~ D <= P_MIP: the certified bound is valid (never above the exact k-sparse
@@ -208,6 +210,7 @@ def test_lipschitz_matches_eigenvalue_and_lanczos_path():
     assert oracle.lambda_max_gram(X) == pytest.approx(lam, rel=1e-10)  # Lanczos branch (p > 2000)
     assert oracle.lipschitz(X, "ls") == pytest.approx(2 * lam, rel=1e-10)
     assert oracle.lipschitz(X, "logistic") == pytest.approx(lam / 4, rel=1e-10)
+    assert oracle.lipschitz(X, "sqhinge") == pytest.approx(2 * lam, rel=1e-10)
 
 
 def test_budget_exhausted_by_fixed_in_set():
@@ -224,3 +227,14 @@ def test_budget_exhausted_by_fixed_in_set():
     assert r.primal == pytest.approx(ref, rel=1e-9)
     free = [j for j in range(40) if j not in Z1]
     assert np.all(r.beta[free] == 0.0)
+
+
+def test_squared_hinge_conjugate_closed_form_and_domain():
+    """One coordinate by hand (y = 1): f(u) = (1 - u)^2 for u < 1; at u = 0.5 the slope is
+    s = -1 and F*(s) = sup_t s t - f(t) is attained at t = 1 + s/2 = 0.5: -0.5 - 0.25 = -0.75,
+    which is h(-y zeta) = h(s) = s + s^2/4 with zeta = -s. Outside the domain (-y zeta > 0) the
+    conjugate is infinite."""
+    y = np.array([1.0])
+    assert oracle.SquaredHinge.conj_neg(np.array([1.0]), y) == pytest.approx(-0.75, abs=1e-15)
+    assert oracle.SquaredHinge.conj_neg(np.array([-0.5]), y) == math.inf
+    assert oracle.SquaredHinge.f(np.array([2.0]), y) == 0.0  # margin met: no loss

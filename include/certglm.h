@@ -8,7 +8,7 @@
  *     min_beta f(X beta, y) + lambda2 ||beta||_2^2   s.t.  ||beta||_inf <= M,  ||beta||_0 <= k,
  *
  * with f the least-squares loss ||u - y||^2, the logistic loss sum log(1 + exp(-y_i u_i)) or the
- * squared hinge loss sum max(0, 1 - y_i u_i)^2 (App. D.1).
+ * squared hinge loss sum max(0, 1 - y_i u_i)^2, or the Poisson and Gamma losses (App. D.1).
  * A node fixes z_j = 0 on a set Z0 and z_j = 1 on a set Z1 in the perspective relaxation
  * P_conv of Sec. 2; this library solves that relaxation by restarted FISTA (Alg. 3) with the
  * exact prox of Alg. 1 (via the Moreau identity of Sec. 3.3) and the value of g from Alg. 2,
@@ -49,7 +49,13 @@ enum cgl_status {
 
 enum cgl_dtype { CGL_F64 = 0, CGL_F32 = 1, CGL_BF16 = 2 };
 enum cgl_mem { CGL_MEM_HOST = 0, CGL_MEM_DEVICE = 1 };
-enum cgl_loss { CGL_LOSS_LS = 0, CGL_LOSS_LOGISTIC = 1, CGL_LOSS_SQHINGE = 2 };
+enum cgl_loss {
+  CGL_LOSS_LS = 0,
+  CGL_LOSS_LOGISTIC = 1,
+  CGL_LOSS_SQHINGE = 2,
+  CGL_LOSS_POISSON = 3, /* sum exp(u_i) - y_i u_i, y_i >= 0; needs an explicit L */
+  CGL_LOSS_GAMMA = 4    /* sum y_i exp(-u_i) + u_i, y_i > 0; needs an explicit L */
+};
 
 /* Arithmetic of the iteration. Every bound is certified in FP64 either way.
  *   CGL_PREC_F64:   FP64 iterates and FP64 products with X in its stored precision
@@ -142,15 +148,16 @@ int cgl_ctx_kernel_stats(cgl_ctx* ctx, int32_t which, int32_t reset, double* tot
  *   X      : n x p row-major, leading dimension ldx >= p, element type x_dtype (F64, F32, or
  *            BF16 as raw 16-bit patterns); x_mem says whether X is a host or a device pointer.
  *            The values given ARE the problem (a BF16 X is not an approximation of anything).
- *   y      : n host doubles (logistic and squared hinge: each -1 or +1).
+ *   y      : n host doubles (logistic and squared hinge: each -1 or +1; Poisson >= 0; Gamma > 0).
  *   loss   : enum cgl_loss.  lambda2 > 0, M > 0, k >= 1.
  *   L      : Lipschitz constant of grad F (Alg. 3); L <= 0 asks the library to compute it
  *            (power iteration on X^T X in FP64, times 2 for least squares and squared hinge,
- *            / 4 for logistic,
- *            then enlarged by a safety factor of 1.002).
+ *            / 4 for logistic, then enlarged by a safety factor of 1.002); Poisson and Gamma
+ *            have no global constant and need L > 0.
  * The library copies X (in its stored precision, plus a transposed BF16 copy for the mixed
  * path) and y into device memory it owns. Errors: CGL_E_INVAL (n, p < 1; p > 32768; ldx < p;
- * lambda2 <= 0; M <= 0; k < 1; non-finite y; classification y not in {-1, +1}), CGL_E_NOMEM. */
+ * lambda2 <= 0; M <= 0; k < 1; non-finite y; y outside the loss's range; L <= 0 for Poisson
+ * or Gamma), CGL_E_NOMEM. */
 int cgl_problem_create(cgl_ctx* ctx, const void* X, int32_t x_dtype, int32_t x_mem, int64_t n,
                        int64_t p, int64_t ldx, const double* y, int32_t loss, double lambda2,
                        double M, int32_t k, double L, cgl_problem** out);

@@ -10,6 +10,8 @@ from .core import (  # noqa: F401
     LeastSquares,
     Logistic,
     SquaredHinge,
+    Poisson,
+    Gamma,
     NodeResult,
     NodeSets,
     brute_force_mip,

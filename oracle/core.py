@@ -343,6 +343,67 @@ class SquaredHinge:
         return 2.0
 
 
+def _h_entropy(z):
+    """h(z) = z log z - z for z > 0, h(0) = 0, +inf for z < 0 (App. D.1)."""
+    z = np.asarray(z, dtype=np.float64)
+    if np.any(z < 0):
+        return math.inf
+    return float(np.sum(_xlogx(z) - z))
+
+
+class Poisson:
+    """f(u, y) = sum exp(u_i) - y_i u_i, y_i >= 0; F*(-zeta) = sum h(y_i - zeta_i) (App. D.1).
+    The derivative exp(u) - y has no global Lipschitz constant: L must be supplied."""
+
+    name = "poisson"
+
+    @staticmethod
+    def f(u, y):
+        u = np.asarray(u, dtype=np.float64)
+        return float(np.sum(np.exp(u) - y * u))
+
+    @staticmethod
+    def grad(u, y):
+        return np.exp(np.asarray(u, dtype=np.float64)) - y
+
+    @staticmethod
+    def conj_neg(zeta, y):
+        return _h_entropy(y - np.asarray(zeta, dtype=np.float64))
+
+    @staticmethod
+    def lipschitz_factor():
+        raise ValueError("the Poisson loss has no global Lipschitz constant; give L")
+
+
+class Gamma:
+    """f(u, y) = sum y_i exp(-u_i) + u_i, y_i > 0. Its conjugate, from the definition:
+    f_i*(s) = sup_u (s - 1) u - y_i exp(-u) = y_i h((1 - s) / y_i), so F*(-zeta) =
+    sum y_i h((1 + zeta_i) / y_i) (App. D.1 prints the argument with the other sign of zeta).
+    The derivative 1 - y exp(-u) has no global Lipschitz constant: L must be supplied."""
+
+    name = "gamma"
+
+    @staticmethod
+    def f(u, y):
+        u = np.asarray(u, dtype=np.float64)
+        return float(np.sum(y * np.exp(-u) + u))
+
+    @staticmethod
+    def grad(u, y):
+        return 1.0 - y * np.exp(-np.asarray(u, dtype=np.float64))
+
+    @staticmethod
+    def conj_neg(zeta, y):
+        z = (1.0 + np.asarray(zeta, dtype=np.float64)) / y
+        if np.any(z < 0):
+            return math.inf
+        return float(np.sum(y * (_xlogx(z) - z)))
+
+    @staticmethod
+    def lipschitz_factor():
+        raise ValueError("the Gamma loss has no global Lipschitz constant; give L")
+
+
 def _sigmoid(t):
     t = np.asarray(t, dtype=np.float64)
     out = np.empty_like(t)
@@ -353,7 +414,8 @@ def _sigmoid(t):
     return out
 
 
-LOSSES = {"ls": LeastSquares, "logistic": Logistic, "sqhinge": SquaredHinge}
+LOSSES = {"ls": LeastSquares, "logistic": Logistic, "sqhinge": SquaredHinge,
+          "poisson": Poisson, "gamma": Gamma}
 
 
 def get_loss(loss):

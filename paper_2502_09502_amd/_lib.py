@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libcertglm.so")
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_BUSY, E_NOTFOUND, E_INTERNAL = range(7)
 F64, F32, BF16 = 0, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
-LOSS = {"ls": 0, "logistic": 1, "sqhinge": 2}
+LOSS = {"ls": 0, "logistic": 1, "sqhinge": 2, "poisson": 3, "gamma": 4}
 PREC = {"f64": 0, "mixed": 1}
 STATUS = {0: "converged", 1: "not_converged", 2: "infeasible", 3: "numeric", 4: "cancelled",
           5: "pruned", 6: "below_incumbent"}

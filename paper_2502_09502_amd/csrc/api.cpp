@@ -461,15 +461,18 @@ int cgl_problem_create(cgl_ctx* ctx, const void* X, int32_t x_dtype, int32_t x_m
   if (ldx < p) invalid("ldx < p");
   if (x_dtype != CGL_F64 && x_dtype != CGL_F32 && x_dtype != CGL_BF16) invalid("bad x_dtype");
   if (x_mem != CGL_MEM_HOST && x_mem != CGL_MEM_DEVICE) invalid("bad x_mem");
-  if (loss != CGL_LOSS_LS && loss != CGL_LOSS_LOGISTIC && loss != CGL_LOSS_SQHINGE)
-    invalid("bad loss");
+  if (loss < CGL_LOSS_LS || loss > CGL_LOSS_GAMMA) invalid("bad loss");
+  if ((loss == CGL_LOSS_POISSON || loss == CGL_LOSS_GAMMA) && !(L > 0.0))
+    invalid("the Poisson and Gamma losses have no global Lipschitz constant: give L > 0");
   if (!(lambda2 > 0.0) || !std::isfinite(lambda2)) invalid("lambda2 must be > 0");
   if (!(M > 0.0) || !std::isfinite(M)) invalid("M must be > 0");
   if (k < 1) invalid("k must be >= 1");
   for (int64_t i = 0; i < n; ++i) {
     if (!std::isfinite(y[i])) invalid("non-finite y");
-    if (loss != CGL_LOSS_LS && y[i] != 1.0 && y[i] != -1.0)
+    if ((loss == CGL_LOSS_LOGISTIC || loss == CGL_LOSS_SQHINGE) && y[i] != 1.0 && y[i] != -1.0)
       invalid("classification labels must be -1 or +1");
+    if (loss == CGL_LOSS_POISSON && y[i] < 0.0) invalid("Poisson responses must be >= 0");
+    if (loss == CGL_LOSS_GAMMA && !(y[i] > 0.0)) invalid("Gamma responses must be > 0");
   }
   CGL_HIP(hipSetDevice(ctx->device));
   std::unique_ptr<Problem> P(new Problem());
@@ -478,7 +481,7 @@ int cgl_problem_create(cgl_ctx* ctx, const void* X, int32_t x_dtype, int32_t x_m
   P->p = p;
   P->ldx = pad_cols(p);
   P->xtype = x_dtype == CGL_F64 ? XT_F64 : (x_dtype == CGL_F32 ? XT_F32 : XT_BF16);
-  P->loss = loss == CGL_LOSS_LS ? LOSS_LS : (loss == CGL_LOSS_LOGISTIC ? LOSS_LOGISTIC : LOSS_SQHINGE);
+  P->loss = loss;  // enum cgl_loss and LossKind share their values
   P->lam2 = lambda2;
   P->M = M;
   P->k = k;

@@ -100,28 +100,28 @@ void MixedWork::ensure(Problem& P) {
   ncchunk = (int)((n_pad + cchunk - 1) / cchunk);
   cpart.alloc((size_t)S * ncchunk * 16);
   list.alloc((size_t)S * sizeof(int));
-  // cold-start base: u_0 = 0, r_0 = grad f(0) (least squares -2y, logistic -y/2),
-  // H_0 = X^T r_0 in FP64
+  // cold-start base: u_0 = 0, r_0 = grad f(0) = a + b y (per loss), H_0 = X^T r_0 in FP64
   {
     const PlainGeom g = plain_geometry(P.xtype, P.n, P.ldx);
-    DevBuf part;
+    std::vector<double> yv((size_t)P.n), r0((size_t)P.n);
+    CGL_HIP(hipMemcpy(yv.data(), P.y.ptr, (size_t)P.n * 8, hipMemcpyDeviceToHost));
+    const double ga = loss_grad0_a(P.loss), gb = loss_grad0_b(P.loss);
+    for (int64_t i = 0; i < P.n; ++i) r0[(size_t)i] = ga + gb * yv[(size_t)i];
+    DevBuf part, dr0;
     part.alloc((size_t)g.nchunks * P.ldx * 8);
+    dr0.alloc((size_t)P.n * 8);
+    CGL_HIP(hipMemcpy(dr0.ptr, r0.data(), (size_t)P.n * 8, hipMemcpyHostToDevice));
     H0_cold.alloc((size_t)ldp * 8);
-    launch_xt(P.xtype, P.X.ptr, P.ldx, P.n, P.ldx, g, P.y.as<double>(), 0, nullptr, nullptr, 0,
+    CGL_HIP(hipMemsetAsync(H0_cold.ptr, 0, (size_t)ldp * 8, s));
+    launch_xt(P.xtype, P.X.ptr, P.ldx, P.n, P.ldx, g, dr0.as<double>(), 0, nullptr, nullptr, 0,
               1, part.as<double>(), nullptr, s);
     launch_grad_step(part.as<double>(), g.nchunks, P.ldx, nullptr, nullptr, 0, 0.0,
                      H0_cold.as<double>(), nullptr, s);
     CGL_HIP(hipStreamSynchronize(s));
-    std::vector<double> h((size_t)ldp), yv((size_t)P.n);
-    CGL_HIP(hipMemcpy(h.data(), H0_cold.ptr, (size_t)ldp * 8, hipMemcpyDeviceToHost));
-    CGL_HIP(hipMemcpy(yv.data(), P.y.ptr, (size_t)P.n * 8, hipMemcpyDeviceToHost));
-    const double f = loss_grad0_factor(P.loss);  // r_0 = grad f(0) = f * y
-    for (auto& v : h) v *= f;
-    CGL_HIP(hipMemcpy(H0_cold.ptr, h.data(), (size_t)ldp * 8, hipMemcpyHostToDevice));
     std::vector<double> b0((size_t)n_pad, 0.0), b1((size_t)n_pad, 0.0);
     for (int64_t i = 0; i < P.n; ++i) {
       if (P.loss == LOSS_LS) b0[(size_t)i] = -yv[(size_t)i];  // e_0 = 0 - y
-      else b1[(size_t)i] = f * yv[(size_t)i];                 // r_0, with u_0 = 0
+      else b1[(size_t)i] = r0[(size_t)i];                      // r_0, with u_0 = 0
     }
     base0_cold.alloc((size_t)n_pad * 8);
     base1_cold.alloc((size_t)n_pad * 8);

@@ -7,7 +7,7 @@
 
 namespace cgl {
 
-enum LossKind : int { LOSS_LS = 0, LOSS_LOGISTIC = 1, LOSS_SQHINGE = 2 };
+enum LossKind : int { LOSS_LS = 0, LOSS_LOGISTIC = 1, LOSS_SQHINGE = 2, LOSS_POISSON = 3, LOSS_GAMMA = 4 };
 enum XType : int { XT_F64 = 0, XT_F32 = 1, XT_BF16 = 2 };
 
 // Per-node iteration state of Alg. 3, resident in device memory.

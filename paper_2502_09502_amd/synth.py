@@ -10,6 +10,7 @@ paper's experimental setup (App. B.2) with these readings:
   "j mod (p/k) = 0" in 1-based indexing);
 * least squares: y = X beta* + sigma * eps with sigma^2 = ||X beta*||^2 / (n * SNR), SNR = 5;
 * logistic and squared hinge: y_i = +1 with probability sigmoid(x_i^T beta*), else -1;
+* Poisson: counts with mean exp(x_i^T beta*); Gamma: shape-2 responses with that mean;
 * lower-precision storage: FP32 = round-to-nearest-even of the FP64 values, BF16 = RNE of the
   FP32 values. When a problem is stored in FP32 or BF16, those rounded values ARE the problem.
 
@@ -22,7 +23,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-LOSS_ID = {"ls": 0, "logistic": 1, "sqhinge": 2}
+LOSS_ID = {"ls": 0, "logistic": 1, "sqhinge": 2, "poisson": 3, "gamma": 4}
 
 
 # ---------------------------------------------------------------------------------------------
@@ -79,6 +80,10 @@ def labels(X: np.ndarray, b_star: np.ndarray, loss: str, rng: np.random.Generato
     if loss in ("logistic", "sqhinge"):  # classification labels in {-1, +1}
         prob = 1.0 / (1.0 + np.exp(-u))
         return np.where(rng.random(n) < prob, 1.0, -1.0)
+    if loss == "poisson":  # counts with mean exp(x_i^T beta*)
+        return rng.poisson(np.exp(u)).astype(np.float64)
+    if loss == "gamma":  # positive responses with mean exp(x_i^T beta*), shape 2
+        return rng.gamma(2.0, np.exp(u) / 2.0)
     raise ValueError(loss)
 
 

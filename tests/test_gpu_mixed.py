@@ -139,3 +139,32 @@ def test_mixed_warm_start_parent_and_incumbent():
     assert rp.status == "pruned" and lo < rp.lower_bound <= ref.primal
     assert rb.status in ("below_incumbent", "converged") and rb.primal < hi
     assert rb.lower_bound <= ref.primal
+
+
+@pytest.mark.parametrize("loss", ["poisson", "gamma"])
+def test_poisson_gamma_with_given_L_plain_and_mixed(loss):
+    """Losses without a global Lipschitz constant take the caller's L; both paths certify the
+    nodes to the oracle's objective with the same L. L bounds the curvature within 0.5 of the
+    root solution (found first with a cruder bound)."""
+    d = synth.make_dataset(400, 60, 3, loss=loss, config_id=91, k_true=3, M=1.0)
+    X = d.X * 0.3
+    lam = oracle.lambda_max_gram(X)
+    crude = 4.0 * lam * math.exp(3.0 * np.abs(X).max()) * (float(np.max(d.y)) if loss == "gamma" else 1.0)
+    root = oracle.solve_node(X, d.y, loss, d.lam2, 1.0, d.k, tol=1e-6, L=crude, max_iter=400000)
+    u = X @ root.beta
+    curv = np.exp(u + 0.5) if loss == "poisson" else d.y * np.exp(-u + 0.5)
+    L = 1.2 * float(np.linalg.eigvalsh(X.T @ (curv[:, None] * X))[-1])
+    with pytest.raises(_lib.CglError):
+        _lib.Problem(ctx(), X, d.y, loss=loss, lam2=d.lam2, M=1.0, k=d.k)  # no L: rejected
+    prob = _lib.Problem(ctx(), X, d.y, loss=loss, lam2=d.lam2, M=1.0, k=d.k, L=L)
+    sets = synth.node_sets(d.p, d.k, 3, 6, config_id=91)
+    for prec in ("f64", "mixed"):
+        res = prob.solve_batch([prob.node(Z0=z0, Z1=z1, tol=1e-6, max_iter=100000, precision=prec)
+                                for z0, z1 in sets])
+        for (z0, z1), r in zip(sets, res):
+            ref = oracle.solve_node(X, d.y, loss, d.lam2, 1.0, d.k, z0, z1, tol=1e-9, L=L,
+                                    max_iter=400000)
+            assert r.status == "converged", (prec, r)
+            assert rel(r.primal, ref.primal) <= 1e-6, (prec, r.primal, ref.primal)
+            # the relaxation can be exact (box binding on k coordinates): equal up to rounding
+            assert r.lower_bound <= ref.primal + 1e-12 * max(1.0, abs(ref.primal))

@@ -18,10 +18,23 @@ def _tiny(n=20, p=8, loss="ls", seed=0):
 # ------------------------------------------------------------------------------- losses
 
 
-@pytest.mark.parametrize("loss", ["ls", "logistic", "sqhinge"])
+def _responses(loss, rng, n):
+    if loss == "ls":
+        return rng.normal(size=n)
+    if loss == "poisson":
+        return rng.poisson(2.0, size=n).astype(float)
+    if loss == "gamma":
+        return rng.gamma(2.0, 1.0, size=n)
+    return rng.choice([-1.0, 1.0], size=n)
+
+
+ALL_LOSSES = ["ls", "logistic", "sqhinge", "poisson", "gamma"]
+
+
+@pytest.mark.parametrize("loss", ALL_LOSSES)
 def test_loss_gradient_finite_difference(loss):
     rng = np.random.default_rng(1)
-    y = rng.normal(size=7) if loss == "ls" else rng.choice([-1.0, 1.0], size=7)
+    y = _responses(loss, rng, 7)
     L = oracle.get_loss(loss)
     u = rng.normal(size=7)
     g = L.grad(u, y)
@@ -32,12 +45,12 @@ def test_loss_gradient_finite_difference(loss):
         assert g[i] == pytest.approx(fd, rel=1e-6, abs=1e-8)
 
 
-@pytest.mark.parametrize("loss", ["ls", "logistic", "sqhinge"])
+@pytest.mark.parametrize("loss", ALL_LOSSES)
 def test_loss_conjugate_fenchel_young_and_sup(loss):
     """F(u) + F*(s) = s^T u at s = grad F(u); F*(s) = sup_u s^T u - F(u) (coordinatewise)."""
     rng = np.random.default_rng(2)
     n = 6
-    y = rng.normal(size=n) if loss == "ls" else rng.choice([-1.0, 1.0], size=n)
+    y = _responses(loss, rng, n)
     L = oracle.get_loss(loss)
     u = rng.normal(size=n)
     s = L.grad(u, y)
@@ -62,7 +75,7 @@ def test_logistic_conjugate_domain():
 # ------------------------------------------------------------------------------- dual bound
 
 
-@pytest.mark.parametrize("loss", ["ls", "logistic", "sqhinge"])
+@pytest.mark.parametrize("loss", ALL_LOSSES)
 def test_weak_duality_random_points(loss):
     d = _tiny(loss=loss)
     ns = oracle.node_sets(d.p, Z0=[1], Z1=[4])
@@ -74,8 +87,12 @@ def test_weak_duality_random_points(loss):
             zeta = rng.normal(size=d.n) * 2
         elif loss == "logistic":
             zeta = d.y * rng.uniform(0, 1, size=d.n)
-        else:  # squared hinge: -y zeta <= 0
+        elif loss == "sqhinge":  # -y zeta <= 0
             zeta = d.y * rng.uniform(0, 3, size=d.n)
+        elif loss == "poisson":  # y - zeta >= 0
+            zeta = d.y - rng.uniform(0, 2, size=d.n)
+        else:  # gamma: (1 + zeta) / y >= 0
+            zeta = -1.0 + rng.uniform(0, 3, size=d.n)
         D = oracle.dual_value(d.X, d.y, loss, d.lam2, d.M, d.k, ns, zeta)
         assert D <= P + 1e-9
 
@@ -238,3 +255,22 @@ def test_squared_hinge_conjugate_closed_form_and_domain():
     assert oracle.SquaredHinge.conj_neg(np.array([1.0]), y) == pytest.approx(-0.75, abs=1e-15)
     assert oracle.SquaredHinge.conj_neg(np.array([-0.5]), y) == math.inf
     assert oracle.SquaredHinge.f(np.array([2.0]), y) == 0.0  # margin met: no loss
+
+
+@pytest.mark.parametrize("loss", ["poisson", "gamma"])
+def test_poisson_gamma_node_solve_with_given_L(loss):
+    """Losses without a global Lipschitz constant: with an L that bounds the curvature along the
+    path, Alg. 3 certifies the node, and the bound is below the brute-force k-sparse optimum."""
+    d = synth.make_dataset(60, 8, 2, loss=loss, config_id=90, k_true=2, M=1.0)
+    X, y = d.X * 0.5, d.y  # milder curvature
+    lam = oracle.lambda_max_gram(X)
+    L = 8.0 * lam * (math.exp(2.0 * np.abs(X).max()) if loss == "poisson" else
+                     float(np.max(y)) * math.exp(2.0 * np.abs(X).max()))
+    with pytest.raises(ValueError):
+        oracle.lipschitz(X, loss)
+    r = oracle.solve_node(X, y, loss, d.lam2, 1.0, 2, Z0=[1], tol=1e-8, L=L, max_iter=200000)
+    assert r.status == oracle.CONVERGED
+    pmip = oracle.brute_force_mip(X, y, loss, d.lam2, 1.0, 2, Z0=[1])
+    # the relaxation can be exact here (the box binds on k coordinates): equality up to rounding
+    slack = max(1.0, abs(pmip))
+    assert r.lower_bound <= pmip + 1e-13 * slack and r.primal <= pmip + 1e-9 * slack

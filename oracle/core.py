@@ -577,6 +577,106 @@ def solve_node(X, y, loss, lam2, M, k, Z0=(), Z1=(), tol=1e-6, max_iter=100000, 
 
 
 # ----------------------------------------------------------------------------------------------
+# Eigen-perspective relaxation for least squares (App. D.2)
+# ----------------------------------------------------------------------------------------------
+#
+# With Q = X^T X - s I (0 <= s <= lambda_min(X^T X), so Q is positive semidefinite) and
+# lambda_eig = lambda2 + s, the node problem's least-squares objective splits as
+#   ||X b - y||^2 + lambda2 sum b_j^2 / z_j = b^T Q b - 2 y^T X b + ||y||^2 + s ||b||^2 + ...,
+# and s ||b||^2 + lambda2 sum b_j^2 / z_j <= lambda_eig sum b_j^2 / z_j for z in [0, 1], so
+#   P_eig(node) = min_b  b^T Q b - 2 y^T X b + ||y||^2 + 2 lambda_eig g_node(b)
+# lies between the perspective relaxation and P_MIP (s = 0 gives the perspective relaxation).
+# Weak duality with F(b) = b^T Q b and G(b) = -2 y^T X b + 2 lambda_eig g_node(b) at
+# zeta = -grad F(b_hat) = -2 Q b_hat gives (the constant ||y||^2 kept so that the bound is one of
+# the node's objective; App. D.2 drops it, and its last display has the signs of both terms
+# flipped):
+#   D_eig(b_hat) = ||y||^2 - b_hat^T Q b_hat - 2 lambda_eig g_node*((X^T y - Q b_hat) / lambda_eig).
+
+
+def lambda_min_gram(X):
+    """Smallest eigenvalue of X^T X (dense symmetric eigen-solver for p <= 2000, else Lanczos)."""
+    X = np.asarray(X, dtype=np.float64)
+    n, p = X.shape
+    if p <= 2000:
+        return float(np.linalg.eigvalsh(X.T @ X)[0])
+    from scipy.sparse.linalg import LinearOperator, eigsh
+
+    op = LinearOperator((p, p), matvec=lambda v: X.T @ (X @ v), dtype=np.float64)
+    return float(eigsh(op, k=1, which="SA", tol=1e-12, return_eigenvectors=False)[0])
+
+
+def eig_primal_value(X, y, lam2, M, k, ns: NodeSets, beta, shift):
+    """Objective of the eigen-perspective node problem: ||X b - y||^2 - s ||b||^2
+    + 2 (lambda2 + s) g_node(b)."""
+    gv = g_node(beta, M, k, ns)
+    if math.isinf(gv):
+        return math.inf
+    r = X @ beta - y
+    return float(r @ r) - shift * float(beta @ beta) + 2.0 * (lam2 + shift) * gv
+
+
+def eig_dual_value(X, y, lam2, M, k, ns: NodeSets, beta_hat, shift):
+    """D_eig(b_hat) above: ||y||^2 - b^T Q b - 2 lambda_eig g_node*((X^T y - Q b) / lambda_eig)."""
+    lam_eig = lam2 + shift
+    Qb = X.T @ (X @ beta_hat) - shift * beta_hat
+    a = (X.T @ y - Qb) / lam_eig
+    return float(y @ y) - float(beta_hat @ Qb) - 2.0 * lam_eig * gstar_node(a, M, k, ns)
+
+
+def solve_node_eig(X, y, lam2, M, k, shift, Z0=(), Z1=(), tol=1e-6, max_iter=100000, L=None):
+    """Alg. 3 on the eigen-perspective node problem (least squares), certified by D_eig:
+      gamma = beta^t + phi/(phi+3) (beta^t - beta^{t-1});
+      grad  = 2 Q gamma - 2 X^T y = X^T (2 (X gamma - y)) - 2 s gamma;
+      beta^{t+1} = prox_{g_node / rho}(gamma - grad / L), rho = L / (2 lambda_eig),
+      L = 2 lambda_max(Q) = 2 (lambda_max(X^T X) - s);
+      restart on the objective, and D_eig(beta^{t+1}) every iteration."""
+    X = np.asarray(X, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n, p = X.shape
+    if not (0.0 <= shift):
+        raise ValueError("the shift must be >= 0")
+    ns = node_sets(p, Z0, Z1)
+    if ns.one.size > k:
+        return NodeResult(beta=np.zeros(p), primal=math.inf, lower_bound=math.inf, gap_abs=0.0,
+                          gap_rel=0.0, iters=0, restarts=0, status=INFEASIBLE)
+    if L is None:
+        L = 2.0 * (lambda_max_gram(X) - shift)
+    lam_eig = lam2 + shift
+    rho = L / (2.0 * lam_eig)
+    beta = np.zeros(p)
+    beta_prev = beta.copy()
+    phi = 1.0
+    L_prev = eig_primal_value(X, y, lam2, M, k, ns, beta, shift)
+    P_best, beta_best = L_prev, beta.copy()
+    D_best = -math.inf
+    restarts = 0
+    status = NOT_CONVERGED
+    t = 0
+    for t in range(1, max_iter + 1):
+        c = phi / (phi + 3.0)
+        gamma = beta + c * (beta - beta_prev)
+        grad = X.T @ (2.0 * (X @ gamma - y)) - 2.0 * shift * gamma
+        beta_new = prox_node(gamma - grad / L, rho, M, k, ns)
+        L_new = eig_primal_value(X, y, lam2, M, k, ns, beta_new, shift)
+        if L_new >= L_prev:
+            phi = 1.0
+            restarts += 1
+        else:
+            phi += 1.0
+        beta_prev, beta = beta, beta_new
+        L_prev = L_new
+        if L_new < P_best:
+            P_best, beta_best = L_new, beta_new.copy()
+        D_best = max(D_best, eig_dual_value(X, y, lam2, M, k, ns, beta_new, shift))
+        if rel_gap(P_best, D_best) <= tol:
+            status = CONVERGED
+            break
+    return NodeResult(beta=beta_best, primal=P_best, lower_bound=D_best,
+                      gap_abs=P_best - D_best, gap_rel=rel_gap(P_best, D_best), iters=t,
+                      restarts=restarts, status=status, L=L)
+
+
+# ----------------------------------------------------------------------------------------------
 # Brute-force mixed-integer optimum for tiny p (tests only)
 # ----------------------------------------------------------------------------------------------
 

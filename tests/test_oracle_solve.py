@@ -274,3 +274,70 @@ def test_poisson_gamma_node_solve_with_given_L(loss):
     # the relaxation can be exact here (the box binds on k coordinates): equality up to rounding
     slack = max(1.0, abs(pmip))
     assert r.lower_bound <= pmip + 1e-13 * slack and r.primal <= pmip + 1e-9 * slack
+
+
+# ------------------------------------------------------------------ eigen-perspective relaxation
+
+
+def _eig_data(seed=0, n=40, p=8):
+    d = synth.make_dataset(n, p, 2, loss="ls", config_id=95 + seed, k_true=2)
+    return d, oracle.lambda_min_gram(d.X)
+
+
+def test_lambda_min_matches_dense_eigenvalues():
+    rng = np.random.default_rng(4)
+    X = rng.normal(size=(60, 12))
+    assert oracle.lambda_min_gram(X) == pytest.approx(float(np.linalg.eigvalsh(X.T @ X)[0]),
+                                                      rel=1e-12)
+
+
+def test_eig_with_zero_shift_is_the_perspective_relaxation():
+    d, _ = _eig_data(0)
+    r0 = oracle.solve_node(d.X, d.y, "ls", d.lam2, d.M, 2, Z0=[3], tol=1e-10)
+    r1 = oracle.solve_node_eig(d.X, d.y, d.lam2, d.M, 2, 0.0, Z0=[3], tol=1e-10)
+    assert r1.status == oracle.CONVERGED
+    assert r1.primal == pytest.approx(r0.primal, rel=1e-9)
+    assert r1.lower_bound == pytest.approx(r0.lower_bound, rel=1e-8)
+
+
+def test_eig_ridge_closed_form_when_budget_covers_free_set():
+    """All z_j = 1: the eigen-perspective problem is ridge regression with lambda2 for any
+    admissible shift (s ||b||^2 - s ||b||^2 cancels)."""
+    d = synth.make_dataset(40, 6, 6, loss="ls", config_id=97, k_true=2, M=100.0)
+    s = 0.9 * oracle.lambda_min_gram(d.X)
+    b = np.linalg.solve(d.X.T @ d.X + d.lam2 * np.eye(6), d.X.T @ d.y)
+    ref = float(np.sum((d.X @ b - d.y) ** 2) + d.lam2 * b @ b)
+    r = oracle.solve_node_eig(d.X, d.y, d.lam2, 100.0, 6, s, tol=1e-11)
+    assert r.primal == pytest.approx(ref, rel=1e-9)
+    assert r.lower_bound <= ref * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_eig_bound_valid_and_tighter(seed):
+    """perspective bound <= eigen-perspective bound <= P_MIP (brute force)."""
+    d, lmin = _eig_data(seed)
+    assert lmin > 0
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(d.p)
+    Z0 = [int(perm[0])] if seed % 2 else []
+    Z1 = [int(perm[1])] if seed >= 2 else []
+    k = 2
+    std = oracle.solve_node(d.X, d.y, "ls", d.lam2, d.M, k, Z0=Z0, Z1=Z1, tol=1e-10)
+    eig = oracle.solve_node_eig(d.X, d.y, d.lam2, d.M, k, lmin, Z0=Z0, Z1=Z1, tol=1e-10)
+    assert eig.status == oracle.CONVERGED
+    pmip = oracle.brute_force_mip(d.X, d.y, "ls", d.lam2, d.M, k, Z0=Z0, Z1=Z1)
+    assert eig.lower_bound <= pmip * (1 + 1e-12)
+    assert eig.lower_bound >= std.lower_bound - 1e-8 * abs(std.primal)
+
+
+def test_eig_dual_is_weak_duality():
+    """D_eig(b_hat) <= the eigen-perspective objective at any point, for any b_hat."""
+    d, lmin = _eig_data(1)
+    ns = oracle.node_sets(d.p, [2], [5])
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        bh = rng.normal(size=d.p)
+        D = oracle.eig_dual_value(d.X, d.y, d.lam2, d.M, 2, ns, bh, lmin)
+        b = oracle.prox_node(rng.normal(size=d.p), 3.0, d.M, 2, ns)
+        P = oracle.eig_primal_value(d.X, d.y, d.lam2, d.M, 2, ns, b, lmin)
+        assert D <= P + 1e-9

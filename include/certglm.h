@@ -164,6 +164,17 @@ int cgl_problem_create(cgl_ctx* ctx, const void* X, int32_t x_dtype, int32_t x_m
 int cgl_problem_destroy(cgl_problem* prob);
 /* The Lipschitz constant in use. */
 int cgl_problem_lipschitz(const cgl_problem* prob, double* L);
+/* Eigen-perspective relaxation for least squares (App. D.2): with Q = X^T X - shift I and
+ * lambda_eig = lambda2 + shift, later FP64-path solves minimise
+ *   ||X beta - y||^2 - shift ||beta||^2 + 2 lambda_eig g_node(beta)
+ * (between the perspective relaxation, shift = 0, and the k-sparse optimum) and certify it with
+ *   ||y||^2 - beta^T Q beta - 2 lambda_eig g_node*((X^T y - Q beta) / lambda_eig)
+ * evaluated at the iteration's momentum point. The bound is valid for 0 <= shift <=
+ * lambda_min(X^T X): the caller supplies the shift (e.g. from an eigen-solver, with a margin);
+ * the library does not verify it. L becomes 2 (1.002 lambda_max(X^T X) - shift).
+ * Errors: CGL_E_INVAL for another loss, shift < 0 or shift >= lambda_max. Batched (MIXED)
+ * solves and cgl_certify reject a shifted problem; shift = 0 restores the perspective one. */
+int cgl_problem_set_eigen(cgl_problem* prob, double shift);
 
 /* ------------------------------------------------------------------ solves */
 

@@ -25,7 +25,7 @@ EXPORTS = [
     "cgl_version", "cgl_status_str", "cgl_last_error", "cgl_node_init", "cgl_ctx_create",
     "cgl_ctx_destroy", "cgl_ctx_set_profiling", "cgl_ctx_kernel_stats", "cgl_problem_create", "cgl_problem_destroy", "cgl_problem_lipschitz",
     "cgl_solve_node", "cgl_solve_batch", "cgl_certify", "cgl_problem_matvec",
-    "cgl_prox_node_batch", "cgl_server_create", "cgl_server_submit", "cgl_server_poll",
+    "cgl_prox_node_batch", "cgl_problem_set_eigen", "cgl_server_create", "cgl_server_submit", "cgl_server_poll",
     "cgl_server_cancel", "cgl_server_stats", "cgl_server_destroy",
 ]
 
@@ -86,6 +86,7 @@ def load(path: str = LIB_PATH):
     lib.cgl_certify.argtypes = [P, C.POINTER(CglNode), pd, pd, pd]
     lib.cgl_problem_matvec.argtypes = [P, i32, pd, pd]
     lib.cgl_prox_node_batch.argtypes = [P, dbl, dbl, i32, C.POINTER(CglNode), pd, i32, i64, pd, pd]
+    lib.cgl_problem_set_eigen.argtypes = [P, dbl]
     if hasattr(lib, "cgl_server_create"):
         lib.cgl_server_create.argtypes = [P, C.c_size_t, i32, C.POINTER(P)]
         lib.cgl_server_submit.argtypes = [P, P, C.POINTER(CglNode), C.POINTER(C.c_uint64)]
@@ -228,6 +229,10 @@ class Problem:
         v = C.c_double()
         check(self.lib.cgl_problem_lipschitz(self.h, C.byref(v)))
         return v.value
+
+    def set_eigen(self, shift: float) -> None:
+        """Eigen-perspective relaxation with Q = X^T X - shift I (0 <= shift <= lambda_min)."""
+        check(self.lib.cgl_problem_set_eigen(self.h, float(shift)))
 
     def node(self, **kw) -> NodeSpec:
         return NodeSpec(self.p, **kw)

@@ -201,6 +201,7 @@ void PlainWork::ensure(Problem& P) {
   lpart.alloc((size_t)geom.nxb * 8);
   cls.alloc(P.ldx);
   st.alloc(sizeof(NodeDev));
+  gsq.alloc((size_t)((P.ldx + 255) / 256) * 8);
   CGL_HIP(hipHostMalloc(&st_host, sizeof(NodeDev), hipHostMallocDefault));
   ready = true;
 }
@@ -213,22 +214,26 @@ PlainWork::~PlainWork() {
 // One iteration of Alg. 3 on the plain path. ev (optional): four events bracketing the X^T pass
 // and the X pass, for kernel timing.
 static void plain_iteration(Problem& P, PlainWork& W, hipStream_t s, hipEvent_t* ev = nullptr) {
-  const double two_l2 = 2.0 * P.lam2;
+  const double two_l2 = 2.0 * (P.lam2 + P.shift);  // 2 lambda_eig with the eigen shift
+  const bool eig = P.shift != 0.0;
+  const int ngsq = (int)((P.ldx + 255) / 256);
   NodeDev* st = W.st.as<NodeDev>();
   if (ev) CGL_HIP(hipEventRecord(ev[0], s));
   launch_xt(P.xtype, P.X.ptr, P.ldx, P.n, P.ldx, W.geom, W.uring.as<double>(), P.n, st,
             P.y.as<double>(), P.loss, 0, W.part.as<double>(), W.fpart.as<double>(), s);
   if (ev) CGL_HIP(hipEventRecord(ev[1], s));
   launch_grad_step(W.part.as<double>(), W.geom.nchunks, P.ldx, st, W.bring.as<double>(), P.ldx,
-                   1.0 / P.L, W.h.as<double>(), W.w.as<double>(), s);
+                   1.0 / P.L, W.h.as<double>(), W.w.as<double>(), s, P.shift,
+                   eig ? W.gsq.as<double>() : nullptr);
   launch_prox(1, W.w.as<double>(), 0, W.h.as<double>(), 0, W.cls.as<uint8_t>(), 0, P.p, P.rho,
-              P.M, two_l2, st, W.bring.as<double>(), P.ldx, 0, s);
+              P.M, two_l2, st, W.bring.as<double>(), P.ldx, 0, s, eig ? 1 : 0);
   if (ev) CGL_HIP(hipEventRecord(ev[2], s));
   launch_xb(P.xtype, P.X.ptr, P.ldx, P.n, P.ldx, W.bring.as<double>(), P.ldx,
             W.uring.as<double>(), P.n, st, P.y.as<double>(), P.loss, W.lpart.as<double>(), s);
   if (ev) CGL_HIP(hipEventRecord(ev[3], s));
   launch_finish(W.lpart.as<double>(), W.geom.nxb, W.fpart.as<double>(), W.geom.nchunks, two_l2,
-                st, W.bring.as<double>(), P.ldx, W.bbest.as<double>(), P.p, s);
+                st, W.bring.as<double>(), P.ldx, W.bbest.as<double>(), P.p, s, P.shift,
+                eig ? W.gsq.as<double>() : nullptr, ngsq);
 }
 
 static bool use_graphs() {
@@ -493,6 +498,7 @@ int cgl_problem_create(cgl_ctx* ctx, const void* X, int32_t x_dtype, int32_t x_m
   } else {
     const double lam = power_lambda_max(*P);
     const double factor = loss_lipschitz_factor(P->loss);
+    P->lam_max = lam;
     P->L = factor * lam * 1.002;
   }
   P->rho = P->L / (2.0 * P->lam2);
@@ -534,6 +540,28 @@ int cgl_solve_node(cgl_problem* prob, const cgl_node* node, double* beta_out, cg
   } else {
     solve_plain(P, *node, nh, beta_out, res);
   }
+  return CGL_OK;
+  CGL_API_END
+}
+
+int cgl_problem_set_eigen(cgl_problem* prob, double shift) {
+  CGL_API_BEGIN
+  if (!prob) invalid("prob is NULL");
+  Problem& P = *reinterpret_cast<Problem*>(prob);
+  if (P.loss != LOSS_LS) invalid("the eigen-perspective relaxation is for least squares");
+  if (!(shift >= 0.0) || !std::isfinite(shift)) invalid("shift must be >= 0");
+  CGL_HIP(hipSetDevice(P.ctx->device));
+  if (P.lam_max <= 0.0) P.lam_max = power_lambda_max(P);
+  if (shift >= P.lam_max) invalid("shift must be below lambda_max(X^T X)");
+  // L = 2 lambda_max(Q), Q = X^T X - s I, with the same safety factor on lambda_max; a graph
+  // captured with the previous parameters is dropped
+  if (P.plain.graph_exec) {
+    CGL_HIP(hipGraphExecDestroy(P.plain.graph_exec));
+    P.plain.graph_exec = nullptr;
+  }
+  P.shift = shift;
+  P.L = 2.0 * (1.002 * P.lam_max - shift);
+  P.rho = P.L / (2.0 * (P.lam2 + shift));
   return CGL_OK;
   CGL_API_END
 }
@@ -583,6 +611,7 @@ int cgl_certify(cgl_problem* prob, const cgl_node* node, const double* beta, dou
   CGL_API_BEGIN
   if (!prob || !node || !beta || !primal || !dual) invalid("NULL argument");
   Problem& P = *reinterpret_cast<Problem*>(prob);
+  if (P.shift != 0.0) invalid("cgl_certify evaluates the perspective relaxation (shift 0)");
   CGL_HIP(hipSetDevice(P.ctx->device));
   const NodeHost nh = make_node_host(*node, P.p, P.k);
   if (nh.infeasible) {

@@ -482,6 +482,8 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
   W.ensure(P);
   if (W.free_slots() != W.S)
     invalid("the problem's batched engine is in use by a server; solve through the server");
+  if (P.shift != 0.0)
+    invalid("the eigen-perspective relaxation runs on the FP64 path (CGL_PREC_F64)");
   hipStream_t s = P.ctx->stream;
   std::vector<NodeHost> hosts;
   hosts.reserve((size_t)count);

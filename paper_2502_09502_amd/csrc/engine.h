@@ -70,7 +70,7 @@ struct Problem;
 struct PlainWork {
   bool ready = false;
   PlainGeom geom{};
-  DevBuf bring, uring, bbest, w, h, part, fpart, lpart, cls, st;
+  DevBuf bring, uring, bbest, w, h, part, fpart, lpart, cls, st, gsq;
   NodeDev* st_host = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   void ensure(Problem& P);
@@ -89,6 +89,8 @@ struct Problem {
   DevBuf X;  // n x ldx in the stored precision, zero padded
   DevBuf y;  // n doubles
   PlainWork plain;
+  double shift = 0.0;          // eigen-perspective shift s (App. D.2); 0: perspective relaxation
+  double lam_max = 0.0;        // lambda_max(X^T X) estimate when the library computed L
   MixedWork* mixed = nullptr;  // created on first mixed solve
   size_t mixed_bytes = 0;      // its device footprint, once known
   ~Problem();

@@ -28,14 +28,15 @@ void launch_xt(int xtype, const void* X, int64_t ldx, int64_t n, int64_t p_pad,
                hipStream_t stream);
 void launch_grad_step(const double* part, int nchunks, int64_t p_pad, const NodeDev* st,
                       const double* b_base, int64_t b_stride, double inv_L, double* h, double* w,
-                      hipStream_t stream);
+                      hipStream_t stream, double shift = 0.0, double* gsq_part = nullptr);
 void launch_prox(int nodes, const double* w, int64_t w_ld, const double* h, int64_t h_ld,
                  const uint8_t* cls, int64_t cls_ld, int64_t p, double rho, double M,
                  double two_l2, NodeDev* st, double* b_base, int64_t b_stride,
-                 int64_t b_node_stride, hipStream_t stream);
+                 int64_t b_node_stride, hipStream_t stream, int want_bsq = 0);
 void launch_finish(const double* loss_part, int nloss, const double* fstar_part, int nfstar,
                    double two_l2, NodeDev* st, const double* b_base, int64_t b_stride,
-                   double* b_best, int64_t p, hipStream_t stream);
+                   double* b_best, int64_t p, hipStream_t stream, double shift = 0.0,
+                   const double* gsq_part = nullptr, int ngsq = 0);
 void launch_init_state(const double* loss_part, int nloss, double L0_g, NodeDev* st,
                        hipStream_t stream);
 

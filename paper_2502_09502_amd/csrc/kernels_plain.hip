@@ -228,21 +228,33 @@ __global__ __launch_bounds__(256) void k_xt(const XT* __restrict__ X, int64_t ld
 __global__ __launch_bounds__(256) void k_grad_step(const double* __restrict__ part, int nchunks,
                                                    int64_t p_pad, const NodeDev* __restrict__ st,
                                                    const double* __restrict__ b_base,
-                                                   int64_t b_stride, double inv_L,
+                                                   int64_t b_stride, double inv_L, double shift,
                                                    double* __restrict__ h,
-                                                   double* __restrict__ w) {
+                                                   double* __restrict__ w,
+                                                   double* __restrict__ gsq_part) {
+  // with the eigen-perspective shift s the gradient is X^T grad f(X gamma) - 2 s gamma (App. D.2);
+  // h receives the whole gradient, gsq_part the block's share of ||gamma||^2
+  __shared__ double red[4];
   if (st != nullptr && st->done) return;
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= p_pad) return;
-  double s = 0.0;
-  for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * p_pad + j];
-  h[j] = s;
-  if (st != nullptr) {
-    const int iter = st->iter;
-    const double bt = slot_ptr(b_base, b_stride, iter, 0)[j];
-    const double btm = slot_ptr(b_base, b_stride, iter, 2)[j];
-    const double gamma = bt + st->c * (bt - btm);
-    w[j] = gamma - s * inv_L;
+  double gsq = 0.0;
+  if (j < p_pad) {
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * p_pad + j];
+    if (st != nullptr) {
+      const int iter = st->iter;
+      const double bt = slot_ptr(b_base, b_stride, iter, 0)[j];
+      const double btm = slot_ptr(b_base, b_stride, iter, 2)[j];
+      const double gamma = bt + st->c * (bt - btm);
+      s -= 2.0 * shift * gamma;
+      w[j] = gamma - s * inv_L;
+      gsq = gamma * gamma;
+    }
+    h[j] = s;
+  }
+  if (gsq_part != nullptr) {
+    gsq = block_reduce(gsq, red, OpAdd(), 0.0);
+    if (threadIdx.x == 0) gsq_part[blockIdx.x] = gsq;
   }
 }
 
@@ -257,7 +269,7 @@ __global__ __launch_bounds__(1024) void k_prox(const double* __restrict__ w, int
                                                int64_t cls_ld, int64_t p, double rho, double M,
                                                double two_l2, NodeDev* __restrict__ st_all,
                                                double* __restrict__ b_base, int64_t b_stride,
-                                               int64_t b_node_stride) {
+                                               int64_t b_node_stride, int want_bsq) {
   __shared__ ProxSmem sm;
   const int node = blockIdx.x;
   NodeDev* st = st_all + node;
@@ -281,13 +293,16 @@ __global__ __launch_bounds__(1024) void k_prox(const double* __restrict__ w, int
     cb |= (uint64_t)cs << (2 * s);
   }
   double* bout = slot_ptr(b_base + (int64_t)node * b_node_stride, b_stride, iter, 1);
+  double bsq = 0.0;
   const ProxOut po = node_prox<E>(
       [&](int s) { return pv.get(s); }, neg, cb, st->kp, st->nfree, rho, M, st->vstar,
       [&](int s, double b) {
         const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
         if (j < p) bout[j] = b;
+        bsq += b * b;
       },
       sm);
+  if (want_bsq) bsq = bsum(bsq, sm);
   const bool check = ((iter % st->check_every) == 0) || (iter >= st->max_iter);
   double gs = 0.0;
   if (check && h != nullptr) {
@@ -302,6 +317,7 @@ __global__ __launch_bounds__(1024) void k_prox(const double* __restrict__ w, int
   if (threadIdx.x == 0) {
     st->g_new = po.gval;
     st->gstar_new = gs;
+    st->bsq_new = bsq;
     st->checked = check ? 1 : 0;
     st->vstar = po.vstar;
   }
@@ -320,18 +336,24 @@ __global__ __launch_bounds__(256) void k_finish(const double* __restrict__ loss_
                                                 NodeDev* __restrict__ st,
                                                 const double* __restrict__ b_base,
                                                 int64_t b_stride, double* __restrict__ b_best,
-                                                int64_t p) {
+                                                int64_t p, double shift,
+                                                const double* __restrict__ gsq_part, int ngsq) {
   __shared__ double red[4];
   __shared__ int improve;
   if (st->done) return;
-  double a = 0.0, f = 0.0;
+  double a = 0.0, f = 0.0, gsq = 0.0;
   for (int i = threadIdx.x; i < nloss; i += blockDim.x) a += loss_part[i];
   for (int i = threadIdx.x; i < nfstar; i += blockDim.x) f += fstar_part[i];
+  if (gsq_part != nullptr)
+    for (int i = threadIdx.x; i < ngsq; i += blockDim.x) gsq += gsq_part[i];
   a = block_reduce(a, red, OpAdd(), 0.0);
   f = block_reduce(f, red, OpAdd(), 0.0);
+  gsq = block_reduce(gsq, red, OpAdd(), 0.0);
   const int iter = st->iter;
   if (threadIdx.x == 0) {
-    const double Lnew = a + two_l2 * st->g_new;
+    // eigen-perspective shift s (App. D.2): objective f - s ||beta||^2 + 2 lambda_eig g, and the
+    // bound gains s ||gamma||^2 (two_l2 is then 2 lambda_eig); s = 0 is the plain relaxation
+    const double Lnew = a - shift * st->bsq_new + two_l2 * st->g_new;
     st->L_work = Lnew;
     if (Lnew >= st->L_prev) { st->phi = 1.0; st->restarts += 1; }
     else st->phi += 1.0;
@@ -339,7 +361,7 @@ __global__ __launch_bounds__(256) void k_finish(const double* __restrict__ loss_
     improve = 0;
     if (Lnew < st->P_best) { st->P_best = Lnew; st->best_iter = iter + 1; improve = 1; }
     if (st->checked) {
-      const double D = -f - two_l2 * st->gstar_new;
+      const double D = -f - two_l2 * st->gstar_new + shift * gsq;
       if (D > st->D_best) st->D_best = D;
     }
     const double gap = (st->P_best - st->D_best) / fmax(fabs(st->P_best), 1.0);
@@ -435,9 +457,9 @@ void launch_xt(int xtype, const void* X, int64_t ldx, int64_t n, int64_t p_pad,
 
 void launch_grad_step(const double* part, int nchunks, int64_t p_pad, const NodeDev* st,
                       const double* b_base, int64_t b_stride, double inv_L, double* h, double* w,
-                      hipStream_t stream) {
+                      hipStream_t stream, double shift, double* gsq_part) {
   hipLaunchKernelGGL(k_grad_step, dim3((unsigned)((p_pad + 255) / 256)), dim3(256), 0, stream,
-                     part, nchunks, p_pad, st, b_base, b_stride, inv_L, h, w);
+                     part, nchunks, p_pad, st, b_base, b_stride, inv_L, shift, h, w, gsq_part);
 }
 
 int prox_elems(int64_t p) {
@@ -454,12 +476,13 @@ int prox_elems(int64_t p) {
 void launch_prox(int nodes, const double* w, int64_t w_ld, const double* h, int64_t h_ld,
                  const uint8_t* cls, int64_t cls_ld, int64_t p, double rho, double M,
                  double two_l2, NodeDev* st, double* b_base, int64_t b_stride,
-                 int64_t b_node_stride, hipStream_t stream) {
+                 int64_t b_node_stride, hipStream_t stream, int want_bsq) {
   const int E = prox_elems(p);
 #define CGL_PROX_CASE(EE)                                                                       \
   case EE:                                                                                      \
     hipLaunchKernelGGL(k_prox<EE>, dim3(nodes), dim3(kProxThreads), 0, stream, w, w_ld, h, h_ld, \
-                       cls, cls_ld, p, rho, M, two_l2, st, b_base, b_stride, b_node_stride);    \
+                       cls, cls_ld, p, rho, M, two_l2, st, b_base, b_stride, b_node_stride,     \
+                       want_bsq);                                                               \
     break;
   switch (E) {
     CGL_PROX_CASE(1)
@@ -476,9 +499,10 @@ void launch_prox(int nodes, const double* w, int64_t w_ld, const double* h, int6
 
 void launch_finish(const double* loss_part, int nloss, const double* fstar_part, int nfstar,
                    double two_l2, NodeDev* st, const double* b_base, int64_t b_stride,
-                   double* b_best, int64_t p, hipStream_t stream) {
+                   double* b_best, int64_t p, hipStream_t stream, double shift,
+                   const double* gsq_part, int ngsq) {
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, stream, loss_part, nloss, fstar_part,
-                     nfstar, two_l2, st, b_base, b_stride, b_best, p);
+                     nfstar, two_l2, st, b_base, b_stride, b_best, p, shift, gsq_part, ngsq);
 }
 
 void launch_init_state(const double* loss_part, int nloss, double L0_g, NodeDev* st,

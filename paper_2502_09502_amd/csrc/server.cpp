@@ -251,6 +251,8 @@ int cgl_server_submit(cgl_server* srv, cgl_problem* prob, const cgl_node* node,
   if (!srv || !prob || !node || !ticket) invalid("NULL argument");
   Problem* P = reinterpret_cast<Problem*>(prob);
   if (P->ctx != srv->ctx) invalid("the problem belongs to another context");
+  if (P->shift != 0.0 && node->precision == CGL_PREC_MIXED)
+    invalid("the eigen-perspective relaxation runs on the FP64 path (CGL_PREC_F64)");
   if (srv->queue.size() >= kQueueCap) {
     set_error("server queue is full");
     return CGL_E_BUSY;

@@ -47,6 +47,7 @@ struct NodeDev {
   int b_int0;        // scratch flag of the certification kernel
   int last_ring;     // ring slot holding the latest prox output (the iterate g_new belongs to)
   int need_base;     // warm start admitted: parked until an FP64 round sets its base point
+  double bsq_new;    // ||beta^{t+1}||^2 (eigen-perspective objective)
 };
 
 constexpr int kRunning = -1;

@@ -134,3 +134,36 @@ def test_config2_full_size_properties():
         assert res.lower_bound <= P
         Pc, Dc = prob.certify(res.beta)
         assert rel(Pc, P) <= 1e-11 and rel(Dc, D) <= 1e-10
+
+
+def test_eigen_perspective_relaxation():
+    """Eigen-perspective relaxation (App. D.2) on the FP64 path: the certified objective matches
+    the oracle's, the bound is at least the perspective one and never above the oracle's optimum;
+    other losses, negative shifts, batched solves and cgl_certify reject it."""
+    d = synth.make_dataset(300, 60, 5, loss="ls", config_id=77, k_true=5)
+    lmin = oracle.lambda_min_gram(d.X)
+    assert lmin > 0
+    shift = lmin * (1.0 - 1e-6)
+    prob = _problem(d)
+    sets = [((), ()), ([3, 11], [7]), ([], [1, 2])]
+    std = [prob.solve(Z0=z0, Z1=z1, tol=1e-7) for z0, z1 in sets]
+    prob.set_eigen(shift)
+    for (z0, z1), s0 in zip(sets, std):
+        r = prob.solve(Z0=z0, Z1=z1, tol=1e-7)
+        ref = oracle.solve_node_eig(d.X, d.y, d.lam2, d.M, d.k, shift, z0, z1, tol=1e-10)
+        assert r.status == "converged", r
+        assert rel(r.primal, ref.primal) <= 1e-6, (r.primal, ref.primal)
+        assert r.lower_bound <= ref.primal
+        assert r.lower_bound >= s0.lower_bound - 1e-6 * abs(s0.primal)
+    with pytest.raises(_lib.CglError):
+        prob.solve_batch([prob.node(precision="mixed")])
+    with pytest.raises(_lib.CglError):
+        prob.certify(np.zeros(d.p))
+    with pytest.raises(_lib.CglError):
+        prob.set_eigen(-1.0)
+    prob.set_eigen(0.0)  # back to the perspective relaxation
+    r = prob.solve(tol=1e-7)
+    assert rel(r.primal, std[0].primal) <= 1e-6
+    dl = synth.make_dataset(300, 60, 5, loss="logistic", config_id=77)
+    with pytest.raises(_lib.CglError):
+        _problem(dl).set_eigen(0.1)

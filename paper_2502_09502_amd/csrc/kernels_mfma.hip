@@ -88,6 +88,11 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int mtiles, int k
 // =====================================================================================
 // dU^{t+1} = sum of the X-pass split-K partials (into the ring slot of this cycle) and the loss
 // terms f_i(u_0 + dU) summed per chunk. grid: (chunks, slots); 256 threads.
+//
+// In the first cycle after a re-centre that kept the momentum (rebase), the product of this
+// cycle is X~ bf16(beta^{t+1} - beta_0') against the previous base beta_0', and beta^{t+1} is the
+// new base: dU^{t+1} = 0 and the previous correction becomes X~ bf16(beta^t - beta_0') minus this
+// product, i.e. X (beta^t - beta^{t+1}) with the rounding of an ordinary cycle's difference.
 // =====================================================================================
 __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
   __shared__ double red[4];
@@ -95,13 +100,19 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
   const NodeDev* st = md.st + slot;
   if (!slot_running(st)) return;
   const int cyc = *md.cycle;
+  const bool rebase = st->rebase != 0;
   float* dun = md.dU + (int64_t)(cyc & 1) * md.dU_ring + (int64_t)slot * md.n_pad;
+  float* duo = md.dU + (int64_t)((cyc + 1) & 1) * md.dU_ring + (int64_t)slot * md.n_pad;
   const int64_t i0 = (int64_t)blockIdx.x * md.rchunk;
   const int64_t i1 = min(md.n_pad, i0 + md.rchunk);
   double ls = 0.0;
   for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
     float du = 0.f;
     for (int q = 0; q < md.ksx; ++q) du += md.dUp[(int64_t)q * md.dUp_split + (int64_t)slot * md.n_pad + i];
+    if (rebase) {
+      duo[i] -= du;
+      du = 0.f;
+    }
     dun[i] = du;
     if (i < md.n) {
       const double u = md.base0[(int64_t)slot * md.n_pad + i] + (double)du;
@@ -127,6 +138,9 @@ __global__ __launch_bounds__(64) void k_mixed_restart(MixedDev md) {
     st->L_work = Lnew;
     if (!st->primed) {
       st->primed = 1;
+    } else if (st->rebase) {
+      // L^t was evaluated against the previous base: the momentum runs on untested
+      st->phi += 1.0;
     } else if (Lnew >= st->L_prev) {
       st->phi = 1.0;
       st->restarts += 1;
@@ -136,6 +150,7 @@ __global__ __launch_bounds__(64) void k_mixed_restart(MixedDev md) {
     st->L_prev = Lnew;
     if (Lnew < st->P_best) st->P_best = Lnew;  // working-precision best (monitor only)
     st->c = st->phi / (st->phi + 3.0);
+    st->rebase = 0;  // read by the loss kernel of this cycle only
   }
 }
 
@@ -373,6 +388,15 @@ __global__ __launch_bounds__(256) void k_cert_resid(MixedDev md, const int* list
   }
 }
 
+// A re-centre keeps the momentum of Alg. 3 when the slot advanced in the latest cycle: the
+// iterate before the certified one is still in the ring, the operand of the next X pass still
+// holds bf16(beta^{t+1} - beta_0) against the old base, and the ring of X-products holds
+// X~ bf16(beta^t - beta_0). Moving the base point is a change of numerical representation, not a
+// restart of the method.
+__device__ __forceinline__ bool keeps_momentum(const NodeDev* st, int cyc) {
+  return st->need_base == 0 && st->iter > 1 && st->last_ring == cyc % 3;
+}
+
 // Per certified slot: P = f + 2 lambda2 g, D = -F* - 2 lambda2 g*(X^T zeta / (2 lambda2)) with
 // X^T zeta = -H64 (FP64 weak-duality bound, Sec. 3.4). Keeps the best certified P (and its
 // beta) and D; finishes the slot or re-centres it on the certified iterate.
@@ -386,6 +410,8 @@ __global__ __launch_bounds__(1024) void k_cert_finish(MixedDev md, const int* li
   const int slot = list[q];
   NodeDev* st = md.st + slot;
   const int64_t p = md.p;
+  const int cyc = *md.cycle;
+  const bool keep = keeps_momentum(st, cyc);
   const uint8_t* cl = md.cls + (int64_t)slot * md.ldp;
   __shared__ double vbuf[ProxVals<E>::lds ? E * kProxThreads : 1];
   ProxVals<E> hv;
@@ -428,12 +454,16 @@ __global__ __launch_bounds__(1024) void k_cert_finish(MixedDev md, const int* li
       st->status = status;
       st->done = 1;
     } else {
-      // re-centre on this iterate: restart the momentum (Alg. 3 with phi = 1)
+      // re-centre on this iterate
       st->recentres += 1;
-      st->primed = 0;
-      st->phi = 1.0;
-      st->c = 0.25;
-      st->L_prev = HUGE_VAL;
+      if (keep) {
+        st->rebase = 1;
+      } else {  // no previous iterate: start the momentum afresh (phi = 1)
+        st->primed = 0;
+        st->phi = 1.0;
+        st->c = 0.25;
+        st->L_prev = HUGE_VAL;
+      }
       st->P_best = P;
       st->D_best = D;
       st->mgap_ref = HUGE_VAL;
@@ -446,24 +476,24 @@ __global__ __launch_bounds__(1024) void k_cert_finish(MixedDev md, const int* li
   __syncthreads();
   const bool improve = st->b_int0 != 0;
   const bool done = st->done != 0;
-  const int cyc = *md.cycle;
+  const bool fresh = !done && !keep;  // the ring, the operand and the products start at the base
   for (int64_t j = threadIdx.x; j < md.ldp; j += blockDim.x) {
     const double bj = B64[(int64_t)q * md.ldp + j];
     if (improve) md.bres[(int64_t)slot * md.ldp + j] = bj;
     if (!done) {
       md.beta0[(int64_t)slot * md.ldp + j] = bj;
       md.H0[(int64_t)slot * md.ldp + j] = H64[(int64_t)q * md.ldp + j];
-      for (int r = 0; r < 3; ++r) md.bring[(int64_t)r * md.bring_stride + (int64_t)slot * md.ldp + j] = bj;
     }
-    md.dop[frag_index(slot, j, md.S_pad >> 5)] = 0;
+    if (fresh)
+      for (int r = 0; r < 3; ++r) md.bring[(int64_t)r * md.bring_stride + (int64_t)slot * md.ldp + j] = bj;
+    if (!keep || done) md.dop[frag_index(slot, j, md.S_pad >> 5)] = 0;
   }
-  if (!done) {
+  if (fresh) {
     for (int64_t i = threadIdx.x; i < md.n_pad; i += blockDim.x) {
       md.dU[(int64_t)slot * md.n_pad + i] = 0.f;
       md.dU[md.dU_ring + (int64_t)slot * md.n_pad + i] = 0.f;
     }
   }
-  (void)cyc;
 }
 
 // Admission from the cold start beta = 0 (the base quantities are the same for every node:

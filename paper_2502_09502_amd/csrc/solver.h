@@ -48,6 +48,7 @@ struct NodeDev {
   int last_ring;     // ring slot holding the latest prox output (the iterate g_new belongs to)
   int need_base;     // warm start admitted: parked until an FP64 round sets its base point
   double bsq_new;    // ||beta^{t+1}||^2 (eigen-perspective objective)
+  int rebase;        // mixed path: the base moved under a running momentum (next cycle only)
 };
 
 constexpr int kRunning = -1;

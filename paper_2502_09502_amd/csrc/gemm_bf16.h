@@ -15,8 +15,11 @@
 // contiguous 1 KiB access. Fragments are ordered by k-block of 16, then node block of 32.
 //
 // Latency: vector-memory loads retire in issue order, so a wait for one load also waits for
-// every older one. All loads of a k-step (A and B) are therefore issued as one group GT_PD steps
-// ahead of their use; the wait at step s then only concerns the oldest group.
+// every older one. The A tile of a k-step (HBM) is loaded GT_PD steps ahead of its use and the
+// B fragments (L2 resident) GT_PDB steps ahead, B first within a step's group, so that a wait
+// only concerns the oldest loads. The eight A fragments of a step are read from LDS in one
+// group before its MFMAs: the LDS latency is paid once per step rather than once per MFMA pair
+// (and the B registers freed by the shorter B prefetch hold them).
 #pragma once
 
 #include "common.h"
@@ -32,7 +35,8 @@ constexpr int GT_N = 256;
 constexpr int GT_K = 32;
 constexpr int GT_RT = GT_M / 32;  // row tiles per wave
 constexpr int GT_LD = GT_K + 8;   // LDS row pitch in bf16 (80 bytes)
-constexpr int GT_PD = 4;          // k-steps in flight (even: the LDS slot of step s is s & 1)
+constexpr int GT_PD = 4;          // A k-steps in flight (even: the LDS slot of step s is s & 1)
+constexpr int GT_PDB = 2;         // B k-steps in flight (divides GT_PD)
 
 // Element offset of B(node, k) in fragment order with nb node blocks of 32.
 __device__ __forceinline__ int64_t frag_index(int64_t node, int64_t k, int64_t nb) {
@@ -82,17 +86,19 @@ __device__ __forceinline__ void gemm_bf16_mainloop(const GemmArgs& g, int64_t m0
   // body below has no conditionals and the register arrays stay in registers; prefetches past
   // the end re-read the last step (a valid address; the values are not used).
   u32x4 ra[GT_PD][2];
-  bf16x8 rb[GT_PD][2][2];
+  bf16x8 rb[GT_PDB][2][2];
 #pragma unroll
   for (int d = 0; d < GT_PD; ++d) {
+    if (d < GT_PDB) {
+      const uint16_t* b = bg + (int64_t)d * fstep;
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) rb[d][c][ks] = *reinterpret_cast<const bf16x8*>(b + ks * fks + c * 512);
+    }
     const int64_t o = (int64_t)d * GT_K;
     ra[d][0] = *reinterpret_cast<const u32x4*>(ag + o);
     ra[d][1] = *reinterpret_cast<const u32x4*>(ag + ag_hi + o);
-    const uint16_t* b = bg + (int64_t)d * fstep;
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) rb[d][c][ks] = *reinterpret_cast<const bf16x8*>(b + ks * fks + c * 512);
     // issue the groups oldest first, so the in-loop waits see the same order as the steady state
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -107,28 +113,36 @@ __device__ __forceinline__ void gemm_bf16_mainloop(const GemmArgs& g, int64_t m0
       *reinterpret_cast<u32x4*>(slot + arow * GT_LD + ak) = ra[d][0];
       *reinterpret_cast<u32x4*>(slot + (arow + 64) * GT_LD + ak) = ra[d][1];
       __syncthreads();
+      bf16x8 af[2][GT_RT];
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
-        bf16x8 af[GT_RT];
+      for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
         for (int r = 0; r < GT_RT; ++r)
-          af[r] = *reinterpret_cast<const bf16x8*>(slot + (r * 32 + fr) * GT_LD + ks * 16 + fk);
+          af[ks][r] = *reinterpret_cast<const bf16x8*>(slot + (r * 32 + fr) * GT_LD + ks * 16 + fk);
+      __builtin_amdgcn_sched_barrier(0);
+      const int db = d % GT_PDB;
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
 #pragma unroll
         for (int r = 0; r < GT_RT; ++r)
 #pragma unroll
           for (int c = 0; c < 2; ++c)
-            acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[r], rb[d][c][ks], acc[r][c],
+            acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[ks][r], rb[db][c][ks], acc[r][c],
                                                                 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      {
+        const int64_t st = min((int64_t)(s + d + GT_PDB), last);
+        const uint16_t* b = bg + st * fstep;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+            rb[db][c][ks] = *reinterpret_cast<const bf16x8*>(b + ks * fks + c * 512);
       }
       const int64_t st = min((int64_t)(s + d + GT_PD), last);
       ra[d][0] = *reinterpret_cast<const u32x4*>(ag + st * GT_K);
       ra[d][1] = *reinterpret_cast<const u32x4*>(ag + ag_hi + st * GT_K);
-      const uint16_t* b = bg + st * fstep;
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-          rb[d][c][ks] = *reinterpret_cast<const bf16x8*>(b + ks * fks + c * 512);
     }
   }
 }

@@ -6,20 +6,22 @@
 //   C: FP64, node-major (ldc). With split-K the chunks write Q x M partials that a second
 //      kernel sums in a fixed order, so the result does not depend on scheduling.
 //
-// One wave computes a 32-row x 16*NT-node block with v_mfma_f64_16x16x4f64 and needs no LDS
-// and no barrier. The k index of each MFMA is permuted so that every lane's operands are
+// One wave computes a (16 F64_RT)-row x 16*NT-node block with v_mfma_f64_16x16x4f64 and needs
+// no LDS and no barrier. The k index of each MFMA is permuted so that every lane's operands are
 // contiguous in memory: in the 16-wide k-step at k0, lane (i, kk) (i = lane % 16,
 // kk = lane / 16) holds k0 + 4 kk + s for MFMA sub-step s, for A (row i) and B (node i) alike,
 // which leaves the contraction unchanged. A and B fragments go straight from global memory
-// into registers, F64_PD steps ahead; elements past the end of the k-range (padding, whose
-// contents are not guaranteed) are replaced by zero before they enter a product.
+// into registers, F64_PD steps ahead. Elements past the end of the k-range (padding, whose
+// contents are not guaranteed, and the re-read steps that pad the loop) are replaced by zero
+// before they enter a product.
 #pragma once
 
 #include "common.h"
 
 namespace cgl {
 
-constexpr int F64_PD = 4;  // 16-wide k-steps in flight per wave
+constexpr int F64_PD = 2;  // 16-wide k-steps in flight per wave
+constexpr int F64_RT = 4;  // row tiles of 16 per wave
 
 typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64acc4;
 
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(F64GemmArgs g) {
   typedef typename F64Frag<double>::raw b4;
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const int64_t m0 = ((int64_t)blockIdx.x * 4 + wid) * 32;
+  const int64_t m0 = ((int64_t)blockIdx.x * 4 + wid) * (16 * F64_RT);
   if (m0 >= g.M) return;  // no barrier below: a wave past the last row may leave at once
   const int q0 = (int)blockIdx.y * 16 * NT;
   const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
@@ -80,18 +82,18 @@ __global__ __launch_bounds__(256) void k_gemm_f64(F64GemmArgs g) {
   const int li = lane & 15;
   const int kk = lane >> 4;
   // rows and nodes past the end are clamped to the last valid one (their results are dropped)
-  const XT* ap[2];
+  const XT* ap[F64_RT];
 #pragma unroll
-  for (int r = 0; r < 2; ++r)
+  for (int r = 0; r < F64_RT; ++r)
     ap[r] = (const XT*)g.A + min(m0 + 16 * r + li, g.M - 1) * g.lda + kb + 4 * kk;
   const double* bp[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t)
     bp[t] = g.B + (int64_t)min(q0 + 16 * t + li, g.Q - 1) * g.ldb + kb + 4 * kk;
 
-  f64acc4 acc[2][NT];
+  f64acc4 acc[F64_RT][NT];
 #pragma unroll
-  for (int r = 0; r < 2; ++r)
+  for (int r = 0; r < F64_RT; ++r)
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -103,13 +105,13 @@ __global__ __launch_bounds__(256) void k_gemm_f64(F64GemmArgs g) {
     // padded steps re-read the last step (a valid address) and are masked to zero
     const int nsp = (nsteps + F64_PD - 1) / F64_PD * F64_PD;
     const int64_t last = (int64_t)(nsteps - 1) * 16;
-    typename FA::raw ra[F64_PD][2];
+    typename FA::raw ra[F64_PD][F64_RT];
     b4 rb[F64_PD][NT];
 #pragma unroll
     for (int d = 0; d < F64_PD; ++d) {
       const int64_t o = min((int64_t)d * 16, last);
 #pragma unroll
-      for (int r = 0; r < 2; ++r) ra[d][r] = FA::load(ap[r] + o);
+      for (int r = 0; r < F64_RT; ++r) ra[d][r] = FA::load(ap[r] + o);
 #pragma unroll
       for (int t = 0; t < NT; ++t) rb[d][t] = *reinterpret_cast<const b4*>(bp[t] + o);
       __builtin_amdgcn_sched_barrier(0);
@@ -119,25 +121,25 @@ __global__ __launch_bounds__(256) void k_gemm_f64(F64GemmArgs g) {
       for (int d = 0; d < F64_PD; ++d) {
         __builtin_amdgcn_sched_barrier(0);
         const int64_t kl = kb + (int64_t)(s + d) * 16 + 4 * kk;  // this lane's first k
-        double a[2][4], b[NT][4];
+        double a[F64_RT][4], b[NT][4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const bool ok = kl + e < ke;
 #pragma unroll
-          for (int r = 0; r < 2; ++r) a[r][e] = ok ? FA::get(ra[d][r], e) : 0.0;
+          for (int r = 0; r < F64_RT; ++r) a[r][e] = ok ? FA::get(ra[d][r], e) : 0.0;
 #pragma unroll
           for (int t = 0; t < NT; ++t) b[t][e] = ok ? rb[d][t][e] : 0.0;
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e)
 #pragma unroll
-          for (int r = 0; r < 2; ++r)
+          for (int r = 0; r < F64_RT; ++r)
 #pragma unroll
             for (int t = 0; t < NT; ++t)
               acc[r][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r][e], b[t][e], acc[r][t], 0, 0, 0);
         const int64_t o = min((int64_t)(s + d + F64_PD) * 16, last);
 #pragma unroll
-        for (int r = 0; r < 2; ++r) ra[d][r] = FA::load(ap[r] + o);
+        for (int r = 0; r < F64_RT; ++r) ra[d][r] = FA::load(ap[r] + o);
 #pragma unroll
         for (int t = 0; t < NT; ++t) rb[d][t] = *reinterpret_cast<const b4*>(bp[t] + o);
       }
@@ -146,7 +148,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(F64GemmArgs g) {
   // C tile element (i, j) sits in lane j + 16 (i % 4), accumulator element i / 4
   double* C = g.C + (int64_t)blockIdx.z * g.Q * g.ldc;
 #pragma unroll
-  for (int r = 0; r < 2; ++r)
+  for (int r = 0; r < F64_RT; ++r)
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll

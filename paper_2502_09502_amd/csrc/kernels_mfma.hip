@@ -665,7 +665,7 @@ void launch_gemm_f64(int xtype, const void* A, int64_t lda, int64_t M, int64_t K
   if (Q <= 0 || M <= 0) return;
   // node tile: 32 when that pads Q no further than 16 would, else 16
   const int nt = ((Q + 31) / 32 * 32 == (Q + 15) / 16 * 16) ? 2 : 1;
-  const int64_t mblocks = (M + 127) / 128;
+  const int64_t mblocks = (M + 64 * F64_RT - 1) / (64 * F64_RT);
   const int64_t qblocks = (Q + 16 * nt - 1) / (16 * nt);
   const int64_t steps = std::max<int64_t>(1, (K + 15) / 16);
   // split K until there are about 4 workgroups per compute unit, each chunk >= 32 steps

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -34,6 +35,12 @@ void MixedWork::ensure(Problem& P) {
   if (ready) return;
   hipStream_t s = P.ctx->stream;
   std::fill(want_since, want_since + kSlots, (int64_t)-1);
+  // batching of the certification rounds (tuning knobs; the defaults suit the 256-slot engine)
+  for (auto [name, dst] : {std::pair<const char*, int*>{"CGL_CERT_BATCH", &cert_batch},
+                           std::pair<const char*, int*>{"CGL_CERT_WAIT", &cert_wait}}) {
+    const char* e = std::getenv(name);
+    if (e && std::atoi(e) > 0) *dst = std::atoi(e);
+  }
   S = kSlots;
   S_pad = (int)round_up(S, 256);
   n_pad = round_up(P.n, 128);  // rows of X~: a multiple of the GEMM tile and of its k-chunk grain
@@ -319,7 +326,7 @@ void MixedWork::run_chunk(Problem& P) {
 
 bool MixedWork::cert_round(Problem& P) {
   // Batch the FP64 rounds: a node that asks for certification keeps iterating until enough
-  // nodes ask (kCertBatch), the oldest request has waited kCertWait chunks, or every active node
+  // nodes ask (cert_batch), the oldest request has waited cert_wait chunks, or every active node
   // is waiting, so each round's FP64 products are shared by more nodes.
   std::vector<int> want;
   int active = 0;
@@ -343,7 +350,7 @@ bool MixedWork::cert_round(Problem& P) {
   const int nq = (int)want.size();
   bool parked = false;  // a warm start waiting for its base point cannot wait for others
   for (int sl : want) parked = parked || st_host[sl].need_base;
-  if (!parked && nq < kCertBatch && nq < active && cycles - oldest < (int64_t)kCertWait * kChunk)
+  if (!parked && nq < cert_batch && nq < active && cycles - oldest < (int64_t)cert_wait * kChunk)
     return false;
   hipStream_t s = P.ctx->stream;
   cgl_ctx* ctx = P.ctx;

@@ -14,7 +14,7 @@ namespace cgl {
 constexpr int kSlots = 256;  // node slots per problem
 constexpr int kChunk = 4;    // iterations per graph launch between host checks
 constexpr int kCertBatch = 32;  // certification requests that trigger a round at once
-constexpr int kCertWait = 2;    // chunks the oldest request may wait for others
+constexpr int kCertWait = 1;    // chunks the oldest request may wait for others
 
 struct Admission {
   int slot;
@@ -43,6 +43,8 @@ struct MixedWork {
   int64_t want_since[kSlots];  // cycle at which a slot's certification request was first seen
   int64_t cycles = 0;
   int64_t cert_rounds = 0;
+  int cert_batch = kCertBatch;  // CGL_CERT_BATCH overrides
+  int cert_wait = kCertWait;    // CGL_CERT_WAIT overrides
   hipGraphExec_t graph_exec = nullptr;  // kChunk cycles
   MixedDev md{};
 

@@ -27,6 +27,7 @@ Problem::~Problem() { delete mixed; }
 MixedWork::~MixedWork() {
   if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
   if (st_host) (void)hipHostFree(st_host);
+  if (beta_host) (void)hipHostFree(beta_host);
 }
 
 static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -140,6 +141,7 @@ void MixedWork::ensure(Problem& P) {
     f_cold = f0;
   }
   CGL_HIP(hipHostMalloc(&st_host, (size_t)S * sizeof(NodeDev), hipHostMallocDefault));
+  CGL_HIP(hipHostMalloc(&beta_host, (size_t)S * P.p * sizeof(double), hipHostMallocDefault));
   std::memset(st_host, 0, (size_t)S * sizeof(NodeDev));
   CGL_HIP(hipMemcpyAsync(st.ptr, st_host, (size_t)S * sizeof(NodeDev), hipMemcpyHostToDevice, s));
   cls_host.assign(Sp, CLS_PAD);
@@ -455,25 +457,43 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
   CGL_HIP(hipStreamSynchronize(s));
 }
 
-void MixedWork::retire(Problem& P, int sl, cgl_result* res, double* beta_out) {
+void MixedWork::retire(Problem& P, const std::vector<int>& slots,
+                       const std::vector<cgl_result*>& res, const std::vector<double*>& beta_out) {
   hipStream_t s = P.ctx->stream;
-  const NodeDev& d = st_host[sl];
-  res->primal = d.P_cert;
-  res->lower_bound = d.D_cert;
-  res->gap_abs = d.P_cert - d.D_cert;
-  res->gap_rel = res->gap_abs / std::max(std::fabs(d.P_cert), 1.0);
-  res->iters = d.iter - 1;
-  res->restarts = d.restarts;
-  res->status = d.status == kRunning ? CGL_NOT_CONVERGED : d.status;
-  res->recentres = d.recentres;
-  res->err_vs_fp64_est = std::isfinite(d.P_cert)
+  std::vector<int> rows;  // slots whose iterate is wanted, in the order of their staging rows
+  for (size_t i = 0; i < slots.size(); ++i) {
+    const int sl = slots[i];
+    const NodeDev& d = st_host[sl];
+    cgl_result* r = res[i];
+    r->primal = d.P_cert;
+    r->lower_bound = d.D_cert;
+    r->gap_abs = d.P_cert - d.D_cert;
+    r->gap_rel = r->gap_abs / std::max(std::fabs(d.P_cert), 1.0);
+    r->iters = d.iter - 1;
+    r->restarts = d.restarts;
+    r->status = d.status == kRunning ? CGL_NOT_CONVERGED : d.status;
+    r->recentres = d.recentres;
+    r->err_vs_fp64_est = std::isfinite(d.P_cert)
                              ? std::fabs(d.L_work - d.P_cert) / std::max(std::fabs(d.P_cert), 1.0)
                              : 0.0;
-  if (beta_out)
-    CGL_HIP(hipMemcpyAsync(beta_out, bres.as<double>() + (int64_t)sl * ldp, (size_t)P.p * 8,
+    if (beta_out[i]) rows.push_back(sl);
+  }
+  if (!rows.empty()) {
+    const int nq = (int)rows.size();
+    CGL_HIP(hipMemcpyAsync(list.ptr, rows.data(), (size_t)nq * sizeof(int), hipMemcpyHostToDevice, s));
+    launch_gather_rows(bres.as<double>(), ldp, list.as<int>(), nq, P.p, B64.as<double>(), s);
+    CGL_HIP(hipMemcpyAsync(beta_host, B64.ptr, (size_t)nq * P.p * sizeof(double),
                            hipMemcpyDeviceToHost, s));
-  st_host[sl].active = 0;
-  slot_owner[(size_t)sl] = -1;
+    CGL_HIP(hipStreamSynchronize(s));
+    size_t q = 0;
+    for (size_t i = 0; i < slots.size(); ++i)
+      if (beta_out[i])
+        std::memcpy(beta_out[i], beta_host + (q++) * P.p, (size_t)P.p * sizeof(double));
+  }
+  for (int sl : slots) {
+    st_host[sl].active = 0;
+    slot_owner[(size_t)sl] = -1;
+  }
 }
 
 // Upload the host image of the slot states (after retire/admit edits; the device is idle).
@@ -532,15 +552,19 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
     phase(5, [&] { W.run_chunk(P); });
     phase(6, [&] { W.cert_round(P); });
     phase(7, [&] {
-      bool changed = false;
+      std::vector<int> done;
+      std::vector<cgl_result*> rs;
+      std::vector<double*> bs;
       for (int sl = 0; sl < W.S; ++sl) {
         const int owner = W.slot_owner[(size_t)sl];
         if (owner < 0 || !W.st_host[sl].done) continue;
-        W.retire(P, sl, &res[owner], beta_out ? beta_out + (int64_t)owner * P.p : nullptr);
-        ++finished;
-        changed = true;
+        done.push_back(sl);
+        rs.push_back(&res[owner]);
+        bs.push_back(beta_out ? beta_out + (int64_t)owner * P.p : nullptr);
       }
-      if (changed) {
+      if (!done.empty()) {
+        W.retire(P, done, rs, bs);
+        finished += (int32_t)done.size();
         W.push_states(P);
         fill();
       }

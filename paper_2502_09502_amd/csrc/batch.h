@@ -37,6 +37,7 @@ struct MixedWork {
       fpart, cycle, prevsel, B64, U64, R64, H64, cpart, list, H0_cold, base0_cold, base1_cold, Xt, part64;
   size_t part64_cap = 0;
   NodeDev* st_host = nullptr;
+  double* beta_host = nullptr;  // pinned staging of retired iterates (S x p)
   std::vector<uint8_t> cls_host;
   std::vector<int> slot_owner;
   int64_t admitted_at[kSlots] = {0};
@@ -57,7 +58,11 @@ struct MixedWork {
   void run_chunk(Problem& P);
   bool cert_round(Problem& P);
   void admit(Problem& P, const std::vector<Admission>& adm);
-  void retire(Problem& P, int slot, cgl_result* res, double* beta_out);
+  // Results of finished slots and their best certified iterates (beta_out[i] may be null): one
+  // gather of the iterates on the device, one copy to pinned host memory, then into the
+  // callers' buffers. The slots are freed.
+  void retire(Problem& P, const std::vector<int>& slots, const std::vector<cgl_result*>& res,
+              const std::vector<double*>& beta_out);
   void push_states(Problem& P);
   int free_slots() const;
   size_t device_bytes() const;  // device memory held by this engine

@@ -533,6 +533,23 @@ void launch_admit(const MixedDev& md, const int* list, int nq, const double* H0_
                      base0_cold, base1_cold);
 }
 
+// dst (nq x p, contiguous) = rows list[q] of src (leading dimension ld).
+__global__ __launch_bounds__(256) void k_gather_rows(const double* src, int64_t ld, const int* list,
+                                                     int nq, int64_t p, double* dst) {
+  const int q = blockIdx.y;
+  if (q >= nq) return;
+  const double* r = src + (int64_t)list[q] * ld;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < p; j += (int64_t)gridDim.x * 256)
+    dst[(int64_t)q * p + j] = r[j];
+}
+
+void launch_gather_rows(const double* src, int64_t ld, const int* list, int nq, int64_t p,
+                        double* dst, hipStream_t s) {
+  if (nq <= 0) return;
+  hipLaunchKernelGGL(k_gather_rows, dim3(8, (unsigned)nq), dim3(256), 0, s, src, ld, list, nq, p,
+                     dst);
+}
+
 // Zero a slot's operand rows (retired or empty slots must not contribute to the products).
 __global__ __launch_bounds__(256) void k_slot_clear(MixedDev md, int slot) {
   for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < md.ldp; j += (int64_t)gridDim.x * 256)

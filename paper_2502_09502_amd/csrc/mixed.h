@@ -74,6 +74,9 @@ void launch_cert_resid(const MixedDev& md, const int* list, int nq, const double
 void launch_cert_finish(const MixedDev& md, const int* list, int nq, const double* B64,
                         const double* H64, const double* part, int nchunk, hipStream_t s);
 void launch_slot_clear(const MixedDev& md, int slot, hipStream_t s);
+// dst (nq x p, contiguous) = rows list[q] of src (leading dimension ld).
+void launch_gather_rows(const double* src, int64_t ld, const int* list, int nq, int64_t p,
+                        double* dst, hipStream_t s);
 void launch_admit(const MixedDev& md, const int* list, int nq, const double* H0_cold,
                   const double* base0_cold, const double* base1_cold, hipStream_t s);
 

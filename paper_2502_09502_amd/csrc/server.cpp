@@ -202,19 +202,26 @@ void run_round(cgl_server& S) {
     MixedWork& W = *P.mixed;
     W.run_chunk(P);
     W.cert_round(P);
-    bool changed = false;
+    std::vector<int> done;
     for (int sl = 0; sl < W.S; ++sl) {
-      std::unique_ptr<Request>& r = R.slot_req[(size_t)sl];
-      if (!r) continue;
-      if (!W.st_host[sl].done && !r->cancelled) continue;
-      cgl_result res{};
-      std::vector<double> beta((size_t)P.p);
-      W.retire(P, sl, &res, beta.data());
-      if (r->cancelled) res.status = CGL_CANCELLED;
-      finish(S, std::move(r), res, std::move(beta));
-      changed = true;
+      const std::unique_ptr<Request>& r = R.slot_req[(size_t)sl];
+      if (r && (W.st_host[sl].done || r->cancelled)) done.push_back(sl);
     }
-    if (changed) {
+    if (!done.empty()) {
+      std::vector<cgl_result> res(done.size());
+      std::vector<std::vector<double>> betas(done.size(), std::vector<double>((size_t)P.p));
+      std::vector<cgl_result*> rs;
+      std::vector<double*> bs;
+      for (size_t i = 0; i < done.size(); ++i) {
+        rs.push_back(&res[i]);
+        bs.push_back(betas[i].data());
+      }
+      W.retire(P, done, rs, bs);
+      for (size_t i = 0; i < done.size(); ++i) {
+        std::unique_ptr<Request>& r = R.slot_req[(size_t)done[i]];
+        if (r->cancelled) res[i].status = CGL_CANCELLED;
+        finish(S, std::move(r), res[i], std::move(betas[i]));
+      }
       W.push_states(P);
       CGL_HIP(hipStreamSynchronize(P.ctx->stream));
     }

@@ -221,10 +221,12 @@ void MixedWork::set_split_xt(int ks) {
 }
 
 // Autotuner of the split-K of both products: every candidate is launched on the engine's own
-// buffers (the operands are still zero, the partials are scratch) and timed with HIP events;
-// the fastest wins (a larger split must be 2% faster to be taken, since its partial sums cost
-// the next kernel). Results are kept on the context per (pass, rows, k-length, nodes);
-// CGL_AUTOTUNE=0 keeps the first candidate that fills the chip in one round.
+// buffers (the operands are still zero, the partials are scratch) and timed with HIP events.
+// Its cost is that time plus the reading of its partial sums by the next kernel (one FP32 slab
+// of nodes x rows per chunk, charged at 4 TB/s, about what the consumers achieve); the cheapest
+// wins, a larger split only when it is 2% cheaper. Results are kept on the context per (pass,
+// rows, k-length, nodes); CGL_AUTOTUNE=0 keeps the first candidate that fills the chip in one
+// round.
 void MixedWork::tune_splits(Problem& P) {
   cgl_ctx* ctx = P.ctx;
   hipStream_t s = ctx->stream;
@@ -246,6 +248,7 @@ void MixedWork::tune_splits(Problem& P) {
     for (int ks : cand)  // without timing: the largest split that runs in one round
       if (m_tiles * ks <= 512) choice = ks;
     if (tune && cand.size() > 1) {
+      const double slab_ms = (double)S_pad * (pass == 0 ? n_pad : ldp) * 4.0 / 4e12 * 1e3;
       double best = HUGE_VAL;
       for (int ks : cand) {
         set(ks);
@@ -256,8 +259,9 @@ void MixedWork::tune_splits(Problem& P) {
         CGL_HIP(hipEventSynchronize(ctx->event(1)));
         float ms = 0.f;
         CGL_HIP(hipEventElapsedTime(&ms, ctx->event(0), ctx->event(1)));
-        if (ms < best * 0.98) {
-          best = ms;
+        const double cost = ms / 3.0 + ks * slab_ms;
+        if (cost < best * 0.98) {
+          best = cost;
           choice = ks;
         }
       }

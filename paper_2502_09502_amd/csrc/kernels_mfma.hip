@@ -229,12 +229,19 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
     int cs = CLS_PAD;
     if (j < p) {
       h = H0[j];
-      for (int q = 0; q < md.ksplit; ++q)
-        h += (double)md.dH[(int64_t)q * md.dH_split + (int64_t)slot * md.ldp + j];
       cs = cl[j];
     }
     pv.set(s, h);
     cb |= (uint64_t)cs << (2 * s);
+  }
+  // split-K partials slab by slab, each a loop of independent loads (same summation order)
+  for (int q = 0; q < md.ksplit; ++q) {
+    const float* dq = md.dH + (int64_t)q * md.dH_split + (int64_t)slot * md.ldp;
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
+      if (j < p) pv.set(s, pv.get(s) + (double)dq[j]);
+    }
   }
   // dual monitor at gamma: D = -F*(-zeta) - 2 lambda2 g_node*(-grad F(gamma) / (2 lambda2))
   // element-indexed view of the LDS slice for the warm-started selections

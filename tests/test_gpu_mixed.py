@@ -46,6 +46,19 @@ def test_small_batch_matches_oracle(loss, dtype):
         _check(d, r, z0, z1)
 
 
+def test_repeated_recentring_to_tight_gap():
+    """A tolerance far below the BF16 floor makes every node re-centre several times; a re-centre
+    moves the base point under the running momentum (Alg. 3 restarts only on an objective
+    increase), and the certified results still match the oracle."""
+    d = synth.make_dataset(500, 200, 8, config_id=83)
+    prob = _problem(d)
+    sets = synth.node_sets(d.p, d.k, 6, 12, config_id=83)
+    res = prob.solve_batch(_specs(prob, sets, tol=1e-8, max_iter=20000))
+    assert max(r.recentres for r in res) >= 2
+    for (z0, z1), r in zip(sets, res):
+        _check(d, r, z0, z1, tol=1e-8)
+
+
 def test_config1_mixed_root():
     d = synth.make_config("c1")
     prob = _problem(d)

@@ -15,6 +15,7 @@
 
 #include "common.h"
 #include "engine.h"
+#include "gemm_bf16.h"
 #include "kernels.h"
 #include "losses.h"
 #include "mixed.h"
@@ -44,7 +45,7 @@ void MixedWork::ensure(Problem& P) {
   }
   S = kSlots;
   S_pad = (int)round_up(S, 256);
-  n_pad = round_up(P.n, 128);  // rows of X~: a multiple of the GEMM tile and of its k-chunk grain
+  n_pad = round_up(P.n, GT_M);  // rows of X~: a multiple of the GEMM tile and of its k-chunk grain
   ldp = P.ldx;
   // BF16 design and its transpose
   Xb.alloc((size_t)n_pad * ldp * 2);
@@ -68,11 +69,11 @@ void MixedWork::ensure(Problem& P) {
   gop.alloc((size_t)S_pad * n_pad * 2);
   dU.alloc(2 * (size_t)S_pad * n_pad * 4);
   // split-K of the two products: the candidates keep >= 16 k-steps of 32 per chunk and at most
-  // two rounds of 512 workgroups (two 128-row workgroups fit on a compute unit at once); the
+  // four rounds of 256 workgroups (one workgroup of the product fits on a compute unit); the
   // partial buffers are sized for the largest candidate and the choice is made by timing
   // (tune_splits) once the buffers exist
-  split_cands_x = split_candidates(n_pad / 128, ldp);
-  split_cands_xt = split_candidates(ldp / 128, n_pad);
+  split_cands_x = split_candidates(n_pad / GT_M, ldp);
+  split_cands_xt = split_candidates(ldp / GT_M, n_pad);
   set_split_x(split_cands_x.front());
   set_split_xt(split_cands_xt.front());
   dUp.alloc((size_t)split_cands_x.back() * S_pad * n_pad * 4);
@@ -234,7 +235,7 @@ void MixedWork::tune_splits(Problem& P) {
   const bool tune = !(env && env[0] == '0');
   for (int pass = 0; pass < 2; ++pass) {
     const std::vector<int>& cand = pass == 0 ? split_cands_x : split_cands_xt;
-    const int64_t m_tiles = pass == 0 ? n_pad / 128 : ldp / 128;
+    const int64_t m_tiles = pass == 0 ? n_pad / GT_M : ldp / GT_M;
     const std::array<int64_t, 4> key = {pass, pass == 0 ? n_pad : ldp, pass == 0 ? ldp : n_pad,
                                         (int64_t)S_pad};
     auto set = [&](int ks) { pass == 0 ? set_split_x(ks) : set_split_xt(ks); };
@@ -246,7 +247,7 @@ void MixedWork::tune_splits(Problem& P) {
     }
     int choice = cand.back();
     for (int ks : cand)  // without timing: the largest split that runs in one round
-      if (m_tiles * ks <= 512) choice = ks;
+      if (m_tiles * ks <= 256) choice = ks;
     if (tune && cand.size() > 1) {
       const double slab_ms = (double)S_pad * (pass == 0 ? n_pad : ldp) * 4.0 / 4e12 * 1e3;
       double best = HUGE_VAL;

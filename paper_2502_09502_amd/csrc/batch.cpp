@@ -83,7 +83,7 @@ void MixedWork::ensure(Problem& P) {
   lpart.alloc((size_t)S * nrt * 8);
   fpart.alloc((size_t)S * nrt * 8);
   cycle.alloc(sizeof(int));
-  CGL_HIP(hipMemsetAsync(cycle.ptr, 0, sizeof(int), s));
+  CGL_HIP(hipMemsetAsync(cycle.ptr, 0xff, sizeof(int), s));  // -1: the first cycle is 0
   prevsel.alloc((size_t)2 * S * 65 * sizeof(int));
   CGL_HIP(hipMemsetAsync(prevsel.ptr, 0, prevsel.bytes, s));
   CGL_HIP(hipMemsetAsync(dop.ptr, 0, (size_t)S_pad * ldp * 2, s));
@@ -276,16 +276,14 @@ void MixedWork::tune_splits(Problem& P) {
 // passes for kernel timing.
 static void mixed_cycle(MixedWork& W, hipStream_t s, hipEvent_t* ev = nullptr) {
   if (ev) CGL_HIP(hipEventRecord(ev[0], s));
-  launch_gemm_x(W.md, s);
+  launch_gemm_x(W.md, s, true);
   if (ev) CGL_HIP(hipEventRecord(ev[1], s));
   launch_mixed_loss(W.md, s);
-  launch_mixed_restart(W.md, s);
   launch_mixed_resid(W.md, s);
   if (ev) CGL_HIP(hipEventRecord(ev[2], s));
   launch_gemm_xt(W.md, s);
   if (ev) CGL_HIP(hipEventRecord(ev[3], s));
   launch_mixed_node(W.md, s);
-  launch_cycle_advance(W.md, s);
 }
 
 static bool mixed_graphs() {

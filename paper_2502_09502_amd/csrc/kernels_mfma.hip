@@ -13,8 +13,9 @@
 // correction, which shrinks as the iterate approaches the base; the base is re-centred in FP64
 // (and the bound certified, Sec. 3.4) when the working-precision gap stops improving.
 //
-// One iteration (cycle) for every active slot: k_gemm_x (split-K) -> k_mixed_loss ->
-// k_mixed_restart -> k_mixed_resid -> k_gemm_xt (split-K) -> k_mixed_node (prox) -> k_cycle_advance.
+// One iteration (cycle) for every active slot: k_gemm_x (split-K; it also advances the cycle
+// counter) -> k_mixed_loss -> k_mixed_resid (restart test and residual operand) -> k_gemm_xt
+// (split-K) -> k_mixed_node (prox; commits the restart test).
 #include <limits.h>
 
 #include <algorithm>
@@ -51,9 +52,14 @@ __device__ __forceinline__ bool slot_running(const NodeDev* st) {
 // (row tile, k-chunk) pairs, ordered k-chunk-major, are cut into 8 contiguous ranges and range x
 // is given to the ids that land on XCD x. The workgroups of one XCD then share one or two
 // k-chunks of B in that XCD's L2. Node tiles (blockIdx.y) are outermost.
+//
+// bump (optional): the cycle counter, advanced by one thread of the launch; no kernel of the
+// launch reads it and the kernels after it see the new value.
 template <int PASS>
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int mtiles, int ks, int per_xcd) {
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int mtiles, int ks, int per_xcd,
+                                                   int* bump) {
   __shared__ __attribute__((aligned(16))) uint16_t As[2 * GT_M * GT_LD];
+  if (bump != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *bump += 1;
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
   const int pair = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
@@ -125,49 +131,54 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
 }
 
 // =====================================================================================
-// Per-slot restart test (Alg. 3): L^{t+1} = f(X beta^{t+1}) + 2 lambda2 g(beta^{t+1}).
-// =====================================================================================
-__global__ __launch_bounds__(64) void k_mixed_restart(MixedDev md) {
-  NodeDev* st = md.st + blockIdx.x;
-  if (!slot_running(st)) return;
-  double a = 0.0;
-  for (int i = threadIdx.x; i < md.nrt; i += 64) a += md.lpart[(int64_t)blockIdx.x * md.nrt + i];
-  a = wave_sum(a);
-  if (threadIdx.x == 0) {
-    const double Lnew = a + 2.0 * md.lam2 * st->g_new;
-    st->L_work = Lnew;
-    if (!st->primed) {
-      st->primed = 1;
-    } else if (st->rebase) {
-      // L^t was evaluated against the previous base: the momentum runs on untested
-      st->phi += 1.0;
-    } else if (Lnew >= st->L_prev) {
-      st->phi = 1.0;
-      st->restarts += 1;
-    } else {
-      st->phi += 1.0;
-    }
-    st->L_prev = Lnew;
-    if (Lnew < st->P_best) st->P_best = Lnew;  // working-precision best (monitor only)
-    st->c = st->phi / (st->phi + 3.0);
-    st->rebase = 0;  // read by the loss kernel of this cycle only
-  }
-}
-
-// =====================================================================================
-// Residual operand: u_gamma = u_0 + dU^{t+1} + c (dU^{t+1} - dU^t); r = grad f(u_gamma);
-// G = bf16(r - r_0); F*(-zeta) partial sums with zeta = -r (dual monitor at gamma).
+// Restart test (Alg. 3) and residual operand. Every block of a slot evaluates the test from the
+// slot's state (L^{t+1} = f(X beta^{t+1}) + 2 lambda2 g(beta^{t+1}) from the loss partials, in a
+// fixed order) to get the momentum coefficient c; block 0 stores c and the outcome, which the
+// node kernel commits (no block of this kernel writes what another reads).
+// Then u_gamma = u_0 + dU^{t+1} + c (dU^{t+1} - dU^t); r = grad f(u_gamma); G = bf16(r - r_0);
+// F*(-zeta) partial sums with zeta = -r (dual monitor at gamma).
 // grid: (chunks, slots); 256 threads.
 // =====================================================================================
 __global__ __launch_bounds__(256) void k_mixed_resid(MixedDev md) {
   __shared__ double red[4];
+  __shared__ double cs;
   const int slot = blockIdx.y;
-  const NodeDev* st = md.st + slot;
+  NodeDev* st = md.st + slot;
   if (!slot_running(st)) return;
   const int cyc = *md.cycle;
   const float* dun = md.dU + (int64_t)(cyc & 1) * md.dU_ring + (int64_t)slot * md.n_pad;
   const float* duo = md.dU + (int64_t)((cyc + 1) & 1) * md.dU_ring + (int64_t)slot * md.n_pad;
-  const double c = st->c;
+  if (threadIdx.x < 64) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < md.nrt; i += 64) a += md.lpart[(int64_t)slot * md.nrt + i];
+    a = wave_sum(a);
+    if (threadIdx.x == 0) {
+      const double Lnew = a + 2.0 * md.lam2 * st->g_new;
+      double phi = st->phi;
+      int primed = st->primed, restarts = st->restarts;
+      if (!primed) {
+        primed = 1;
+      } else if (st->rebase) {
+        // L^t was evaluated against the previous base: the momentum runs on untested
+        phi += 1.0;
+      } else if (Lnew >= st->L_prev) {
+        phi = 1.0;
+        restarts += 1;
+      } else {
+        phi += 1.0;
+      }
+      cs = phi / (phi + 3.0);
+      if (blockIdx.x == 0) {
+        st->c = cs;
+        st->rs_phi = phi;
+        st->rs_L = Lnew;
+        st->rs_primed = primed;
+        st->rs_restarts = restarts;
+      }
+    }
+  }
+  __syncthreads();
+  const double c = cs;
   const int64_t i0 = (int64_t)blockIdx.x * md.rchunk;
   const int64_t i1 = min(md.n_pad, i0 + md.rchunk);
   double fs = 0.0;
@@ -213,6 +224,15 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
   const double* H0 = md.H0 + (int64_t)slot * md.ldp;
   const double* b0 = md.beta0 + (int64_t)slot * md.ldp;
   const uint8_t* cl = md.cls + (int64_t)slot * md.ldp;
+  if (threadIdx.x == 0) {  // commit the restart test of this cycle
+    st->phi = st->rs_phi;
+    st->primed = st->rs_primed;
+    st->restarts = st->rs_restarts;
+    st->L_prev = st->rs_L;
+    st->L_work = st->rs_L;
+    if (st->rs_L < st->P_best) st->P_best = st->rs_L;  // working-precision best (monitor only)
+    st->rebase = 0;  // read by the loss and residual kernels of this cycle only
+  }
   const double c = st->c;
   const double invL = 1.0 / md.L;
   const int iter = st->iter;
@@ -309,10 +329,6 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
     st->iter = iter + 1;
     st->last_ring = (cyc + 1) % 3;
   }
-}
-
-__global__ void k_cycle_advance(int* cycle) {
-  if (threadIdx.x == 0) *cycle += 1;
 }
 
 // =====================================================================================
@@ -417,7 +433,7 @@ __global__ __launch_bounds__(1024) void k_cert_finish(MixedDev md, const int* li
   const int slot = list[q];
   NodeDev* st = md.st + slot;
   const int64_t p = md.p;
-  const int cyc = *md.cycle;
+  const int cyc = *md.cycle + 1;  // the cycle the slot runs next (the counter holds the last one)
   const bool keep = keeps_momentum(st, cyc);
   const uint8_t* cl = md.cls + (int64_t)slot * md.ldp;
   __shared__ double vbuf[ProxVals<E>::lds ? E * kProxThreads : 1];
@@ -604,7 +620,7 @@ void launch_make_bf16(int xtype, const void* X, int64_t ldx, int64_t n, int64_t 
     hipLaunchKernelGGL(k_make_bf16<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)X, ldx, n, p, n_pad, ldp, Xb, Xbt);
 }
 
-void launch_gemm_x(const MixedDev& md, hipStream_t s) {
+void launch_gemm_x(const MixedDev& md, hipStream_t s, bool advance) {
   GemmArgs g;
   g.A = md.Xb;
   g.lda = md.ldp;
@@ -618,7 +634,8 @@ void launch_gemm_x(const MixedDev& md, hipStream_t s) {
   g.c_split_stride = md.dUp_split;
   const int mt = (int)(md.n_pad / GT_M), per = (mt * md.ksx + 7) / 8;
   dim3 grid((unsigned)(8 * per), (unsigned)(md.S_pad / GT_N));
-  hipLaunchKernelGGL(k_gemm_bf16<0>, grid, dim3(256), 0, s, g, mt, md.ksx, per);
+  hipLaunchKernelGGL(k_gemm_bf16<0>, grid, dim3(256), 0, s, g, mt, md.ksx, per,
+                     advance ? md.cycle : nullptr);
 }
 
 void launch_gemm_xt(const MixedDev& md, hipStream_t s) {
@@ -635,16 +652,12 @@ void launch_gemm_xt(const MixedDev& md, hipStream_t s) {
   g.c_split_stride = md.dH_split;
   const int mt = (int)(md.ldp / GT_M), per = (mt * md.ksplit + 7) / 8;
   dim3 grid((unsigned)(8 * per), (unsigned)(md.S_pad / GT_N));
-  hipLaunchKernelGGL(k_gemm_bf16<1>, grid, dim3(256), 0, s, g, mt, md.ksplit, per);
+  hipLaunchKernelGGL(k_gemm_bf16<1>, grid, dim3(256), 0, s, g, mt, md.ksplit, per, nullptr);
 }
 
 void launch_mixed_loss(const MixedDev& md, hipStream_t s) {
   hipLaunchKernelGGL(k_mixed_loss, dim3((unsigned)md.nrt, (unsigned)md.slots), dim3(256), 0, s,
                      md);
-}
-
-void launch_mixed_restart(const MixedDev& md, hipStream_t s) {
-  hipLaunchKernelGGL(k_mixed_restart, dim3(md.slots), dim3(64), 0, s, md);
 }
 
 void launch_mixed_resid(const MixedDev& md, hipStream_t s) {
@@ -666,10 +679,6 @@ void launch_mixed_resid(const MixedDev& md, hipStream_t s) {
 void launch_mixed_node(const MixedDev& md, hipStream_t s) {
   const int E = prox_elems(md.p);
   CGL_E_SWITCH(E, hipLaunchKernelGGL(k_mixed_node<EE>, dim3(md.slots), dim3(kProxThreads), 0, s, md));
-}
-
-void launch_cycle_advance(const MixedDev& md, hipStream_t s) {
-  hipLaunchKernelGGL(k_cycle_advance, dim3(1), dim3(64), 0, s, md.cycle);
 }
 
 void launch_transpose(int xtype, const void* X, int64_t ldx, int64_t n, int64_t p, int64_t n_pad,

@@ -46,20 +46,19 @@ struct MixedDev {
   double* fpart;        // S x nrt F* partials (residual kernel)
   int nrt;
   int64_t rchunk;
-  int* cycle;           // global cycle counter
+  int* cycle;           // cycle counter: the cycle running, or between cycles the last one run
   int* prevhead;        // S x 65: last prox head selection (count, indices) per slot
   int* prevtop;         // S x 65: last top-k' selection of the dual monitor per slot
 };
 
 void launch_make_bf16(int xtype, const void* X, int64_t ldx, int64_t n, int64_t p, int64_t n_pad,
                       int64_t ldp, uint16_t* Xb, uint16_t* Xbt, hipStream_t s);
-void launch_gemm_x(const MixedDev& md, hipStream_t s);
+// advance: the launch also advances the cycle counter (the first launch of a cycle)
+void launch_gemm_x(const MixedDev& md, hipStream_t s, bool advance = false);
 void launch_gemm_xt(const MixedDev& md, hipStream_t s);
 void launch_mixed_loss(const MixedDev& md, hipStream_t s);
-void launch_mixed_restart(const MixedDev& md, hipStream_t s);
 void launch_mixed_resid(const MixedDev& md, hipStream_t s);
 void launch_mixed_node(const MixedDev& md, hipStream_t s);
-void launch_cycle_advance(const MixedDev& md, hipStream_t s);
 // C[q][m] = sum_k A[m][k] B[q][k] in FP64 (A row-major in the design's stored precision);
 // part: split-K scratch of part_cap bytes (the split is limited to what fits).
 void launch_gemm_f64(int xtype, const void* A, int64_t lda, int64_t M, int64_t K,

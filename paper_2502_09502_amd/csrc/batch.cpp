@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <stdexcept>
 #include <vector>
 
 #include "common.h"
@@ -29,6 +30,7 @@ MixedWork::~MixedWork() {
   if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
   if (st_host) (void)hipHostFree(st_host);
   if (beta_host) (void)hipHostFree(beta_host);
+  if (count_host) (void)hipHostFree(count_host);
 }
 
 static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -97,6 +99,13 @@ void MixedWork::ensure(Problem& P) {
   H64.alloc(Sp * 8);
   CGL_HIP(hipMemsetAsync(H64.ptr, 0, Sp * 8, s));
   CGL_HIP(hipMemsetAsync(U64.ptr, 0, Sn * 8, s));
+  // union of the certified iterates' supports: flags (zero between rounds), the list, its size
+  // and the iterates compacted to it
+  sflag.alloc((size_t)ldp);
+  CGL_HIP(hipMemsetAsync(sflag.ptr, 0, (size_t)ldp, s));
+  sidx.alloc((size_t)ldp * sizeof(int));
+  scount.alloc(sizeof(int));
+  Bu.alloc(Sp * 8);
   // split-K partials of the FP64 products (split x nodes <= 2 S)
   part64_cap = 2 * (size_t)S * (size_t)std::max<int64_t>(n_pad, ldp) * 8;
   part64.alloc(part64_cap);
@@ -143,6 +152,7 @@ void MixedWork::ensure(Problem& P) {
   }
   CGL_HIP(hipHostMalloc(&st_host, (size_t)S * sizeof(NodeDev), hipHostMallocDefault));
   CGL_HIP(hipHostMalloc(&beta_host, (size_t)S * P.p * sizeof(double), hipHostMallocDefault));
+  CGL_HIP(hipHostMalloc(&count_host, sizeof(int), hipHostMallocDefault));
   std::memset(st_host, 0, (size_t)S * sizeof(NodeDev));
   CGL_HIP(hipMemcpyAsync(st.ptr, st_host, (size_t)S * sizeof(NodeDev), hipMemcpyHostToDevice, s));
   cls_host.assign(Sp, CLS_PAD);
@@ -363,14 +373,23 @@ bool MixedWork::cert_round(Problem& P) {
   CGL_HIP(hipMemcpyAsync(list.ptr, want.data(), (size_t)nq * sizeof(int), hipMemcpyHostToDevice, s));
   hipEvent_t e0 = ctx->profiling ? ctx->event(100) : nullptr;
   hipEvent_t e1 = ctx->profiling ? ctx->event(101) : nullptr;
-  launch_cert_gather(md, list.as<int>(), nq, B64.as<double>(), s);
+  // X beta in FP64 over the union of the iterates' supports (the other coordinates contribute
+  // exact zeros), from the rows of the transposed design
+  launch_cert_gather(md, list.as<int>(), nq, B64.as<double>(), sflag.as<uint8_t>(), s);
+  launch_cert_support(sflag.as<uint8_t>(), P.p, sidx.as<int>(), scount.as<int>(), s);
+  CGL_HIP(hipMemcpyAsync(count_host, scount.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+  CGL_HIP(hipStreamSynchronize(s));
+  const int K = *count_host;
+  if (K < 0 || K > P.p) throw std::runtime_error("support union out of range");
+  support_sum += K;
+  const void* xt = P.xtype == XT_BF16 ? Xbt.ptr : Xt.ptr;
   if (e0) CGL_HIP(hipEventRecord(e0, s));
-  launch_gemm_f64(P.xtype, P.X.ptr, P.ldx, P.n, P.p, B64.as<double>(), ldp, nq, U64.as<double>(),
-                  n_pad, part64.as<double>(), part64_cap, s);
+  launch_cert_compact(B64.as<double>(), ldp, sidx.as<int>(), K, nq, Bu.as<double>(), s);
+  launch_gemm_f64_rows(P.xtype, xt, n_pad, sidx.as<int>(), P.n, K, Bu.as<double>(), ldp, nq,
+                       U64.as<double>(), n_pad, part64.as<double>(), part64_cap, s);
   if (e1) CGL_HIP(hipEventRecord(e1, s));
   launch_cert_resid(md, list.as<int>(), nq, U64.as<double>(), R64.as<double>(),
                     cpart.as<double>(), ncchunk, cchunk, s);
-  const void* xt = P.xtype == XT_BF16 ? Xbt.ptr : Xt.ptr;
   launch_gemm_f64(P.xtype, xt, n_pad, P.p, P.n, R64.as<double>(), n_pad, nq, H64.as<double>(), ldp,
                   part64.as<double>(), part64_cap, s);
   launch_cert_finish(md, list.as<int>(), nq, B64.as<double>(), H64.as<double>(),
@@ -391,7 +410,7 @@ size_t MixedWork::device_bytes() const {
   const DevBuf* bufs[] = {&Xb, &Xbt, &ypad, &st, &cls, &bring, &beta0, &H0, &base0, &base1,
                           &bres, &dop, &gop, &dU, &dUp, &dH, &lpart, &fpart, &cycle, &prevsel, &B64,
                           &U64, &R64, &H64, &cpart, &list, &H0_cold, &base0_cold, &base1_cold,
-                          &Xt, &part64};
+                          &Xt, &part64, &sflag, &sidx, &scount, &Bu};
   size_t b = 0;
   for (const DevBuf* d : bufs) b += d->bytes;
   return b;

@@ -34,10 +34,13 @@ struct MixedWork {
   int64_t rchunk = 0, cchunk = 0;
   double f_cold = 0.0;
   DevBuf Xb, Xbt, ypad, st, cls, bring, beta0, H0, base0, base1, bres, dop, gop, dU, dUp, dH, lpart,
-      fpart, cycle, prevsel, B64, U64, R64, H64, cpart, list, H0_cold, base0_cold, base1_cold, Xt, part64;
+      fpart, cycle, prevsel, B64, U64, R64, H64, cpart, list, H0_cold, base0_cold, base1_cold, Xt, part64,
+      sflag, sidx, scount, Bu;
   size_t part64_cap = 0;
   NodeDev* st_host = nullptr;
   double* beta_host = nullptr;  // pinned staging of retired iterates (S x p)
+  int* count_host = nullptr;    // pinned: size of the support union of a certification round
+  int64_t support_sum = 0;      // sum over certification rounds of the union size (statistics)
   std::vector<uint8_t> cls_host;
   std::vector<int> slot_owner;
   int64_t admitted_at[kSlots] = {0};

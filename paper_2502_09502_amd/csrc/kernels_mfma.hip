@@ -357,16 +357,58 @@ __global__ __launch_bounds__(256) void k_transpose(const XT* __restrict__ X, int
 // Certification / re-centring helpers
 // =====================================================================================
 
-// B64[q][j] = latest iterate of slot list[q] (ring slot cycle % 3).
+// B64[q][j] = latest iterate of slot list[q] (ring slot cycle % 3); flag[j] = 1 where some
+// gathered iterate is nonzero (every writer stores the same value; the flags start at zero).
 __global__ __launch_bounds__(256) void k_cert_gather(MixedDev md, const int* list, int nq,
-                                                     double* B64) {
+                                                     double* B64, uint8_t* flag) {
   const int q = blockIdx.y;
   if (q >= nq) return;
   const int slot = list[q];
   const int ring = md.st[slot].last_ring;
   const double* src = md.bring + (int64_t)ring * md.bring_stride + (int64_t)slot * md.ldp;
-  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < md.ldp; j += (int64_t)gridDim.x * 256)
-    B64[(int64_t)q * md.ldp + j] = src[j];
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < md.ldp; j += (int64_t)gridDim.x * 256) {
+    const double v = src[j];
+    B64[(int64_t)q * md.ldp + j] = v;
+    if (v != 0.0 && j < md.p) flag[j] = 1;
+  }
+}
+
+// The union of the gathered supports as a list: idx[0 .. K) = the flagged coordinates in
+// increasing order, idx[K .. K rounded up to 16) = 0, *count = K; the flags are cleared for the
+// next round. One workgroup.
+__global__ __launch_bounds__(1024) void k_cert_support(uint8_t* flag, int64_t p, int* idx,
+                                                       int* count) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (p + 1023) / 1024;
+  const int64_t j0 = min((int64_t)t * per, p), j1 = min(j0 + per, p);
+  int c = 0;
+  for (int64_t j = j0; j < j1; ++j) c += flag[j] != 0;
+  part[t] = c;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan
+    const int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int o = part[t] - c;
+  for (int64_t j = j0; j < j1; ++j) {
+    if (flag[j] != 0) idx[o++] = (int)j;
+    flag[j] = 0;
+  }
+  const int K = part[1023];
+  if (t < 16 && K + t < (K + 15) / 16 * 16) idx[K + t] = 0;
+  if (t == 0) *count = K;
+}
+
+// Bu[q][u] = B64[q][idx[u]] for u < K, 0 up to K rounded up to 16.
+__global__ __launch_bounds__(256) void k_cert_compact(const double* B64, int64_t ld, const int* idx,
+                                                      int K, int nq, double* Bu) {
+  const int q = blockIdx.y;
+  const int Kp = (K + 15) / 16 * 16;
+  for (int u = blockIdx.x * 256 + threadIdx.x; u < Kp; u += gridDim.x * 256)
+    Bu[(int64_t)q * ld + u] = u < K ? B64[(int64_t)q * ld + idx[u]] : 0.0;
 }
 
 // From U64 = X beta (FP64): the loss f, F*(-zeta) with zeta = -grad f(u) (partials per chunk),
@@ -692,39 +734,85 @@ void launch_transpose(int xtype, const void* X, int64_t ldx, int64_t n, int64_t 
     hipLaunchKernelGGL(k_transpose<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)X, ldx, n, p, n_pad, (uint16_t*)Xt);
 }
 
+// Launch shape of the FP64 products: node tile 32 when that pads Q no further than 16 would, else
+// 16; split K until there are about 4 workgroups per compute unit, each chunk >= 32 steps of 16
+// and the partials within part_cap bytes.
+struct F64Launch {
+  int nt;
+  int64_t mblocks, qblocks, ks, chunk;
+};
+static F64Launch f64_launch(int64_t M, int64_t K, int Q, size_t part_cap) {
+  F64Launch l;
+  l.nt = ((Q + 31) / 32 * 32 == (Q + 15) / 16 * 16) ? 2 : 1;
+  l.mblocks = (M + 64 * F64_RT - 1) / (64 * F64_RT);
+  l.qblocks = (Q + 16 * l.nt - 1) / (16 * l.nt);
+  const int64_t steps = std::max<int64_t>(1, (K + 15) / 16);
+  int64_t ks = (1024 + l.mblocks * l.qblocks - 1) / (l.mblocks * l.qblocks);
+  ks = std::min<int64_t>(ks, std::max<int64_t>(1, steps / 32));
+  ks = std::min<int64_t>(ks, (int64_t)(part_cap / ((size_t)Q * M * sizeof(double))));
+  ks = std::max<int64_t>(ks, 1);
+  l.chunk = (steps + ks - 1) / ks * 16;
+  l.ks = std::max<int64_t>(1, (K + l.chunk - 1) / l.chunk);
+  return l;
+}
+
+static void launch_f64_reduce(const double* part, int64_t ks, int Q, int64_t M, double* C,
+                              int64_t ldc, hipStream_t s) {
+  dim3 rg((unsigned)std::min<int64_t>((M + 255) / 256, 64), (unsigned)Q);
+  hipLaunchKernelGGL(k_gemm_f64_reduce, rg, dim3(256), 0, s, part, (int)ks, Q, M, C, ldc);
+}
+
 void launch_gemm_f64(int xtype, const void* A, int64_t lda, int64_t M, int64_t K,
                      const double* B, int64_t ldb, int Q, double* C, int64_t ldc, double* part,
                      size_t part_cap, hipStream_t s) {
   if (Q <= 0 || M <= 0) return;
-  // node tile: 32 when that pads Q no further than 16 would, else 16
-  const int nt = ((Q + 31) / 32 * 32 == (Q + 15) / 16 * 16) ? 2 : 1;
-  const int64_t mblocks = (M + 64 * F64_RT - 1) / (64 * F64_RT);
-  const int64_t qblocks = (Q + 16 * nt - 1) / (16 * nt);
-  const int64_t steps = std::max<int64_t>(1, (K + 15) / 16);
-  // split K until there are about 4 workgroups per compute unit, each chunk >= 32 steps
-  int64_t ks = (1024 + mblocks * qblocks - 1) / (mblocks * qblocks);
-  ks = std::min<int64_t>(ks, std::max<int64_t>(1, steps / 32));
-  ks = std::min<int64_t>(ks, (int64_t)(part_cap / ((size_t)Q * M * sizeof(double))));
-  ks = std::max<int64_t>(ks, 1);
-  const int64_t chunk = (steps + ks - 1) / ks * 16;
-  ks = std::max<int64_t>(1, (K + chunk - 1) / chunk);
-  F64GemmArgs g{A, lda, B, ldb, M, K, Q, chunk, ks > 1 ? part : C, ks > 1 ? M : ldc};
-  dim3 grid((unsigned)mblocks, (unsigned)qblocks, (unsigned)ks);
-#define CGL_F64_CALL(T)                                                            \
-  if (nt == 2) hipLaunchKernelGGL((k_gemm_f64<T, 2>), grid, dim3(256), 0, s, g); \
+  const F64Launch l = f64_launch(M, K, Q, part_cap);
+  F64GemmArgs g{A, lda, B, ldb, M, K, Q, l.chunk, l.ks > 1 ? part : C, l.ks > 1 ? M : ldc};
+  dim3 grid((unsigned)l.mblocks, (unsigned)l.qblocks, (unsigned)l.ks);
+#define CGL_F64_CALL(T)                                                              \
+  if (l.nt == 2) hipLaunchKernelGGL((k_gemm_f64<T, 2>), grid, dim3(256), 0, s, g); \
   else hipLaunchKernelGGL((k_gemm_f64<T, 1>), grid, dim3(256), 0, s, g);
   if (xtype == XT_F64) { CGL_F64_CALL(double) }
   else if (xtype == XT_F32) { CGL_F64_CALL(float) }
   else { CGL_F64_CALL(uint16_t) }
 #undef CGL_F64_CALL
-  if (ks > 1) {
-    dim3 rg((unsigned)std::min<int64_t>((M + 255) / 256, 64), (unsigned)Q);
-    hipLaunchKernelGGL(k_gemm_f64_reduce, rg, dim3(256), 0, s, part, (int)ks, Q, M, C, ldc);
-  }
+  if (l.ks > 1) launch_f64_reduce(part, l.ks, Q, M, C, ldc, s);
 }
 
-void launch_cert_gather(const MixedDev& md, const int* list, int nq, double* B64, hipStream_t s) {
-  hipLaunchKernelGGL(k_cert_gather, dim3(8, (unsigned)nq), dim3(256), 0, s, md, list, nq, B64);
+void launch_gemm_f64_rows(int xtype, const void* At, int64_t ldat, const int* idx, int64_t M,
+                          int64_t K, const double* B, int64_t ldb, int Q, double* C, int64_t ldc,
+                          double* part, size_t part_cap, hipStream_t s) {
+  if (Q <= 0 || M <= 0) return;
+  const F64Launch l = f64_launch(M, K, Q, part_cap);
+  F64RowsArgs g{At, ldat, idx, B, ldb, M, K, Q, l.chunk, l.ks > 1 ? part : C, l.ks > 1 ? M : ldc};
+  dim3 grid((unsigned)l.mblocks, (unsigned)l.qblocks, (unsigned)l.ks);
+#define CGL_F64_CALL(T)                                                                   \
+  if (l.nt == 2) hipLaunchKernelGGL((k_gemm_f64_rows<T, 2>), grid, dim3(256), 0, s, g); \
+  else hipLaunchKernelGGL((k_gemm_f64_rows<T, 1>), grid, dim3(256), 0, s, g);
+  if (xtype == XT_F64) { CGL_F64_CALL(double) }
+  else if (xtype == XT_F32) { CGL_F64_CALL(float) }
+  else { CGL_F64_CALL(uint16_t) }
+#undef CGL_F64_CALL
+  if (l.ks > 1) launch_f64_reduce(part, l.ks, Q, M, C, ldc, s);
+}
+
+void launch_cert_gather(const MixedDev& md, const int* list, int nq, double* B64, uint8_t* flag,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_cert_gather, dim3(8, (unsigned)nq), dim3(256), 0, s, md, list, nq, B64,
+                     flag);
+}
+
+void launch_cert_support(uint8_t* flag, int64_t p, int* idx, int* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_cert_support, dim3(1), dim3(1024), 0, s, flag, p, idx, count);
+}
+
+void launch_cert_compact(const double* B64, int64_t ld, const int* idx, int K, int nq, double* Bu,
+                         hipStream_t s) {
+  if (nq <= 0) return;
+  const int Kp = (K + 15) / 16 * 16;
+  const unsigned gx = (unsigned)std::max(1, std::min((Kp + 255) / 256, 16));
+  hipLaunchKernelGGL(k_cert_compact, dim3(gx, (unsigned)nq), dim3(256), 0, s, B64, ld, idx, K, nq,
+                     Bu);
 }
 
 void launch_cert_resid(const MixedDev& md, const int* list, int nq, const double* U64,

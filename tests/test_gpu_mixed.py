@@ -104,6 +104,38 @@ def test_mixed_edge_cases():
         assert r[q].status == "not_converged" and r[q].lower_bound <= root.primal
 
 
+def test_certification_round_with_empty_support():
+    """A certification round whose iterates are all zero: the FP64 product X beta runs over an
+    empty union of supports and must give u = 0 (P = f(0) = y'y for least squares)."""
+    d = synth.make_dataset(150, 40, 4, config_id=82)
+    prob = _problem(d)
+    f0 = float(d.y @ d.y)
+    r = prob.solve_batch([prob.node(Z0=np.arange(40), precision="mixed")])[0]
+    assert r.status == "converged" and rel(r.primal, f0) < 1e-12
+    assert np.all(r.beta == 0.0)
+    r = prob.solve_batch([prob.node(precision="mixed", max_iter=1)])[0]
+    root = oracle.solve_node(d.X, d.y, "ls", d.lam2, d.M, d.k, tol=1e-10)
+    assert r.status == "not_converged" and rel(r.primal, f0) < 1e-12
+    assert r.lower_bound <= root.primal
+
+
+def test_disjoint_supports_in_one_round():
+    """Nodes whose free sets do not overlap are certified in the same rounds: the union of their
+    supports covers coordinates that are zero for most of them, and each result still matches
+    the oracle."""
+    d = synth.make_dataset(400, 120, 5, config_id=84)
+    prob = _problem(d)
+    rng = np.random.default_rng(84)
+    perm = rng.permutation(d.p)
+    sets = [(np.sort(np.concatenate([perm[:40 * i], perm[40 * (i + 1):]])), np.array([], int))
+            for i in range(3)]
+    sets.append((np.array([], int), np.array([], int)))
+    res = prob.solve_batch(_specs(prob, sets))
+    for (z0, z1), r in zip(sets, res):
+        assert np.all(r.beta[z0] == 0.0)
+        _check(d, r, z0, z1)
+
+
 def test_config4_subset_full_size():
     """n = 20000, p = 10000, BF16 X: 16 nodes of the benchmark workload are certified to 1e-6;
     the oracle re-evaluates each returned beta to the reported objective and certifies it with

@@ -150,6 +150,31 @@ void MixedWork::ensure(Problem& P) {
       f0 += loss_at0(P.loss, yv[(size_t)i]);
     f_cold = f0;
   }
+  // Least squares with n >= p: G = X^T X in FP64 (2 n p^2 FLOP, once per engine), so that a
+  // certification round gets X^T grad f(X beta) = 2 G beta - 2 X^T y from the rows of G on the
+  // union of the iterates' supports instead of a product with all of X. CGL_NO_GRAM=1 turns it
+  // off.
+  {
+    const char* ng = std::getenv("CGL_NO_GRAM");
+    if (P.loss == LOSS_LS && P.n >= P.p && P.p <= kGramMaxP && !(ng && std::atoi(ng) > 0)) {
+      ldg = round_up(P.p, 256);
+      G.alloc((size_t)P.p * ldg * 8);
+      CGL_HIP(hipMemsetAsync(G.ptr, 0, G.bytes, s));
+      const char* xt = (const char*)(P.xtype == XT_BF16 ? Xbt.ptr : Xt.ptr);
+      const size_t esz = P.xtype == XT_F64 ? 8 : (P.xtype == XT_F32 ? 4 : 2);
+      const int64_t rows = 256;
+      DevBuf wide;
+      wide.alloc((size_t)rows * n_pad * 8);
+      for (int64_t j0 = 0; j0 < P.p; j0 += rows) {  // G rows j0 .. j0 + r
+        const int64_t r = std::min(rows, P.p - j0);
+        launch_widen(P.xtype, xt + (size_t)j0 * n_pad * esz, n_pad, r, n_pad, wide.as<double>(),
+                     n_pad, s);
+        launch_gemm_f64(P.xtype, xt, n_pad, P.p, P.n, wide.as<double>(), n_pad, (int)r,
+                        G.as<double>() + j0 * ldg, ldg, part64.as<double>(), part64_cap, s);
+      }
+      CGL_HIP(hipStreamSynchronize(s));  // the staging rows are released here
+    }
+  }
   CGL_HIP(hipHostMalloc(&st_host, (size_t)S * sizeof(NodeDev), hipHostMallocDefault));
   CGL_HIP(hipHostMalloc(&beta_host, (size_t)S * P.p * sizeof(double), hipHostMallocDefault));
   CGL_HIP(hipHostMalloc(&count_host, sizeof(int), hipHostMallocDefault));
@@ -388,10 +413,19 @@ bool MixedWork::cert_round(Problem& P) {
   launch_gemm_f64_rows(P.xtype, xt, n_pad, sidx.as<int>(), P.n, K, Bu.as<double>(), ldp, nq,
                        U64.as<double>(), n_pad, part64.as<double>(), part64_cap, s);
   if (e1) CGL_HIP(hipEventRecord(e1, s));
+  // X^T grad f(X beta): least squares from the Gram rows on the same support (p K against n p
+  // products), else the FP64 product with all of X^T
+  const bool gram = G.ptr != nullptr && K < P.n;
+  if (gram) {
+    launch_gemm_f64_rows(XT_F64, G.ptr, ldg, sidx.as<int>(), P.p, K, Bu.as<double>(), ldp, nq,
+                         H64.as<double>(), ldp, part64.as<double>(), part64_cap, s);
+    launch_gram_finish(H64.as<double>(), ldp, P.p, nq, H0_cold.as<double>(), s);
+  }
   launch_cert_resid(md, list.as<int>(), nq, U64.as<double>(), R64.as<double>(),
                     cpart.as<double>(), ncchunk, cchunk, s);
-  launch_gemm_f64(P.xtype, xt, n_pad, P.p, P.n, R64.as<double>(), n_pad, nq, H64.as<double>(), ldp,
-                  part64.as<double>(), part64_cap, s);
+  if (!gram)
+    launch_gemm_f64(P.xtype, xt, n_pad, P.p, P.n, R64.as<double>(), n_pad, nq, H64.as<double>(),
+                    ldp, part64.as<double>(), part64_cap, s);
   launch_cert_finish(md, list.as<int>(), nq, B64.as<double>(), H64.as<double>(),
                      cpart.as<double>(), ncchunk, s);
   CGL_HIP(hipMemcpyAsync(st_host, st.ptr, (size_t)S * sizeof(NodeDev), hipMemcpyDeviceToHost, s));
@@ -410,7 +444,7 @@ size_t MixedWork::device_bytes() const {
   const DevBuf* bufs[] = {&Xb, &Xbt, &ypad, &st, &cls, &bring, &beta0, &H0, &base0, &base1,
                           &bres, &dop, &gop, &dU, &dUp, &dH, &lpart, &fpart, &cycle, &prevsel, &B64,
                           &U64, &R64, &H64, &cpart, &list, &H0_cold, &base0_cold, &base1_cold,
-                          &Xt, &part64, &sflag, &sidx, &scount, &Bu};
+                          &Xt, &part64, &sflag, &sidx, &scount, &Bu, &G};
   size_t b = 0;
   for (const DevBuf* d : bufs) b += d->bytes;
   return b;

@@ -15,6 +15,7 @@ constexpr int kSlots = 256;  // node slots per problem
 constexpr int kChunk = 4;    // iterations per graph launch between host checks
 constexpr int kCertBatch = 32;  // certification requests that trigger a round at once
 constexpr int kCertWait = 1;    // chunks the oldest request may wait for others
+constexpr int64_t kGramMaxP = 16384;  // least squares: largest p with an FP64 Gram matrix (2.1 GB)
 
 struct Admission {
   int slot;
@@ -35,7 +36,8 @@ struct MixedWork {
   double f_cold = 0.0;
   DevBuf Xb, Xbt, ypad, st, cls, bring, beta0, H0, base0, base1, bres, dop, gop, dU, dUp, dH, lpart,
       fpart, cycle, prevsel, B64, U64, R64, H64, cpart, list, H0_cold, base0_cold, base1_cold, Xt, part64,
-      sflag, sidx, scount, Bu;
+      sflag, sidx, scount, Bu, G;
+  int64_t ldg = 0;  // least squares: G = X^T X in FP64 (p x ldg), when built
   size_t part64_cap = 0;
   NodeDev* st_host = nullptr;
   double* beta_host = nullptr;  // pinned staging of retired iterates (S x p)

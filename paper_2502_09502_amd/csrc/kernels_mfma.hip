@@ -615,6 +615,43 @@ void launch_gather_rows(const double* src, int64_t ld, const int* list, int nq, 
                      dst);
 }
 
+// dst[r][c] = src[r][c] widened to FP64, r < rows, c < cols (leading dimensions ld, ldd).
+template <typename XT>
+__global__ __launch_bounds__(256) void k_widen(const XT* __restrict__ src, int64_t ld, int64_t rows,
+                                               int64_t cols, double* __restrict__ dst, int64_t ldd) {
+  const int64_t r = blockIdx.y;
+  if (r >= rows) return;
+  const XT* a = src + r * ld;
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < cols; c += (int64_t)gridDim.x * 256)
+    dst[r * ldd + c] = XLoad<XT>::get(a, (size_t)c);
+}
+
+void launch_widen(int xtype, const void* src, int64_t ld, int64_t rows, int64_t cols, double* dst,
+                  int64_t ldd, hipStream_t s) {
+  if (rows <= 0) return;
+  const dim3 grid((unsigned)std::min<int64_t>((cols + 255) / 256, 32), (unsigned)rows);
+  if (xtype == XT_F64)
+    hipLaunchKernelGGL(k_widen<double>, grid, dim3(256), 0, s, (const double*)src, ld, rows, cols, dst, ldd);
+  else if (xtype == XT_F32)
+    hipLaunchKernelGGL(k_widen<float>, grid, dim3(256), 0, s, (const float*)src, ld, rows, cols, dst, ldd);
+  else
+    hipLaunchKernelGGL(k_widen<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)src, ld, rows, cols, dst, ldd);
+}
+
+// Least squares: X^T grad f(X beta) = 2 X^T X beta - 2 X^T y. H[q][j] holds (X^T X beta_q)_j on
+// entry and the gradient on exit; h0 = X^T grad f(0) = -2 X^T y.
+__global__ __launch_bounds__(256) void k_gram_finish(double* H, int64_t ld, int64_t p,
+                                                     const double* h0) {
+  const int q = blockIdx.y;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < p; j += (int64_t)gridDim.x * 256)
+    H[(int64_t)q * ld + j] = 2.0 * H[(int64_t)q * ld + j] + h0[j];
+}
+
+void launch_gram_finish(double* H, int64_t ld, int64_t p, int nq, const double* h0, hipStream_t s) {
+  if (nq <= 0) return;
+  hipLaunchKernelGGL(k_gram_finish, dim3(8, (unsigned)nq), dim3(256), 0, s, H, ld, p, h0);
+}
+
 // Zero a slot's operand rows (retired or empty slots must not contribute to the products).
 __global__ __launch_bounds__(256) void k_slot_clear(MixedDev md, int slot) {
   for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < md.ldp; j += (int64_t)gridDim.x * 256)

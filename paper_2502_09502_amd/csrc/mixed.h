@@ -70,6 +70,11 @@ void launch_gemm_f64(int xtype, const void* A, int64_t lda, int64_t M, int64_t K
 void launch_gemm_f64_rows(int xtype, const void* At, int64_t ldat, const int* idx, int64_t M,
                           int64_t K, const double* B, int64_t ldb, int Q, double* C, int64_t ldc,
                           double* part, size_t part_cap, hipStream_t s);
+// dst[r][c] = src[r][c] (the design's stored precision) widened to FP64, r < rows, c < cols.
+void launch_widen(int xtype, const void* src, int64_t ld, int64_t rows, int64_t cols, double* dst,
+                  int64_t ldd, hipStream_t s);
+// Least squares: H[q][j] = 2 H[q][j] + h0[j] for j < p (H = X^T X beta on entry, h0 = -2 X^T y).
+void launch_gram_finish(double* H, int64_t ld, int64_t p, int nq, const double* h0, hipStream_t s);
 // Xt (p x n_pad) = X^T in the stored precision, zero in columns n .. n_pad.
 void launch_transpose(int xtype, const void* X, int64_t ldx, int64_t n, int64_t p, int64_t n_pad,
                       void* Xt, hipStream_t s);

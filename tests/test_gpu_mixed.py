@@ -136,6 +136,35 @@ def test_disjoint_supports_in_one_round():
         _check(d, r, z0, z1)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "bf16"])
+def test_gram_certificate_matches_direct_product(dtype, monkeypatch):
+    """Least squares with n >= p certifies with X^T grad f(X beta) = 2 G beta - 2 X^T y from an
+    FP64 Gram matrix; with the Gram matrix turned off the same nodes are certified by the FP64
+    product with X^T. Both match the oracle and each bound is below the other's primal value."""
+    d = synth.make_dataset(600, 150, 6, dtype=dtype, config_id=85)
+    sets = synth.node_sets(d.p, d.k, 8, 12, config_id=85)
+    with_gram = _problem(d)
+    a = with_gram.solve_batch(_specs(with_gram, sets))
+    monkeypatch.setenv("CGL_NO_GRAM", "1")
+    direct = _problem(d)
+    b = direct.solve_batch(_specs(direct, sets))
+    for (z0, z1), ra, rb in zip(sets, a, b):
+        _check(d, ra, z0, z1)
+        _check(d, rb, z0, z1)
+        assert rel(ra.primal, rb.primal) <= 2e-6
+        assert ra.lower_bound <= rb.primal and rb.lower_bound <= ra.primal
+
+
+def test_wide_least_squares_mixed():
+    """p > n: no Gram matrix; the certificate comes from the FP64 product with X^T."""
+    d = synth.make_dataset(120, 300, 5, config_id=86)
+    prob = _problem(d)
+    sets = synth.node_sets(d.p, d.k, 4, 10, config_id=86)
+    res = prob.solve_batch(_specs(prob, sets))
+    for (z0, z1), r in zip(sets, res):
+        _check(d, r, z0, z1)
+
+
 def test_config4_subset_full_size():
     """n = 20000, p = 10000, BF16 X: 16 nodes of the benchmark workload are certified to 1e-6;
     the oracle re-evaluates each returned beta to the reported objective and certifies it with

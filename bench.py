@@ -344,11 +344,18 @@ def main():
         return [prob.node(Z0=z0, Z1=z1, tol=1e-6, precision=prec) for z0, z1 in sets]
 
     mode = args.mode
-    if mode == "auto":
-        mode = "batched"
+    engine_setup_ms = None
+    if mode in ("auto", "batched"):
+        # the first batched solve builds the engine (BF16 copies, split-K tuning, graphs and, for
+        # least squares, the FP64 Gram matrix); its time is reported, not part of a step
+        t_eng = time.perf_counter()
         try:
             prob.solve_batch(specs("mixed")[:1])
+            engine_setup_ms = (time.perf_counter() - t_eng) * 1e3
+            mode = "batched"
         except _lib.CglError:
+            if mode == "batched":
+                raise
             mode = "plain"
     step_specs = specs("mixed" if mode == "batched" else "f64")
 
@@ -416,6 +423,8 @@ def main():
     }
     if phases is not None:
         out["phases"] = phases
+    if engine_setup_ms is not None:
+        out["engine_setup_ms"] = round(engine_setup_ms, 1)
     if mode == "plain":
         out["latency_ms"] = {"note": "per-node solve time on the plain path, sequential",
                              "p50": round(1e3 * elapsed / args.steps / len(step_specs), 3)}

@@ -31,6 +31,7 @@ MixedWork::~MixedWork() {
   if (st_host) (void)hipHostFree(st_host);
   if (beta_host) (void)hipHostFree(beta_host);
   if (count_host) (void)hipHostFree(count_host);
+  if (order_host) (void)hipHostFree(order_host);
 }
 
 static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -225,6 +226,44 @@ void MixedWork::ensure(Problem& P) {
   md.cycle = cycle.as<int>();
   md.prevhead = prevsel.as<int>();
   md.prevtop = prevsel.as<int>() + (size_t)S * 65;
+  // X-pass operand order: identity until the first reorder; full extent until the node kernels
+  // have measured it
+  {
+    std::vector<int> id((size_t)ldp);
+    for (int64_t j = 0; j < ldp; ++j) id[(size_t)j] = (int)j;
+    pinv.alloc((size_t)ldp * sizeof(int));
+    pinv_new.alloc((size_t)ldp * sizeof(int));
+    perm.alloc((size_t)ldp * sizeof(int));
+    perm_new.alloc((size_t)ldp * sizeof(int));
+    CGL_HIP(hipMemcpy(pinv.ptr, id.data(), (size_t)ldp * sizeof(int), hipMemcpyHostToDevice));
+    CGL_HIP(hipMemcpy(perm.ptr, id.data(), (size_t)ldp * sizeof(int), hipMemcpyHostToDevice));
+    const int full[2] = {(int)ldp, (int)ldp};
+    keff.alloc(2 * sizeof(int));
+    CGL_HIP(hipMemcpy(keff.ptr, full, sizeof(full), hipMemcpyHostToDevice));
+    dop_tmp.alloc(dop.bytes);
+    CGL_HIP(hipHostMalloc(&order_host, (size_t)(4 + S) * sizeof(int), hipHostMallocDefault));
+    // no support prefix (and so no strays) until the first reorder
+    pfx.alloc(sizeof(int));
+    const int nopfx = (int)ldp;
+    CGL_HIP(hipMemcpy(pfx.ptr, &nopfx, sizeof(int), hipMemcpyHostToDevice));
+    sn.alloc((size_t)S * sizeof(int));
+    CGL_HIP(hipMemset(sn.ptr, 0, (size_t)S * sizeof(int)));
+    sj.alloc((size_t)S * kStrayCap * sizeof(int));
+    sv.alloc((size_t)S * kStrayCap * sizeof(float));
+    md.pfx = pfx.as<int>();
+    md.sn = sn.as<int>();
+    md.sj = sj.as<int>();
+    md.sv = sv.as<float>();
+    const char* e = std::getenv("CGL_NO_REORDER");
+    reorder = !(e && std::atoi(e) > 0);
+    // test hook: a support prefix shorter than the union (multiple of 128) forces strays and
+    // operand entries past the prefix
+    const char* c = std::getenv("CGL_PREFIX_CAP");
+    if (c && std::atoi(c) > 0) prefix_cap = round_up(std::atoi(c), 2 * GT_K);
+    md.pinv = pinv.as<int>();
+    md.perm = perm.as<int>();
+    md.keff = keff.as<int>();
+  }
   CGL_HIP(hipStreamSynchronize(s));
   tune_splits(P);
   ready = true;
@@ -326,9 +365,47 @@ static bool mixed_graphs() {
   return !(e && e[0] == '1');
 }
 
+void MixedWork::reorder_operand(Problem& P) {
+  hipStream_t s = P.ctx->stream;
+  int* h = order_host;  // [0, 2): extent counters, [2]: union size, [4, 4 + S): strays per slot
+  launch_perm_flags(md, sflag.as<uint8_t>(), s);
+  launch_perm_build(sflag.as<uint8_t>(), P.p, ldp, perm_new.as<int>(), pinv_new.as<int>(),
+                    scount.as<int>(), s);
+  CGL_HIP(hipMemcpyAsync(h, keff.ptr, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  CGL_HIP(hipMemcpyAsync(h + 2, scount.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+  CGL_HIP(hipMemcpyAsync(h + 4, sn.ptr, (size_t)S * sizeof(int), hipMemcpyDeviceToHost, s));
+  CGL_HIP(hipStreamSynchronize(s));
+  const int64_t grain = 2 * GT_K;
+  const int64_t now = round_up(std::max(h[0], h[1]), grain);
+  int64_t after = std::min(round_up(h[2], grain), ldp);
+  if (prefix_cap > 0) after = std::min(after, prefix_cap);
+  int64_t strays = 0;
+  for (int i = 0; i < S; ++i) strays += h[4 + i];
+  const bool shorter = after <= now - std::max<int64_t>(2 * grain, now / 8);
+  // a stray costs its slot one column of X~ per cycle; a reorder costs about 0.3 ms
+  if (!shorter && strays <= 2 * S) return;  // the current order still serves
+  CGL_HIP(hipMemcpyAsync(dop_tmp.ptr, dop.ptr, dop.bytes, hipMemcpyDeviceToDevice, s));
+  CGL_HIP(hipMemsetAsync(keff.ptr, 0, 2 * sizeof(int), s));
+  launch_perm_operand(md, dop_tmp.as<uint16_t>(), pinv.as<int>(), pinv_new.as<int>(), s);
+  launch_perm_design(Xbt.as<uint16_t>(), n_pad, perm_new.as<int>(), P.p, Xb.as<uint16_t>(), ldp,
+                     s);
+  CGL_HIP(hipMemcpyAsync(pinv.ptr, pinv_new.ptr, (size_t)ldp * sizeof(int),
+                         hipMemcpyDeviceToDevice, s));
+  CGL_HIP(hipMemcpyAsync(perm.ptr, perm_new.ptr, (size_t)ldp * sizeof(int),
+                         hipMemcpyDeviceToDevice, s));
+  h[3] = (int)after;  // the union fills the prefix; later entrants behind it become strays
+  CGL_HIP(hipMemcpyAsync(pfx.ptr, h + 3, sizeof(int), hipMemcpyHostToDevice, s));
+  CGL_HIP(hipStreamSynchronize(s));  // h is reused by the next check
+  reorders += 1;
+}
+
 void MixedWork::run_chunk(Problem& P) {
   hipStream_t s = P.ctx->stream;
   cgl_ctx* ctx = P.ctx;
+  if (reorder && cycles - reorder_checked >= kReorderEvery) {
+    reorder_checked = cycles;
+    reorder_operand(P);
+  }
   // with profiling on, each cycle's two products are bracketed by HIP events on the stream (HIP
   // cannot time events recorded inside a graph, so the cycles are then launched one by one)
   if (ctx->profiling || !mixed_graphs()) {
@@ -444,7 +521,8 @@ size_t MixedWork::device_bytes() const {
   const DevBuf* bufs[] = {&Xb, &Xbt, &ypad, &st, &cls, &bring, &beta0, &H0, &base0, &base1,
                           &bres, &dop, &gop, &dU, &dUp, &dH, &lpart, &fpart, &cycle, &prevsel, &B64,
                           &U64, &R64, &H64, &cpart, &list, &H0_cold, &base0_cold, &base1_cold,
-                          &Xt, &part64, &sflag, &sidx, &scount, &Bu, &G};
+                          &Xt, &part64, &sflag, &sidx, &scount, &Bu, &G, &pinv, &pinv_new,
+                          &perm, &perm_new, &keff, &dop_tmp, &pfx, &sn, &sj, &sv};
   size_t b = 0;
   for (const DevBuf* d : bufs) b += d->bytes;
   return b;

@@ -15,6 +15,7 @@ constexpr int kSlots = 256;  // node slots per problem
 constexpr int kChunk = 4;    // iterations per graph launch between host checks
 constexpr int kCertBatch = 32;  // certification requests that trigger a round at once
 constexpr int kCertWait = 1;    // chunks the oldest request may wait for others
+constexpr int kReorderEvery = 8;  // cycles between checks of the X-pass operand order
 constexpr int64_t kGramMaxP = 16384;  // least squares: largest p with an FP64 Gram matrix (2.1 GB)
 
 struct Admission {
@@ -36,13 +37,18 @@ struct MixedWork {
   double f_cold = 0.0;
   DevBuf Xb, Xbt, ypad, st, cls, bring, beta0, H0, base0, base1, bres, dop, gop, dU, dUp, dH, lpart,
       fpart, cycle, prevsel, B64, U64, R64, H64, cpart, list, H0_cold, base0_cold, base1_cold, Xt, part64,
-      sflag, sidx, scount, Bu, G;
+      sflag, sidx, scount, Bu, G, pinv, pinv_new, perm, perm_new, keff, dop_tmp, pfx, sn, sj, sv;
   int64_t ldg = 0;  // least squares: G = X^T X in FP64 (p x ldg), when built
   size_t part64_cap = 0;
   NodeDev* st_host = nullptr;
   double* beta_host = nullptr;  // pinned staging of retired iterates (S x p)
   int* count_host = nullptr;    // pinned: size of the support union of a certification round
   int64_t support_sum = 0;      // sum over certification rounds of the union size (statistics)
+  int* order_host = nullptr;    // pinned: extent counters, support prefix, strays per slot
+  bool reorder = true;          // CGL_NO_REORDER=1 keeps the natural coordinate order
+  int64_t reorder_checked = 0;  // cycle of the last reorder check
+  int64_t reorders = 0;
+  int64_t prefix_cap = 0;       // CGL_PREFIX_CAP (tests): upper bound of the support prefix
   std::vector<uint8_t> cls_host;
   std::vector<int> slot_owner;
   int64_t admitted_at[kSlots] = {0};
@@ -62,6 +68,10 @@ struct MixedWork {
   void ensure(Problem& P);
   void run_chunk(Problem& P);
   bool cert_round(Problem& P);
+  // Puts the coordinates where a running slot's recent iterates or base point are nonzero first
+  // in the X-pass operand order (and the columns of Xb alike), with the support prefix at their
+  // count, when that shortens the operand's extent by an eighth or the strays have piled up.
+  void reorder_operand(Problem& P);
   void admit(Problem& P, const std::vector<Admission>& adm);
   // Results of finished slots and their best certified iterates (beta_out[i] may be null): one
   // gather of the iterates on the device, one copy to pinned host memory, then into the

@@ -1,6 +1,8 @@
 // Shared device/host helpers for the certglm HIP library (gfx950, wave64).
 #pragma once
 
+#include <climits>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -96,6 +98,7 @@ struct OpAnd {
 __device__ __forceinline__ double wave_sum(double v) { return wave_reduce(v, 0.0, OpAdd()); }
 __device__ __forceinline__ float wave_sum(float v) { return wave_reduce(v, 0.0f, OpAdd()); }
 __device__ __forceinline__ int wave_sum(int v) { return wave_reduce(v, 0, OpAdd()); }
+__device__ __forceinline__ int wave_max(int v) { return wave_reduce(v, INT_MIN, OpMax()); }
 __device__ __forceinline__ double wave_max(double v) {
   return wave_reduce(v, -HUGE_VAL, OpMax());
 }

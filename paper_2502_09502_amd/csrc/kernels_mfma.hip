@@ -57,7 +57,7 @@ __device__ __forceinline__ bool slot_running(const NodeDev* st) {
 // launch reads it and the kernels after it see the new value.
 template <int PASS>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int mtiles, int ks, int per_xcd,
-                                                   int* bump) {
+                                                   int* bump, const int* extent) {
   __shared__ __attribute__((aligned(16))) uint16_t As[2 * GT_M * GT_LD];
   if (bump != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *bump += 1;
   const int lane = threadIdx.x & 63;
@@ -67,8 +67,16 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int mtiles, int k
   const int z = pair / mtiles;
   const int64_t m0 = (int64_t)(pair % mtiles) * GT_M;
   const int64_t n0 = (int64_t)blockIdx.y * GT_N;
-  const int64_t k0 = (int64_t)z * g.kchunk;
-  const int64_t k1 = min(g.K, k0 + g.kchunk);
+  int64_t K = g.K, kc = g.kchunk;
+  if (extent != nullptr) {
+    // X pass: the operand is zero at positions >= max(extent[0], extent[1]); the ks chunks
+    // split that prefix (multiples of 2 GT_K; chunks past it are empty and store zeros)
+    const int64_t e = max(extent[0], extent[1]);
+    K = min(K, (e + 2 * GT_K - 1) / (2 * GT_K) * (2 * GT_K));
+    kc = ((K + ks - 1) / ks + 2 * GT_K - 1) / (2 * GT_K) * (2 * GT_K);
+  }
+  const int64_t k0 = (int64_t)z * kc;
+  const int64_t k1 = min(K, k0 + kc);
   floatx16 acc[GT_RT][2];
   gemm_bf16_mainloop(g, m0, n0, k0, k1, As, acc);
   float* C = g.C + (int64_t)z * g.c_split_stride;
@@ -102,6 +110,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int mtiles, int k
 // =====================================================================================
 __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
   __shared__ double red[4];
+  // the X pass of this cycle has read the operand extent: its counter restarts for cycle + 2
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) md.keff[*md.cycle & 1] = 0;
   const int slot = blockIdx.y;
   const NodeDev* st = md.st + slot;
   if (!slot_running(st)) return;
@@ -111,10 +121,20 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
   float* duo = md.dU + (int64_t)((cyc + 1) & 1) * md.dU_ring + (int64_t)slot * md.n_pad;
   const int64_t i0 = (int64_t)blockIdx.x * md.rchunk;
   const int64_t i1 = min(md.n_pad, i0 + md.rchunk);
+  // strays of the operand: X~ column j is row j of X~^T
+  __shared__ const uint16_t* scol[kStrayCap];
+  __shared__ float sval[kStrayCap];
+  const int ns = md.sn[slot];
+  for (int e = threadIdx.x; e < ns; e += 256) {
+    scol[e] = md.Xbt + (int64_t)md.sj[(int64_t)slot * kStrayCap + e] * md.n_pad;
+    sval[e] = md.sv[(int64_t)slot * kStrayCap + e];
+  }
+  __syncthreads();
   double ls = 0.0;
   for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
     float du = 0.f;
     for (int q = 0; q < md.ksx; ++q) du += md.dUp[(int64_t)q * md.dUp_split + (int64_t)slot * md.n_pad + i];
+    for (int e = 0; e < ns; ++e) du += bf16_to_float(scol[e][i]) * sval[e];
     if (rebase) {
       duo[i] -= du;
       du = 0.f;
@@ -285,16 +305,86 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
     pv.set(s, md.rho * fabs(w));
   }
   const int64_t nbk = md.S_pad >> 5;
+  // operand extent (LDS: nothing extra stays live through the prox)
+  __shared__ int ext_s, ext_over;
+  if (threadIdx.x == 0) {
+    ext_s = 0;
+    ext_over = 0;
+  }
+  __syncthreads();
   const ProxOut po = node_prox<E>(
       [&](int s) { return pv.get(s); }, neg, cb, st->kp, st->nfree, md.rho, md.M, st->vstar,
       [&](int s, double b) {
         const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
         if (j < p) {
           bout[j] = b;
-          md.dop[frag_index(slot, j, nbk)] = float_to_bf16((float)(b - b0[j]));
+          const int pos = md.pinv[j];
+          const uint16_t d = float_to_bf16((float)(b - b0[j]));
+          md.dop[frag_index(slot, pos, nbk)] = d;
+          if ((d & 0x7fffu) != 0) atomicMax(&ext_s, pos + 1);
         }
       },
       sm, slice, md.prevhead + (int64_t)slot * 65);
+  __syncthreads();
+  // Entries past the support prefix leave the operand as strays, the first kStrayCap of them in
+  // position order (the rest stay and the extent covers them). Two passes over the operand stores
+  // of the whole block (ordered by the barrier above): count per thread, exclusive scan, assign.
+  const int pfx = *md.pfx;
+  const int ext_all = ext_s;
+  int ext = min(ext_all, pfx);
+  int ns = 0;
+  if (ext_all > pfx) {  // uniform over the block
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const int ubeg = (pfx & ~7) + 8 * (int)threadIdx.x;
+    auto late = [&](int u8, const u32x4& v, int e) {
+      const int u = u8 + e;
+      const uint16_t d = (uint16_t)((v[e >> 1] >> (16 * (e & 1))) & 0xffffu);
+      return u >= pfx && u < ext_all && (d & 0x7fffu) != 0;
+    };
+    int cnt = 0;
+    for (int u8 = ubeg; u8 < ext_all; u8 += 8 * kProxThreads) {
+      const u32x4 v = *reinterpret_cast<const u32x4*>(md.dop + frag_index(slot, u8, nbk));
+      for (int e = 0; e < 8; ++e) cnt += late(u8, v, e) ? 1 : 0;
+    }
+    // exclusive scan of cnt in thread order (groups of one stride round are in position order
+    // across threads, and the rounds are in order)
+    __shared__ int wsum[kProxThreads / 64];
+    int incl = cnt;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int o = __shfl_up(incl, off, 64);
+      if ((threadIdx.x & 63) >= off) incl += o;
+    }
+    if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    int base = 0, total = 0;
+    for (int w = 0; w < kProxThreads / 64; ++w) {
+      if (w < (int)(threadIdx.x >> 6)) base += wsum[w];
+      total += wsum[w];
+    }
+    int idx = base + incl - cnt;
+    ns = min(total, kStrayCap);
+    for (int u8 = ubeg; u8 < ext_all && cnt > 0; u8 += 8 * kProxThreads) {
+      uint16_t* g8 = md.dop + frag_index(slot, u8, nbk);
+      const u32x4 v = *reinterpret_cast<const u32x4*>(g8);
+      for (int e = 0; e < 8; ++e) {
+        if (!late(u8, v, e)) continue;
+        const int u = u8 + e;
+        if (idx < kStrayCap) {
+          md.sj[(int64_t)slot * kStrayCap + idx] = md.perm[u];
+          md.sv[(int64_t)slot * kStrayCap + idx] =
+              bf16_to_float((uint16_t)((v[e >> 1] >> (16 * (e & 1))) & 0xffffu));
+          g8[e] = 0;
+        } else {
+          atomicMax(&ext_over, u + 1);
+        }
+        ++idx;
+      }
+    }
+    __syncthreads();
+    ext = max(ext, ext_over);
+  }
+  if (threadIdx.x == 0 && ext > 0) atomicMax(md.keff + ((cyc + 1) & 1), ext);
+  if (threadIdx.x == 0) md.sn[slot] = ns;
   double fs = 0.0;
   if (check) {
     for (int i = threadIdx.x; i < md.nrt; i += blockDim.x)
@@ -553,6 +643,7 @@ __global__ __launch_bounds__(1024) void k_cert_finish(MixedDev md, const int* li
       for (int r = 0; r < 3; ++r) md.bring[(int64_t)r * md.bring_stride + (int64_t)slot * md.ldp + j] = bj;
     if (!keep || done) md.dop[frag_index(slot, j, md.S_pad >> 5)] = 0;
   }
+  if ((!keep || done) && threadIdx.x == 0) md.sn[slot] = 0;
   if (fresh) {
     for (int64_t i = threadIdx.x; i < md.n_pad; i += blockDim.x) {
       md.dU[(int64_t)slot * md.n_pad + i] = 0.f;
@@ -573,6 +664,7 @@ __global__ __launch_bounds__(256) void k_admit(MixedDev md, const int* list, int
   if (blockIdx.x == 0 && threadIdx.x == 0) {  // no selection history for a new node
     md.prevhead[(int64_t)slot * 65] = 0;
     md.prevtop[(int64_t)slot * 65] = 0;
+    md.sn[slot] = 0;
   }
   for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < md.ldp; j += stride) {
     const int64_t o = (int64_t)slot * md.ldp + j;
@@ -615,6 +707,133 @@ void launch_gather_rows(const double* src, int64_t ld, const int* list, int nq, 
                      dst);
 }
 
+// =====================================================================================
+// Operand order by support (the X pass reads only the prefix of X~'s permuted columns where some
+// slot's operand is nonzero)
+// =====================================================================================
+
+__global__ __launch_bounds__(256) void k_perm_flags(MixedDev md, uint8_t* flag) {
+  const int slot = blockIdx.y;
+  const NodeDev* st = md.st + slot;
+  if (!slot_running(st)) return;
+  // the three iterates of the ring (the latest and the two before it) and the base point
+  const double* b = md.bring + (int64_t)slot * md.ldp;
+  const double* b0 = md.beta0 + (int64_t)slot * md.ldp;
+  const int64_t rs = md.bring_stride;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < md.p; j += (int64_t)gridDim.x * 256)
+    if (b[j] != 0.0 || b[rs + j] != 0.0 || b[2 * rs + j] != 0.0 || b0[j] != 0.0) flag[j] = 1;
+}
+
+void launch_perm_flags(const MixedDev& md, uint8_t* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_perm_flags, dim3(4, (unsigned)md.slots), dim3(256), 0, s, md, flag);
+}
+
+__global__ __launch_bounds__(1024) void k_perm_build(uint8_t* flag, int64_t p, int64_t ldp,
+                                                     int* perm, int* pinv, int* count) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (p + 1023) / 1024;
+  const int64_t j0 = min((int64_t)t * per, p), j1 = min(j0 + per, p);
+  int c = 0;
+  for (int64_t j = j0; j < j1; ++j) c += flag[j] != 0;
+  part[t] = c;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan of the flagged counts
+    const int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  const int U = part[1023];
+  int f = part[t] - c;                    // flagged coordinates before j0
+  int u = U + (int)(j0 - f);              // unflagged coordinates go after all flagged ones
+  for (int64_t j = j0; j < j1; ++j) {
+    const int pos = flag[j] != 0 ? f++ : u++;
+    pinv[j] = pos;
+    perm[pos] = (int)j;
+    flag[j] = 0;
+  }
+  for (int64_t j = p + t; j < ldp; j += 1024) {
+    pinv[j] = (int)j;
+    perm[j] = (int)j;
+  }
+  if (t == 0) *count = U;
+}
+
+void launch_perm_build(uint8_t* flag, int64_t p, int64_t ldp, int* perm, int* pinv, int* count,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_perm_build, dim3(1), dim3(1024), 0, s, flag, p, ldp, perm, pinv, count);
+}
+
+__global__ __launch_bounds__(256) void k_perm_operand(MixedDev md, const uint16_t* dop_old,
+                                                      const int* pinv_old, const int* pinv_new) {
+  const int slot = blockIdx.y;
+  const int64_t nbk = md.S_pad >> 5;
+  int ext = 0;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < md.p; j += (int64_t)gridDim.x * 256) {
+    const uint16_t d = dop_old[frag_index(slot, pinv_old[j], nbk)];
+    const int pos = pinv_new[j];
+    md.dop[frag_index(slot, pos, nbk)] = d;
+    if ((d & 0x7fffu) != 0) ext = max(ext, pos + 1);
+  }
+  ext = wave_max(ext);
+  if ((threadIdx.x & 63) == 0 && ext > 0) {
+    atomicMax(md.keff, ext);
+    atomicMax(md.keff + 1, ext);
+  }
+}
+
+void launch_perm_operand(const MixedDev& md, const uint16_t* dop_old, const int* pinv_old,
+                         const int* pinv_new, hipStream_t s) {
+  hipLaunchKernelGGL(k_perm_operand, dim3(8, (unsigned)md.slots), dim3(256), 0, s, md, dop_old,
+                     pinv_old, pinv_new);
+}
+
+// 64 positions x 64 rows per block through LDS, 16-byte global accesses: thread t reads 8
+// consecutive rows i of design row perm[u] (u = t / 8 + 32 h) and scatters them into the
+// transposed tile; it then writes 8 consecutive positions of one row of Xb per store.
+__global__ __launch_bounds__(256) void k_perm_design(const uint16_t* __restrict__ Xbt,
+                                                     int64_t n_pad, const int* __restrict__ perm,
+                                                     int64_t p, uint16_t* __restrict__ Xb,
+                                                     int64_t ldp) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  __shared__ __attribute__((aligned(16))) uint16_t tile[64][72];  // [i][u]
+  const int64_t u0 = (int64_t)blockIdx.x * 64, i0 = (int64_t)blockIdx.y * 64;
+  const int t = threadIdx.x;
+  const int c8 = (t & 7) * 8;  // 8 rows i (load) or 8 positions u (store)
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = (t >> 3) + 32 * h;  // position within the tile
+    const int64_t u = u0 + r;
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (u < p) v = *reinterpret_cast<const u32x4*>(Xbt + (int64_t)perm[u] * n_pad + i0 + c8);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      tile[c8 + 2 * e][r] = (uint16_t)(v[e] & 0xffffu);
+      tile[c8 + 2 * e + 1][r] = (uint16_t)(v[e] >> 16);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int i = (t >> 3) + 32 * h;
+    const int64_t u = u0 + c8;
+    const u32x4 v = *reinterpret_cast<const u32x4*>(&tile[i][c8]);
+    if (u + 8 <= p) {
+      *reinterpret_cast<u32x4*>(Xb + (i0 + i) * ldp + u) = v;
+    } else {
+      for (int e = 0; e < 8 && u + e < p; ++e)
+        Xb[(i0 + i) * ldp + u + e] = (uint16_t)((v[e >> 1] >> (16 * (e & 1))) & 0xffffu);
+    }
+  }
+}
+
+void launch_perm_design(const uint16_t* Xbt, int64_t n_pad, const int* perm, int64_t p,
+                        uint16_t* Xb, int64_t ldp, hipStream_t s) {
+  const dim3 grid((unsigned)((p + 63) / 64), (unsigned)(n_pad / 64));
+  hipLaunchKernelGGL(k_perm_design, grid, dim3(256), 0, s, Xbt, n_pad, perm, p, Xb, ldp);
+}
+
 // dst[r][c] = src[r][c] widened to FP64, r < rows, c < cols (leading dimensions ld, ldd).
 template <typename XT>
 __global__ __launch_bounds__(256) void k_widen(const XT* __restrict__ src, int64_t ld, int64_t rows,
@@ -654,6 +873,7 @@ void launch_gram_finish(double* H, int64_t ld, int64_t p, int nq, const double* 
 
 // Zero a slot's operand rows (retired or empty slots must not contribute to the products).
 __global__ __launch_bounds__(256) void k_slot_clear(MixedDev md, int slot) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) md.sn[slot] = 0;
   for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < md.ldp; j += (int64_t)gridDim.x * 256)
     md.dop[frag_index(slot, j, md.S_pad >> 5)] = 0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < md.n_pad; i += (int64_t)gridDim.x * 256) {
@@ -714,7 +934,7 @@ void launch_gemm_x(const MixedDev& md, hipStream_t s, bool advance) {
   const int mt = (int)(md.n_pad / GT_M), per = (mt * md.ksx + 7) / 8;
   dim3 grid((unsigned)(8 * per), (unsigned)(md.S_pad / GT_N));
   hipLaunchKernelGGL(k_gemm_bf16<0>, grid, dim3(256), 0, s, g, mt, md.ksx, per,
-                     advance ? md.cycle : nullptr);
+                     advance ? md.cycle : nullptr, (const int*)md.keff);
 }
 
 void launch_gemm_xt(const MixedDev& md, hipStream_t s) {
@@ -731,7 +951,8 @@ void launch_gemm_xt(const MixedDev& md, hipStream_t s) {
   g.c_split_stride = md.dH_split;
   const int mt = (int)(md.ldp / GT_M), per = (mt * md.ksplit + 7) / 8;
   dim3 grid((unsigned)(8 * per), (unsigned)(md.S_pad / GT_N));
-  hipLaunchKernelGGL(k_gemm_bf16<1>, grid, dim3(256), 0, s, g, mt, md.ksplit, per, nullptr);
+  hipLaunchKernelGGL(k_gemm_bf16<1>, grid, dim3(256), 0, s, g, mt, md.ksplit, per, nullptr,
+                     nullptr);
 }
 
 void launch_mixed_loss(const MixedDev& md, hipStream_t s) {

@@ -49,7 +49,24 @@ struct MixedDev {
   int* cycle;           // cycle counter: the cycle running, or between cycles the last one run
   int* prevhead;        // S x 65: last prox head selection (count, indices) per slot
   int* prevtop;         // S x 65: last top-k' selection of the dual monitor per slot
+  // X-pass operand order: coordinate j sits at operand position pinv[j] (the columns of Xb are
+  // permuted alike; identity past p), and the operand is zero at positions >= max(keff[0],
+  // keff[1]). The node kernel of cycle t raises keff[(t + 1) & 1]; the loss kernel of cycle t
+  // clears keff[t & 1] after the X pass of cycle t has read it.
+  const int* pinv;      // ldp
+  const int* perm;      // ldp: the coordinate at each operand position
+  int* keff;            // 2 counters
+  // Operand entries at positions >= *pfx (the support prefix of the current order) leave the
+  // operand as strays: up to kStrayCap per slot, as (coordinate, value) pairs that the loss
+  // kernel adds to the X-pass product (X~ column from the rows of X~^T); a slot with more keeps
+  // the rest in the operand, which the extent then covers.
+  const int* pfx;       // 1
+  int* sn;              // S: strays of the operand in flight
+  int* sj;              // S x kStrayCap coordinates
+  float* sv;            // S x kStrayCap values (BF16-rounded)
 };
+
+constexpr int kStrayCap = 64;
 
 void launch_make_bf16(int xtype, const void* X, int64_t ldx, int64_t n, int64_t p, int64_t n_pad,
                       int64_t ldp, uint16_t* Xb, uint16_t* Xbt, hipStream_t s);
@@ -92,6 +109,20 @@ void launch_cert_resid(const MixedDev& md, const int* list, int nq, const double
 void launch_cert_finish(const MixedDev& md, const int* list, int nq, const double* B64,
                         const double* H64, const double* part, int nchunk, hipStream_t s);
 void launch_slot_clear(const MixedDev& md, int slot, hipStream_t s);
+// Operand order by support: flag[j] = 1 where one of a running slot's last three iterates or its
+// base point is nonzero; then perm (position -> coordinate) and pinv (coordinate -> position) with the flagged
+// coordinates first, each group in increasing order (identity past p), *count = their number;
+// the flags are cleared.
+void launch_perm_flags(const MixedDev& md, uint8_t* flag, hipStream_t s);
+void launch_perm_build(uint8_t* flag, int64_t p, int64_t ldp, int* perm, int* pinv, int* count,
+                       hipStream_t s);
+// Re-lay the operand of every slot from the order pinv_old (a copy in dop_old) to pinv_new and
+// raise both extent counters to one past the last nonzero position.
+void launch_perm_operand(const MixedDev& md, const uint16_t* dop_old, const int* pinv_old,
+                         const int* pinv_new, hipStream_t s);
+// Xb[i][u] = Xbt[perm[u]][i] for u < p (columns past p keep their zeros).
+void launch_perm_design(const uint16_t* Xbt, int64_t n_pad, const int* perm, int64_t p,
+                        uint16_t* Xb, int64_t ldp, hipStream_t s);
 // dst (nq x p, contiguous) = rows list[q] of src (leading dimension ld).
 void launch_gather_rows(const double* src, int64_t ld, const int* list, int nq, int64_t p,
                         double* dst, hipStream_t s);

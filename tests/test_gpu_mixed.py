@@ -155,6 +155,54 @@ def test_gram_certificate_matches_direct_product(dtype, monkeypatch):
         assert ra.lower_bound <= rb.primal and rb.lower_bound <= ra.primal
 
 
+@pytest.mark.parametrize("loss", ["ls", "logistic"])
+def test_operand_reorder_matches_natural_order(loss, monkeypatch):
+    """The X pass reads only the prefix of a support-first column order of X~ (re-laid every few
+    cycles while the nodes run); with the reordering turned off the same nodes give the same
+    certified results within the tolerance, and both match the oracle."""
+    d = synth.make_dataset(500, 300, 6, loss=loss, config_id=87)
+    sets = synth.node_sets(d.p, d.k, 10, 15, config_id=87)
+    re = _problem(d)
+    a = re.solve_batch(_specs(re, sets))
+    monkeypatch.setenv("CGL_NO_REORDER", "1")
+    nat = _problem(d)
+    b = nat.solve_batch(_specs(nat, sets))
+    for (z0, z1), ra, rb in zip(sets, a, b):
+        _check(d, ra, z0, z1)
+        assert rel(ra.primal, rb.primal) <= 2e-6
+        assert ra.lower_bound <= rb.primal + 1e-12 * abs(rb.primal)
+        assert rb.lower_bound <= ra.primal + 1e-12 * abs(ra.primal)
+
+
+def test_support_prefix_strays_and_overflow(monkeypatch):
+    """A support prefix capped far below the union (128 of 300 coordinates) sends every later
+    entrant out of the operand as a stray (added to the X-pass product from X~^T) and, past the
+    per-slot stray capacity, back into the operand beyond the prefix; the certified results still
+    match the oracle."""
+    monkeypatch.setenv("CGL_PREFIX_CAP", "128")
+    d = synth.make_dataset(500, 300, 6, config_id=88)
+    sets = synth.node_sets(d.p, d.k, 6, 15, config_id=88)
+    sets.append((np.array([], int), np.array([], int)))
+    prob = _problem(d)
+    res = prob.solve_batch(_specs(prob, sets))
+    for (z0, z1), r in zip(sets, res):
+        _check(d, r, z0, z1)
+
+
+def test_same_inputs_same_bits():
+    """Two engines on the same inputs (same context, so the same split-K choice) reproduce each
+    other bit for bit, reorders and strays included: no step depends on scheduling."""
+    d = synth.make_dataset(500, 300, 6, config_id=89)
+    sets = synth.node_sets(d.p, d.k, 12, 15, config_id=89)
+    a = _problem(d)
+    ra = a.solve_batch(_specs(a, sets))
+    b = _problem(d)
+    rb = b.solve_batch(_specs(b, sets))
+    for x, y in zip(ra, rb):
+        assert (x.primal, x.lower_bound, x.iters, x.restarts) == (y.primal, y.lower_bound, y.iters, y.restarts)
+        assert np.array_equal(x.beta, y.beta)
+
+
 def test_wide_least_squares_mixed():
     """p > n: no Gram matrix; the certificate comes from the FP64 product with X^T."""
     d = synth.make_dataset(120, 300, 5, config_id=86)

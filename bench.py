@@ -362,7 +362,7 @@ def main():
     for _ in range(args.warmup):
         prob.solve_batch(step_specs)
     ctx.set_profiling(True)
-    for w in range(8):
+    for w in range(10):
         ctx.kernel_stats(w, reset=True)
     t0 = time.perf_counter()
     results = []
@@ -381,6 +381,10 @@ def main():
                         (7, "admission_retirement")):
             ms, cnt = ctx.kernel_stats(w)
             phases[name] = {"ms_per_step": round(ms / args.steps, 3), "count_per_step": cnt / args.steps}
+        # the X pass reads only the operand's nonzero prefix of the support-first column order
+        frac, passes = ctx.kernel_stats(9)
+        if passes:
+            phases["x_pass_kernel"]["mean_columns_read"] = round(frac / passes, 4)
     ok = all(r.status == "converged" and r.gap_rel <= 1e-6 for r in results)
     iters = [r.iters for r in results]
     print(f"# {mode}: {value:.2f} solves/s, all certified: {ok}, iterations median "

@@ -136,7 +136,9 @@ int cgl_ctx_destroy(cgl_ctx* ctx);
  *        2 = batched BF16 MFMA X^T pass, 3 = batched BF16 MFMA X pass, 4 = batched FP64 pass;
  *        and host wall time of the batched engine's phases (launch to completion):
  *        5 = iteration chunks, 6 = certification rounds, 7 = admission and retirement;
- *        8 = the prox kernel of cgl_prox_node_batch (one launch per call).
+ *        8 = the prox kernel of cgl_prox_node_batch (one launch per call);
+ *        9 = the batched X pass's operand extent: total_ms holds the sum over passes of the
+ *            fraction of the padded columns read (not a time), launches the passes.
  * cgl_ctx_kernel_stats returns the totals since the last reset (reset = 1 clears them). */
 int cgl_ctx_set_profiling(cgl_ctx* ctx, int32_t on);
 int cgl_ctx_kernel_stats(cgl_ctx* ctx, int32_t which, int32_t reset, double* total_ms,

@@ -81,7 +81,7 @@ void MixedWork::ensure(Problem& P) {
   set_split_xt(split_cands_xt.front());
   dUp.alloc((size_t)split_cands_x.back() * S_pad * n_pad * 4);
   dH.alloc((size_t)split_cands_xt.back() * S_pad * ldp * 4);
-  rchunk = 2048;
+  rchunk = kLossChunk;
   nrt = (int)((n_pad + rchunk - 1) / rchunk);
   lpart.alloc((size_t)S * nrt * 8);
   fpart.alloc((size_t)S * nrt * 8);
@@ -237,8 +237,8 @@ void MixedWork::ensure(Problem& P) {
     perm_new.alloc((size_t)ldp * sizeof(int));
     CGL_HIP(hipMemcpy(pinv.ptr, id.data(), (size_t)ldp * sizeof(int), hipMemcpyHostToDevice));
     CGL_HIP(hipMemcpy(perm.ptr, id.data(), (size_t)ldp * sizeof(int), hipMemcpyHostToDevice));
-    const int full[2] = {(int)ldp, (int)ldp};
-    keff.alloc(2 * sizeof(int));
+    const int full[4] = {(int)ldp, (int)ldp, 0, 0};
+    keff.alloc(4 * sizeof(int));
     CGL_HIP(hipMemcpy(keff.ptr, full, sizeof(full), hipMemcpyHostToDevice));
     dop_tmp.alloc(dop.bytes);
     CGL_HIP(hipHostMalloc(&order_host, (size_t)(4 + S) * sizeof(int), hipHostMallocDefault));
@@ -365,7 +365,7 @@ static bool mixed_graphs() {
   return !(e && e[0] == '1');
 }
 
-void MixedWork::reorder_operand(Problem& P) {
+void MixedWork::reorder_probe(Problem& P) {
   hipStream_t s = P.ctx->stream;
   int* h = order_host;  // [0, 2): extent counters, [2]: union size, [4, 4 + S): strays per slot
   launch_perm_flags(md, sflag.as<uint8_t>(), s);
@@ -374,18 +374,23 @@ void MixedWork::reorder_operand(Problem& P) {
   CGL_HIP(hipMemcpyAsync(h, keff.ptr, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   CGL_HIP(hipMemcpyAsync(h + 2, scount.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
   CGL_HIP(hipMemcpyAsync(h + 4, sn.ptr, (size_t)S * sizeof(int), hipMemcpyDeviceToHost, s));
-  CGL_HIP(hipStreamSynchronize(s));
+}
+
+void MixedWork::reorder_apply(Problem& P) {
+  hipStream_t s = P.ctx->stream;
+  int* h = order_host;
   const int64_t grain = 2 * GT_K;
   const int64_t now = round_up(std::max(h[0], h[1]), grain);
   int64_t after = std::min(round_up(h[2], grain), ldp);
   if (prefix_cap > 0) after = std::min(after, prefix_cap);
   int64_t strays = 0;
   for (int i = 0; i < S; ++i) strays += h[4 + i];
+  // a stray costs its slot a column of X~ every cycle (one row of X~^T read by the loss kernel);
+  // a reorder rewrites X~ once (about 0.25 ms)
   const bool shorter = after <= now - std::max<int64_t>(2 * grain, now / 8);
-  // a stray costs its slot one column of X~ per cycle; a reorder costs about 0.3 ms
-  if (!shorter && strays <= 2 * S) return;  // the current order still serves
+  if (!shorter && strays <= S) return;  // the current order still serves
   CGL_HIP(hipMemcpyAsync(dop_tmp.ptr, dop.ptr, dop.bytes, hipMemcpyDeviceToDevice, s));
-  CGL_HIP(hipMemsetAsync(keff.ptr, 0, 2 * sizeof(int), s));
+  CGL_HIP(hipMemsetAsync(keff.ptr, 0, 2 * sizeof(int), s));  // the extent counters only
   launch_perm_operand(md, dop_tmp.as<uint16_t>(), pinv.as<int>(), pinv_new.as<int>(), s);
   launch_perm_design(Xbt.as<uint16_t>(), n_pad, perm_new.as<int>(), P.p, Xb.as<uint16_t>(), ldp,
                      s);
@@ -393,19 +398,16 @@ void MixedWork::reorder_operand(Problem& P) {
                          hipMemcpyDeviceToDevice, s));
   CGL_HIP(hipMemcpyAsync(perm.ptr, perm_new.ptr, (size_t)ldp * sizeof(int),
                          hipMemcpyDeviceToDevice, s));
-  h[3] = (int)after;  // the union fills the prefix; later entrants behind it become strays
+  // the union fills the prefix; later entrants behind it become strays (h[3] is rewritten only
+  // after the next chunk's synchronisation, when this copy has run)
+  h[3] = (int)after;
   CGL_HIP(hipMemcpyAsync(pfx.ptr, h + 3, sizeof(int), hipMemcpyHostToDevice, s));
-  CGL_HIP(hipStreamSynchronize(s));  // h is reused by the next check
   reorders += 1;
 }
 
 void MixedWork::run_chunk(Problem& P) {
   hipStream_t s = P.ctx->stream;
   cgl_ctx* ctx = P.ctx;
-  if (reorder && cycles - reorder_checked >= kReorderEvery) {
-    reorder_checked = cycles;
-    reorder_operand(P);
-  }
   // with profiling on, each cycle's two products are bracketed by HIP events on the stream (HIP
   // cannot time events recorded inside a graph, so the cycles are then launched one by one)
   if (ctx->profiling || !mixed_graphs()) {
@@ -425,9 +427,23 @@ void MixedWork::run_chunk(Problem& P) {
     }
     CGL_HIP(hipGraphLaunch(graph_exec, s));
   }
+  // the operand order is checked with the chunk's own synchronisation and changed (if at all)
+  // before the next launches
+  const bool probe = reorder && cycles + kChunk - reorder_checked >= kReorderEvery;
+  if (probe) reorder_probe(P);
   CGL_HIP(hipMemcpyAsync(st_host, st.ptr, (size_t)S * sizeof(NodeDev), hipMemcpyDeviceToHost, s));
   CGL_HIP(hipStreamSynchronize(s));
+  if (probe) {
+    reorder_checked = cycles + kChunk;
+    reorder_apply(P);
+  }
   if (ctx->profiling) {
+    // mean X-pass operand extent: total = sum of the extents as fractions of ldp, count = passes
+    int es[2];
+    CGL_HIP(hipMemcpy(es, keff.as<int>() + 2, sizeof(es), hipMemcpyDeviceToHost));
+    CGL_HIP(hipMemset(keff.as<int>() + 2, 0, sizeof(es)));
+    ctx->kt_ms[9] += (double)es[0] * (2 * GT_K) / (double)ldp;
+    ctx->kt_n[9] += es[1];
     for (int i = 0; i < kChunk; ++i) {
       float a = 0.f, b = 0.f;
       CGL_HIP(hipEventElapsedTime(&a, ctx->event((size_t)(4 * i)), ctx->event((size_t)(4 * i + 1))));
@@ -589,6 +605,12 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
   CGL_HIP(hipMemcpyAsync(cls.ptr, cls_host.data(), cls_host.size(), hipMemcpyHostToDevice, s));
   CGL_HIP(hipMemcpyAsync(st.ptr, st_host, (size_t)S * sizeof(NodeDev), hipMemcpyHostToDevice, s));
   CGL_HIP(hipStreamSynchronize(s));
+  if (reorder && (int)adm.size() >= S / 4) {
+    // many new supports: no prefix (no strays) until they have settled for two check intervals
+    const int nopfx = (int)ldp;
+    CGL_HIP(hipMemcpy(pfx.ptr, &nopfx, sizeof(int), hipMemcpyHostToDevice));
+    reorder_checked = cycles + kReorderEvery;
+  }
 }
 
 void MixedWork::retire(Problem& P, const std::vector<int>& slots,

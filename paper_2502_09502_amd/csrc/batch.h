@@ -68,10 +68,13 @@ struct MixedWork {
   void ensure(Problem& P);
   void run_chunk(Problem& P);
   bool cert_round(Problem& P);
-  // Puts the coordinates where a running slot's recent iterates or base point are nonzero first
-  // in the X-pass operand order (and the columns of Xb alike), with the support prefix at their
-  // count, when that shortens the operand's extent by an eighth or the strays have piled up.
-  void reorder_operand(Problem& P);
+  // X-pass operand order. The probe (queued at the end of a chunk) lists the coordinates where a
+  // running slot's recent iterates, base point or operand are nonzero and stages the extent and
+  // stray counts for the host; after the chunk's synchronisation, apply puts those coordinates
+  // first (the columns of Xb alike, the support prefix at their count) when that shortens the
+  // operand's extent by an eighth or the strays have piled up.
+  void reorder_probe(Problem& P);
+  void reorder_apply(Problem& P);
   void admit(Problem& P, const std::vector<Admission>& adm);
   // Results of finished slots and their best certified iterates (beta_out[i] may be null): one
   // gather of the iterates on the device, one copy to pinned host memory, then into the

@@ -55,11 +55,13 @@ __device__ __forceinline__ bool slot_running(const NodeDev* st) {
 //
 // bump (optional): the cycle counter, advanced by one thread of the launch; no kernel of the
 // launch reads it and the kernels after it see the new value.
+// extent (X pass only): the operand extent counters (the pass reads the columns below the larger
+// of extent[0] and extent[1]); with bump, extent[2] and extent[3] accumulate the columns read
+// (units of 2 GT_K) and the passes.
 template <int PASS>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int mtiles, int ks, int per_xcd,
-                                                   int* bump, const int* extent) {
+                                                   int* bump, int* extent) {
   __shared__ __attribute__((aligned(16))) uint16_t As[2 * GT_M * GT_LD];
-  if (bump != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *bump += 1;
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
   const int pair = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
@@ -74,6 +76,13 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int mtiles, int k
     const int64_t e = max(extent[0], extent[1]);
     K = min(K, (e + 2 * GT_K - 1) / (2 * GT_K) * (2 * GT_K));
     kc = ((K + ks - 1) / ks + 2 * GT_K - 1) / (2 * GT_K) * (2 * GT_K);
+  }
+  if (bump != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    *bump += 1;
+    if (extent != nullptr) {  // statistics: extents read (units of 2 GT_K columns), passes
+      extent[2] += (int)(K / (2 * GT_K));
+      extent[3] += 1;
+    }
   }
   const int64_t k0 = (int64_t)z * kc;
   const int64_t k1 = min(K, k0 + kc);
@@ -121,20 +130,33 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
   float* duo = md.dU + (int64_t)((cyc + 1) & 1) * md.dU_ring + (int64_t)slot * md.n_pad;
   const int64_t i0 = (int64_t)blockIdx.x * md.rchunk;
   const int64_t i1 = min(md.n_pad, i0 + md.rchunk);
-  // strays of the operand: X~ column j is row j of X~^T
-  __shared__ const uint16_t* scol[kStrayCap];
-  __shared__ float sval[kStrayCap];
+  // strays of the operand: X~ column j is row j of X~^T; each thread sums them for 8 consecutive
+  // rows of the chunk (16-byte loads), in list order
   const int ns = md.sn[slot];
-  for (int e = threadIdx.x; e < ns; e += 256) {
-    scol[e] = md.Xbt + (int64_t)md.sj[(int64_t)slot * kStrayCap + e] * md.n_pad;
-    sval[e] = md.sv[(int64_t)slot * kStrayCap + e];
+  __shared__ float sdu[kLossChunk];
+  if (ns > 0) {  // uniform over the block
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const int64_t r8 = 8 * (int64_t)threadIdx.x;
+    if (i0 + r8 < i1) {
+      float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      for (int e = 0; e < ns; ++e) {
+        const int64_t j = md.sj[(int64_t)slot * kStrayCap + e];
+        const float v = md.sv[(int64_t)slot * kStrayCap + e];
+        const u32x4 x = *reinterpret_cast<const u32x4*>(md.Xbt + j * md.n_pad + i0 + r8);
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          a[c] += bf16_to_float((uint16_t)((x[c >> 1] >> (16 * (c & 1))) & 0xffffu)) * v;
+      }
+#pragma unroll
+      for (int c = 0; c < 8; ++c) sdu[r8 + c] = a[c];
+    }
+    __syncthreads();
   }
-  __syncthreads();
   double ls = 0.0;
   for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
     float du = 0.f;
     for (int q = 0; q < md.ksx; ++q) du += md.dUp[(int64_t)q * md.dUp_split + (int64_t)slot * md.n_pad + i];
-    for (int e = 0; e < ns; ++e) du += bf16_to_float(scol[e][i]) * sval[e];
+    if (ns > 0) du += sdu[i - i0];
     if (rebase) {
       duo[i] -= du;
       du = 0.f;
@@ -306,11 +328,8 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
   }
   const int64_t nbk = md.S_pad >> 5;
   // operand extent (LDS: nothing extra stays live through the prox)
-  __shared__ int ext_s, ext_over;
-  if (threadIdx.x == 0) {
-    ext_s = 0;
-    ext_over = 0;
-  }
+  __shared__ int ext_s;
+  if (threadIdx.x == 0) ext_s = 0;
   __syncthreads();
   const ProxOut po = node_prox<E>(
       [&](int s) { return pv.get(s); }, neg, cb, st->kp, st->nfree, md.rho, md.M, st->vstar,
@@ -326,9 +345,11 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
       },
       sm, slice, md.prevhead + (int64_t)slot * 65);
   __syncthreads();
-  // Entries past the support prefix leave the operand as strays, the first kStrayCap of them in
-  // position order (the rest stay and the extent covers them). Two passes over the operand stores
-  // of the whole block (ordered by the barrier above): count per thread, exclusive scan, assign.
+  // Entries past the support prefix leave the operand as strays, in position order, when there
+  // are at most kStrayCap of them; otherwise they all stay and the extent covers them (their
+  // columns are read by the X pass then, so strays would only add reads). Two passes over the
+  // operand stores of the whole block (ordered by the barrier above): count per thread,
+  // exclusive scan, assign.
   const int pfx = *md.pfx;
   const int ext_all = ext_s;
   int ext = min(ext_all, pfx);
@@ -362,26 +383,21 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
       total += wsum[w];
     }
     int idx = base + incl - cnt;
-    ns = min(total, kStrayCap);
-    for (int u8 = ubeg; u8 < ext_all && cnt > 0; u8 += 8 * kProxThreads) {
+    ns = total <= kStrayCap ? total : 0;
+    for (int u8 = ubeg; u8 < ext_all && cnt > 0 && ns > 0; u8 += 8 * kProxThreads) {
       uint16_t* g8 = md.dop + frag_index(slot, u8, nbk);
       const u32x4 v = *reinterpret_cast<const u32x4*>(g8);
       for (int e = 0; e < 8; ++e) {
         if (!late(u8, v, e)) continue;
         const int u = u8 + e;
-        if (idx < kStrayCap) {
-          md.sj[(int64_t)slot * kStrayCap + idx] = md.perm[u];
-          md.sv[(int64_t)slot * kStrayCap + idx] =
-              bf16_to_float((uint16_t)((v[e >> 1] >> (16 * (e & 1))) & 0xffffu));
-          g8[e] = 0;
-        } else {
-          atomicMax(&ext_over, u + 1);
-        }
+        md.sj[(int64_t)slot * kStrayCap + idx] = md.perm[u];
+        md.sv[(int64_t)slot * kStrayCap + idx] =
+            bf16_to_float((uint16_t)((v[e >> 1] >> (16 * (e & 1))) & 0xffffu));
+        g8[e] = 0;
         ++idx;
       }
     }
-    __syncthreads();
-    ext = max(ext, ext_over);
+    if (ns == 0) ext = ext_all;
   }
   if (threadIdx.x == 0 && ext > 0) atomicMax(md.keff + ((cyc + 1) & 1), ext);
   if (threadIdx.x == 0) md.sn[slot] = ns;
@@ -716,12 +732,19 @@ __global__ __launch_bounds__(256) void k_perm_flags(MixedDev md, uint8_t* flag) 
   const int slot = blockIdx.y;
   const NodeDev* st = md.st + slot;
   if (!slot_running(st)) return;
-  // the three iterates of the ring (the latest and the two before it) and the base point
+  // the three iterates of the ring (the latest and the two before it), the base point, the
+  // operand in flight (after a re-centre that kept the momentum it is measured from the previous
+  // base point) and its strays
   const double* b = md.bring + (int64_t)slot * md.ldp;
   const double* b0 = md.beta0 + (int64_t)slot * md.ldp;
   const int64_t rs = md.bring_stride;
+  const int64_t nbk = md.S_pad >> 5;
   for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < md.p; j += (int64_t)gridDim.x * 256)
-    if (b[j] != 0.0 || b[rs + j] != 0.0 || b[2 * rs + j] != 0.0 || b0[j] != 0.0) flag[j] = 1;
+    if (b[j] != 0.0 || b[rs + j] != 0.0 || b[2 * rs + j] != 0.0 || b0[j] != 0.0 ||
+        (md.dop[frag_index(slot, md.pinv[j], nbk)] & 0x7fffu) != 0)
+      flag[j] = 1;
+  if (blockIdx.x == 0 && (int)threadIdx.x < md.sn[slot])
+    flag[md.sj[(int64_t)slot * kStrayCap + threadIdx.x]] = 1;
 }
 
 void launch_perm_flags(const MixedDev& md, uint8_t* flag, hipStream_t s) {
@@ -934,7 +957,7 @@ void launch_gemm_x(const MixedDev& md, hipStream_t s, bool advance) {
   const int mt = (int)(md.n_pad / GT_M), per = (mt * md.ksx + 7) / 8;
   dim3 grid((unsigned)(8 * per), (unsigned)(md.S_pad / GT_N));
   hipLaunchKernelGGL(k_gemm_bf16<0>, grid, dim3(256), 0, s, g, mt, md.ksx, per,
-                     advance ? md.cycle : nullptr, (const int*)md.keff);
+                     advance ? md.cycle : nullptr, md.keff);
 }
 
 void launch_gemm_xt(const MixedDev& md, hipStream_t s) {

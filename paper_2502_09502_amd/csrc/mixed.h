@@ -55,7 +55,7 @@ struct MixedDev {
   // clears keff[t & 1] after the X pass of cycle t has read it.
   const int* pinv;      // ldp
   const int* perm;      // ldp: the coordinate at each operand position
-  int* keff;            // 2 counters
+  int* keff;            // 2 counters, then the extent statistics (columns / 128, passes)
   // Operand entries at positions >= *pfx (the support prefix of the current order) leave the
   // operand as strays: up to kStrayCap per slot, as (coordinate, value) pairs that the loss
   // kernel adds to the X-pass product (X~ column from the rows of X~^T); a slot with more keeps
@@ -67,6 +67,7 @@ struct MixedDev {
 };
 
 constexpr int kStrayCap = 64;
+constexpr int kLossChunk = 2048;  // rows per block of the loss and residual kernels (8 per thread)
 
 void launch_make_bf16(int xtype, const void* X, int64_t ldx, int64_t n, int64_t p, int64_t n_pad,
                       int64_t ldp, uint16_t* Xb, uint16_t* Xbt, hipStream_t s);
@@ -109,8 +110,8 @@ void launch_cert_resid(const MixedDev& md, const int* list, int nq, const double
 void launch_cert_finish(const MixedDev& md, const int* list, int nq, const double* B64,
                         const double* H64, const double* part, int nchunk, hipStream_t s);
 void launch_slot_clear(const MixedDev& md, int slot, hipStream_t s);
-// Operand order by support: flag[j] = 1 where one of a running slot's last three iterates or its
-// base point is nonzero; then perm (position -> coordinate) and pinv (coordinate -> position) with the flagged
+// Operand order by support: flag[j] = 1 where one of a running slot's last three iterates, its
+// base point or its operand in flight (strays included) is nonzero; then perm (position -> coordinate) and pinv (coordinate -> position) with the flagged
 // coordinates first, each group in increasing order (identity past p), *count = their number;
 // the flags are cleared.
 void launch_perm_flags(const MixedDev& md, uint8_t* flag, hipStream_t s);

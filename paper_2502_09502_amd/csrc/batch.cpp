@@ -241,7 +241,7 @@ void MixedWork::ensure(Problem& P) {
     keff.alloc(4 * sizeof(int));
     CGL_HIP(hipMemcpy(keff.ptr, full, sizeof(full), hipMemcpyHostToDevice));
     dop_tmp.alloc(dop.bytes);
-    CGL_HIP(hipHostMalloc(&order_host, (size_t)(4 + S) * sizeof(int), hipHostMallocDefault));
+    CGL_HIP(hipHostMalloc(&order_host, (size_t)(6 + S) * sizeof(int), hipHostMallocDefault));
     // no support prefix (and so no strays) until the first reorder
     pfx.alloc(sizeof(int));
     const int nopfx = (int)ldp;
@@ -431,6 +431,11 @@ void MixedWork::run_chunk(Problem& P) {
   // before the next launches
   const bool probe = reorder && cycles + kChunk - reorder_checked >= kReorderEvery;
   if (probe) reorder_probe(P);
+  int* es = order_host + 4 + S;  // X-pass extent statistics of this chunk (profiling)
+  if (ctx->profiling) {
+    CGL_HIP(hipMemcpyAsync(es, keff.as<int>() + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    CGL_HIP(hipMemsetAsync(keff.as<int>() + 2, 0, 2 * sizeof(int), s));
+  }
   CGL_HIP(hipMemcpyAsync(st_host, st.ptr, (size_t)S * sizeof(NodeDev), hipMemcpyDeviceToHost, s));
   CGL_HIP(hipStreamSynchronize(s));
   if (probe) {
@@ -439,9 +444,6 @@ void MixedWork::run_chunk(Problem& P) {
   }
   if (ctx->profiling) {
     // mean X-pass operand extent: total = sum of the extents as fractions of ldp, count = passes
-    int es[2];
-    CGL_HIP(hipMemcpy(es, keff.as<int>() + 2, sizeof(es), hipMemcpyDeviceToHost));
-    CGL_HIP(hipMemset(keff.as<int>() + 2, 0, sizeof(es)));
     ctx->kt_ms[9] += (double)es[0] * (2 * GT_K) / (double)ldp;
     ctx->kt_n[9] += es[1];
     for (int i = 0; i < kChunk; ++i) {

@@ -44,7 +44,7 @@ struct MixedWork {
   double* beta_host = nullptr;  // pinned staging of retired iterates (S x p)
   int* count_host = nullptr;    // pinned: size of the support union of a certification round
   int64_t support_sum = 0;      // sum over certification rounds of the union size (statistics)
-  int* order_host = nullptr;    // pinned: extent counters, support prefix, strays per slot
+  int* order_host = nullptr;    // pinned: extent counters, support prefix, strays per slot, extent statistics
   bool reorder = true;          // CGL_NO_REORDER=1 keeps the natural coordinate order
   int64_t reorder_checked = 0;  // cycle of the last reorder check
   int64_t reorders = 0;

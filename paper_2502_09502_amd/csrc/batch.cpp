@@ -348,10 +348,12 @@ void MixedWork::tune_splits(Problem& P) {
 
 // One iteration of Alg. 3 for every running slot; ev (optional): events around the two MFMA
 // passes for kernel timing.
-static void mixed_cycle(MixedWork& W, hipStream_t s, hipEvent_t* ev = nullptr) {
-  if (ev) CGL_HIP(hipEventRecord(ev[0], s));
+// ev: events around the X^T pass (ev[2], ev[3]) and, with time_x, the X pass (ev[0], ev[1]); each
+// event on the stream costs the next kernel a few microseconds of start-up.
+static void mixed_cycle(MixedWork& W, hipStream_t s, hipEvent_t* ev = nullptr, bool time_x = false) {
+  if (ev && time_x) CGL_HIP(hipEventRecord(ev[0], s));
   launch_gemm_x(W.md, s, true);
-  if (ev) CGL_HIP(hipEventRecord(ev[1], s));
+  if (ev && time_x) CGL_HIP(hipEventRecord(ev[1], s));
   launch_mixed_loss(W.md, s);
   launch_mixed_resid(W.md, s);
   if (ev) CGL_HIP(hipEventRecord(ev[2], s));
@@ -408,13 +410,14 @@ void MixedWork::reorder_apply(Problem& P) {
 void MixedWork::run_chunk(Problem& P) {
   hipStream_t s = P.ctx->stream;
   cgl_ctx* ctx = P.ctx;
-  // with profiling on, each cycle's two products are bracketed by HIP events on the stream (HIP
-  // cannot time events recorded inside a graph, so the cycles are then launched one by one)
+  // with profiling on, each cycle's X^T pass (and at level 2 its X pass) is bracketed by HIP
+  // events on the stream (HIP cannot time events recorded inside a graph, so the cycles are then
+  // launched one by one)
   if (ctx->profiling || !mixed_graphs()) {
     for (int i = 0; i < kChunk; ++i) {
       hipEvent_t ev[4];
       for (int e = 0; e < 4; ++e) ev[e] = ctx->event((size_t)(4 * i + e));
-      mixed_cycle(*this, s, ctx->profiling ? ev : nullptr);
+      mixed_cycle(*this, s, ctx->profiling ? ev : nullptr, ctx->profile_x);
     }
   } else {
     if (!graph_exec) {
@@ -431,11 +434,9 @@ void MixedWork::run_chunk(Problem& P) {
   // before the next launches
   const bool probe = reorder && cycles + kChunk - reorder_checked >= kReorderEvery;
   if (probe) reorder_probe(P);
-  int* es = order_host + 4 + S;  // X-pass extent statistics of this chunk (profiling)
-  if (ctx->profiling) {
-    CGL_HIP(hipMemcpyAsync(es, keff.as<int>() + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-    CGL_HIP(hipMemsetAsync(keff.as<int>() + 2, 0, 2 * sizeof(int), s));
-  }
+  int* es = order_host + 4 + S;  // X-pass extent statistics of this chunk (kept when profiling)
+  CGL_HIP(hipMemcpyAsync(es, keff.as<int>() + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  CGL_HIP(hipMemsetAsync(keff.as<int>() + 2, 0, 2 * sizeof(int), s));
   CGL_HIP(hipMemcpyAsync(st_host, st.ptr, (size_t)S * sizeof(NodeDev), hipMemcpyDeviceToHost, s));
   CGL_HIP(hipStreamSynchronize(s));
   if (probe) {
@@ -448,11 +449,13 @@ void MixedWork::run_chunk(Problem& P) {
     ctx->kt_n[9] += es[1];
     for (int i = 0; i < kChunk; ++i) {
       float a = 0.f, b = 0.f;
-      CGL_HIP(hipEventElapsedTime(&a, ctx->event((size_t)(4 * i)), ctx->event((size_t)(4 * i + 1))));
+      if (ctx->profile_x) {
+        CGL_HIP(hipEventElapsedTime(&a, ctx->event((size_t)(4 * i)), ctx->event((size_t)(4 * i + 1))));
+        ctx->kt_ms[3] += a;  // X pass
+        ctx->kt_n[3] += 1;
+      }
       CGL_HIP(hipEventElapsedTime(&b, ctx->event((size_t)(4 * i + 2)), ctx->event((size_t)(4 * i + 3))));
-      ctx->kt_ms[3] += a;  // X pass
       ctx->kt_ms[2] += b;  // X^T pass
-      ctx->kt_n[3] += 1;
       ctx->kt_n[2] += 1;
     }
   }

@@ -500,23 +500,22 @@ bool MixedWork::cert_round(Problem& P) {
   // exact zeros), from the rows of the transposed design
   launch_cert_gather(md, list.as<int>(), nq, B64.as<double>(), sflag.as<uint8_t>(), s);
   launch_cert_support(sflag.as<uint8_t>(), P.p, sidx.as<int>(), scount.as<int>(), s);
+  // the union's size stays on the device: the products read it at launch and split it over
+  // chunks sized for all p coordinates
   CGL_HIP(hipMemcpyAsync(count_host, scount.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
-  CGL_HIP(hipStreamSynchronize(s));
-  const int K = *count_host;
-  if (K < 0 || K > P.p) throw std::runtime_error("support union out of range");
-  support_sum += K;
   const void* xt = P.xtype == XT_BF16 ? Xbt.ptr : Xt.ptr;
+  const int* kdev = scount.as<int>();
   if (e0) CGL_HIP(hipEventRecord(e0, s));
-  launch_cert_compact(B64.as<double>(), ldp, sidx.as<int>(), K, nq, Bu.as<double>(), s);
-  launch_gemm_f64_rows(P.xtype, xt, n_pad, sidx.as<int>(), P.n, K, Bu.as<double>(), ldp, nq,
-                       U64.as<double>(), n_pad, part64.as<double>(), part64_cap, s);
+  launch_cert_compact(B64.as<double>(), ldp, sidx.as<int>(), kdev, P.p, nq, Bu.as<double>(), s);
+  launch_gemm_f64_rows(P.xtype, xt, n_pad, sidx.as<int>(), P.n, P.p, kdev, Bu.as<double>(), ldp,
+                       nq, U64.as<double>(), n_pad, part64.as<double>(), part64_cap, s);
   if (e1) CGL_HIP(hipEventRecord(e1, s));
   // X^T grad f(X beta): least squares from the Gram rows on the same support (p K against n p
   // products), else the FP64 product with all of X^T
-  const bool gram = G.ptr != nullptr && K < P.n;
+  const bool gram = G.ptr != nullptr;
   if (gram) {
-    launch_gemm_f64_rows(XT_F64, G.ptr, ldg, sidx.as<int>(), P.p, K, Bu.as<double>(), ldp, nq,
-                         H64.as<double>(), ldp, part64.as<double>(), part64_cap, s);
+    launch_gemm_f64_rows(XT_F64, G.ptr, ldg, sidx.as<int>(), P.p, P.p, kdev, Bu.as<double>(), ldp,
+                         nq, H64.as<double>(), ldp, part64.as<double>(), part64_cap, s);
     launch_gram_finish(H64.as<double>(), ldp, P.p, nq, H0_cold.as<double>(), s);
   }
   launch_cert_resid(md, list.as<int>(), nq, U64.as<double>(), R64.as<double>(),
@@ -528,6 +527,8 @@ bool MixedWork::cert_round(Problem& P) {
                      cpart.as<double>(), ncchunk, s);
   CGL_HIP(hipMemcpyAsync(st_host, st.ptr, (size_t)S * sizeof(NodeDev), hipMemcpyDeviceToHost, s));
   CGL_HIP(hipStreamSynchronize(s));
+  if (*count_host < 0 || *count_host > P.p) throw std::runtime_error("support union out of range");
+  support_sum += *count_host;
   if (e0) {
     float a = 0.f;
     CGL_HIP(hipEventElapsedTime(&a, e0, e1));

@@ -164,7 +164,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(F64GemmArgs g) {
 //   At: the transposed design (one row per coordinate, row-major, ldat a multiple of 256 that
 //       covers every row m of the product), in the stored precision;
 //   idx: the K coordinates kept, readable up to K rounded up to 16 (entries past K name a valid
-//        row; their terms are replaced by zero);
+//        row; their terms are replaced by zero); K may be read from device memory at launch;
 //   B: Q x K FP64, the right-hand sides compacted to those coordinates (ldb >= K rounded up to 16).
 // When every coordinate left out is zero in every right-hand side, this is the full product of
 // the design with the uncompacted right-hand sides, up to the order of the FP64 sum.
@@ -184,6 +184,7 @@ struct F64RowsArgs {
   int64_t kchunk;  // split-K chunk, a multiple of 16
   double* C;       // final result (ksplit == 1) or Q x M partials per chunk (ksplit > 1)
   int64_t ldc;
+  const int* kdev;  // if set: K is *kdev (at most g.K) and the gridDim.z chunks split it evenly
 };
 
 template <typename XT, int NT>
@@ -197,8 +198,13 @@ __global__ __launch_bounds__(256) void k_gemm_f64_rows(F64RowsArgs g) {
   const int64_t m0 = ((int64_t)blockIdx.x * 4 + wid) * (16 * F64_RT);
   if (m0 >= g.M) return;  // no barrier below: a wave past the last row may leave at once
   const int q0 = (int)blockIdx.y * 16 * NT;
-  const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
-  const int64_t ke = min(kb + g.kchunk, g.K);
+  int64_t K = g.K, kc = g.kchunk;
+  if (g.kdev != nullptr) {
+    K = min((int64_t)*g.kdev, g.K);
+    kc = ((K + gridDim.z - 1) / gridDim.z + 15) / 16 * 16;
+  }
+  const int64_t kb = (int64_t)blockIdx.z * kc;
+  const int64_t ke = min(kb + kc, K);
   const int li = lane & 15;
   const int kk = lane >> 4;
   // rows m0 + 4 li .. + 3 of the transposed design (inside ldat: m0 + 64 <= ldat)

@@ -508,10 +508,11 @@ __global__ __launch_bounds__(1024) void k_cert_support(uint8_t* flag, int64_t p,
   if (t == 0) *count = K;
 }
 
-// Bu[q][u] = B64[q][idx[u]] for u < K, 0 up to K rounded up to 16.
+// Bu[q][u] = B64[q][idx[u]] for u < K = *kdev, 0 up to K rounded up to 16.
 __global__ __launch_bounds__(256) void k_cert_compact(const double* B64, int64_t ld, const int* idx,
-                                                      int K, int nq, double* Bu) {
+                                                      const int* kdev, int nq, double* Bu) {
   const int q = blockIdx.y;
+  const int K = *kdev;
   const int Kp = (K + 15) / 16 * 16;
   for (int u = blockIdx.x * 256 + threadIdx.x; u < Kp; u += gridDim.x * 256)
     Bu[(int64_t)q * ld + u] = u < K ? B64[(int64_t)q * ld + idx[u]] : 0.0;
@@ -1061,11 +1062,12 @@ void launch_gemm_f64(int xtype, const void* A, int64_t lda, int64_t M, int64_t K
 }
 
 void launch_gemm_f64_rows(int xtype, const void* At, int64_t ldat, const int* idx, int64_t M,
-                          int64_t K, const double* B, int64_t ldb, int Q, double* C, int64_t ldc,
-                          double* part, size_t part_cap, hipStream_t s) {
+                          int64_t K, const int* kdev, const double* B, int64_t ldb, int Q,
+                          double* C, int64_t ldc, double* part, size_t part_cap, hipStream_t s) {
   if (Q <= 0 || M <= 0) return;
   const F64Launch l = f64_launch(M, K, Q, part_cap);
-  F64RowsArgs g{At, ldat, idx, B, ldb, M, K, Q, l.chunk, l.ks > 1 ? part : C, l.ks > 1 ? M : ldc};
+  F64RowsArgs g{At, ldat, idx, B, ldb, M, K, Q, l.chunk, l.ks > 1 ? part : C, l.ks > 1 ? M : ldc,
+                kdev};
   dim3 grid((unsigned)l.mblocks, (unsigned)l.qblocks, (unsigned)l.ks);
 #define CGL_F64_CALL(T)                                                                   \
   if (l.nt == 2) hipLaunchKernelGGL((k_gemm_f64_rows<T, 2>), grid, dim3(256), 0, s, g); \
@@ -1087,13 +1089,13 @@ void launch_cert_support(uint8_t* flag, int64_t p, int* idx, int* count, hipStre
   hipLaunchKernelGGL(k_cert_support, dim3(1), dim3(1024), 0, s, flag, p, idx, count);
 }
 
-void launch_cert_compact(const double* B64, int64_t ld, const int* idx, int K, int nq, double* Bu,
-                         hipStream_t s) {
+void launch_cert_compact(const double* B64, int64_t ld, const int* idx, const int* kdev,
+                         int64_t Kmax, int nq, double* Bu, hipStream_t s) {
   if (nq <= 0) return;
-  const int Kp = (K + 15) / 16 * 16;
-  const unsigned gx = (unsigned)std::max(1, std::min((Kp + 255) / 256, 16));
-  hipLaunchKernelGGL(k_cert_compact, dim3(gx, (unsigned)nq), dim3(256), 0, s, B64, ld, idx, K, nq,
-                     Bu);
+  const int64_t Kp = (Kmax + 15) / 16 * 16;
+  const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((Kp + 255) / 256, 16));
+  hipLaunchKernelGGL(k_cert_compact, dim3(gx, (unsigned)nq), dim3(256), 0, s, B64, ld, idx, kdev,
+                     nq, Bu);
 }
 
 void launch_cert_resid(const MixedDev& md, const int* list, int nq, const double* U64,

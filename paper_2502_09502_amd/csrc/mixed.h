@@ -84,10 +84,11 @@ void launch_gemm_f64(int xtype, const void* A, int64_t lda, int64_t M, int64_t K
                      size_t part_cap, hipStream_t s);
 // C[q][m] = sum_{u < K} At[idx[u]][m] B[q][u] in FP64: the product with right-hand sides that
 // are zero outside the coordinates idx (At: transposed design, ldat >= M rounded up to 256;
-// idx readable up to K rounded up to 16; B compacted to those coordinates).
+// idx readable up to K rounded up to 16; B compacted to those coordinates). With kdev, K is read
+// from device memory at launch (at most the K given, which sets the launch shape).
 void launch_gemm_f64_rows(int xtype, const void* At, int64_t ldat, const int* idx, int64_t M,
-                          int64_t K, const double* B, int64_t ldb, int Q, double* C, int64_t ldc,
-                          double* part, size_t part_cap, hipStream_t s);
+                          int64_t K, const int* kdev, const double* B, int64_t ldb, int Q,
+                          double* C, int64_t ldc, double* part, size_t part_cap, hipStream_t s);
 // dst[r][c] = src[r][c] (the design's stored precision) widened to FP64, r < rows, c < cols.
 void launch_widen(int xtype, const void* src, int64_t ld, int64_t rows, int64_t cols, double* dst,
                   int64_t ldd, hipStream_t s);
@@ -102,9 +103,10 @@ void launch_cert_gather(const MixedDev& md, const int* list, int nq, double* B64
 // idx = the flagged coordinates in order (zero padded to a multiple of 16), *count = their
 // number; clears the flags.
 void launch_cert_support(uint8_t* flag, int64_t p, int* idx, int* count, hipStream_t s);
-// Bu[q][u] = B64[q][idx[u]] for u < K, zero up to K rounded up to 16 (leading dimension ld).
-void launch_cert_compact(const double* B64, int64_t ld, const int* idx, int K, int nq, double* Bu,
-                         hipStream_t s);
+// Bu[q][u] = B64[q][idx[u]] for u < K = *kdev (K <= Kmax), zero up to K rounded up to 16
+// (leading dimension ld).
+void launch_cert_compact(const double* B64, int64_t ld, const int* idx, const int* kdev,
+                         int64_t Kmax, int nq, double* Bu, hipStream_t s);
 void launch_cert_resid(const MixedDev& md, const int* list, int nq, const double* U64,
                        double* R64, double* part, int nchunk, int64_t chunk, hipStream_t s);
 void launch_cert_finish(const MixedDev& md, const int* list, int nq, const double* B64,

@@ -53,7 +53,7 @@ def algorithmic_bytes(which: int, n: int, p: int, sx: int, nodes: int) -> float:
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_bf16_c4_traffic.md")
-TRAFFIC_SOURCES = ("paper_2502_09502_amd/csrc/gemm_bf16.h", "paper_2502_09502_amd/csrc/kernels_mfma.hip")
+TRAFFIC_SOURCES = ("paper_2502_09502_amd/csrc/gemm_bf16.h",)  # the product kernels and their main loop
 
 
 def measured_traffic(key: str):

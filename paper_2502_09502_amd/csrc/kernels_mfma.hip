@@ -42,73 +42,6 @@ __device__ __forceinline__ bool slot_running(const NodeDev* st) {
 }
 
 // =====================================================================================
-// BF16 MFMA product (see gemm_bf16.h), split-K partials stored node-major.
-// Element e of lane l in tile c: row i = (e % 4) + 4 (l / 32) + 8 (e / 4), node j = l % 32.
-// =====================================================================================
-// PASS only names the instantiation (0: X~ (beta - beta_0), 1: X~^T (grad - r_0)) so that
-// profiles report the two products separately.
-//
-// 1D grid, XCD-aware: workgroups are dispatched round-robin over the 8 XCDs by linear id, so the
-// (row tile, k-chunk) pairs, ordered k-chunk-major, are cut into 8 contiguous ranges and range x
-// is given to the ids that land on XCD x. The workgroups of one XCD then share one or two
-// k-chunks of B in that XCD's L2. Node tiles (blockIdx.y) are outermost.
-//
-// bump (optional): the cycle counter, advanced by one thread of the launch; no kernel of the
-// launch reads it and the kernels after it see the new value.
-// extent (X pass only): the operand extent counters (the pass reads the columns below the larger
-// of extent[0] and extent[1]); with bump, extent[2] and extent[3] accumulate the columns read
-// (units of 2 GT_K) and the passes.
-template <int PASS>
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int mtiles, int ks, int per_xcd,
-                                                   int* bump, int* extent) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[2 * GT_M * GT_LD];
-  const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
-  const int pair = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (pair >= mtiles * ks) return;  // padding of the last range (no barrier reached yet)
-  const int z = pair / mtiles;
-  const int64_t m0 = (int64_t)(pair % mtiles) * GT_M;
-  const int64_t n0 = (int64_t)blockIdx.y * GT_N;
-  int64_t K = g.K, kc = g.kchunk;
-  if (extent != nullptr) {
-    // X pass: the operand is zero at positions >= max(extent[0], extent[1]); the ks chunks
-    // split that prefix (multiples of 2 GT_K; chunks past it are empty and store zeros)
-    const int64_t e = max(extent[0], extent[1]);
-    K = min(K, (e + 2 * GT_K - 1) / (2 * GT_K) * (2 * GT_K));
-    kc = ((K + ks - 1) / ks + 2 * GT_K - 1) / (2 * GT_K) * (2 * GT_K);
-  }
-  if (bump != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-    *bump += 1;
-    if (extent != nullptr) {  // statistics: extents read (units of 2 GT_K columns), passes
-      extent[2] += (int)(K / (2 * GT_K));
-      extent[3] += 1;
-    }
-  }
-  const int64_t k0 = (int64_t)z * kc;
-  const int64_t k1 = min(K, k0 + kc);
-  floatx16 acc[GT_RT][2];
-  gemm_bf16_mainloop(g, m0, n0, k0, k1, As, acc);
-  float* C = g.C + (int64_t)z * g.c_split_stride;
-  const int hi = lane >> 5;
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const int64_t node = n0 + wid * 64 + c * 32 + (lane & 31);
-#pragma unroll
-    for (int r = 0; r < GT_RT; ++r)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t m = m0 + r * 32 + 4 * hi + 8 * q;
-        float4 v;
-        v.x = acc[r][c][4 * q + 0];
-        v.y = acc[r][c][4 * q + 1];
-        v.z = acc[r][c][4 * q + 2];
-        v.w = acc[r][c][4 * q + 3];
-        *reinterpret_cast<float4*>(C + node * g.ldc + m) = v;
-      }
-  }
-}
-
-// =====================================================================================
 // dU^{t+1} = sum of the X-pass split-K partials (into the ring slot of this cycle) and the loss
 // terms f_i(u_0 + dU) summed per chunk. grid: (chunks, slots); 256 threads.
 //

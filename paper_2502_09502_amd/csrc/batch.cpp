@@ -65,8 +65,9 @@ void MixedWork::ensure(Problem& P) {
   bring.alloc(3 * Sp * 8);
   beta0.alloc(Sp * 8);
   H0.alloc(Sp * 8);
-  base0.alloc(Sn * 8);
+  base0.alloc(P.loss == LOSS_LS ? 8 : Sn * 8);
   base1.alloc(P.loss == LOSS_LS ? 8 : Sn * 8);
+  e0f.alloc(P.loss == LOSS_LS ? Sn * 4 : 8);
   bres.alloc(Sp * 8);
   dop.alloc((size_t)S_pad * ldp * 2);
   gop.alloc((size_t)S_pad * n_pad * 2);
@@ -206,6 +207,7 @@ void MixedWork::ensure(Problem& P) {
   md.H0 = H0.as<double>();
   md.base0 = base0.as<double>();
   md.base1 = base1.as<double>();
+  md.e0f = e0f.as<float>();
   md.bres = bres.as<double>();
   md.dop = dop.as<uint16_t>();
   md.gop = gop.as<uint16_t>();
@@ -540,7 +542,7 @@ bool MixedWork::cert_round(Problem& P) {
 }
 
 size_t MixedWork::device_bytes() const {
-  const DevBuf* bufs[] = {&Xb, &Xbt, &ypad, &st, &cls, &bring, &beta0, &H0, &base0, &base1,
+  const DevBuf* bufs[] = {&Xb, &Xbt, &ypad, &st, &cls, &bring, &beta0, &H0, &base0, &base1, &e0f,
                           &bres, &dop, &gop, &dU, &dUp, &dH, &lpart, &fpart, &cycle, &prevsel, &B64,
                           &U64, &R64, &H64, &cpart, &list, &H0_cold, &base0_cold, &base1_cold,
                           &Xt, &part64, &sflag, &sidx, &scount, &Bu, &G, &pinv, &pinv_new,

@@ -96,9 +96,12 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
     }
     dun[i] = du;
     if (i < md.n) {
-      const double u = md.base0[(int64_t)slot * md.n_pad + i] + (double)du;
-      if (md.loss == LOSS_LS) ls += u * u;      // base0 holds e_0 = u_0 - y
-      else ls += loss_val(md.loss, u, md.y[i]);  // base0 holds u_0
+      if (md.loss == LOSS_LS) {
+        const double e = (double)md.e0f[(int64_t)slot * md.n_pad + i] + (double)du;  // u - y
+        ls += e * e;
+      } else {
+        ls += loss_val(md.loss, md.base0[(int64_t)slot * md.n_pad + i] + (double)du, md.y[i]);
+      }
     }
   }
   ls = block_reduce(ls, red, OpAdd(), 0.0);
@@ -163,7 +166,7 @@ __global__ __launch_bounds__(256) void k_mixed_resid(MixedDev md) {
       const double dg = (double)dun[i] + c * ((double)dun[i] - (double)duo[i]);
       const double y = md.y[i];
       if (md.loss == LOSS_LS) {
-        const double e = md.base0[(int64_t)slot * md.n_pad + i] + dg;  // u_gamma - y
+        const double e = (double)md.e0f[(int64_t)slot * md.n_pad + i] + dg;  // u_gamma - y
         const double r = 2.0 * e;
         fs += 0.25 * r * r + y * r;  // F*(-zeta), zeta = -r: ||zeta||^2/4 - y.zeta
         gv = float_to_bf16((float)(2.0 * dg));
@@ -482,8 +485,12 @@ __global__ __launch_bounds__(256) void k_cert_resid(MixedDev md, const int* list
       }
     }
     R64[(int64_t)q * md.n_pad + i] = r;
-    md.base0[(int64_t)slot * md.n_pad + i] = b0;
-    if (md.loss != LOSS_LS) md.base1[(int64_t)slot * md.n_pad + i] = b1;
+    if (md.loss == LOSS_LS) {
+      md.e0f[(int64_t)slot * md.n_pad + i] = (float)b0;
+    } else {
+      md.base0[(int64_t)slot * md.n_pad + i] = b0;
+      md.base1[(int64_t)slot * md.n_pad + i] = b1;
+    }
   }
   ls = block_reduce(ls, red, OpAdd(), 0.0);
   fs = block_reduce(fs, red + 4, OpAdd(), 0.0);
@@ -626,8 +633,12 @@ __global__ __launch_bounds__(256) void k_admit(MixedDev md, const int* list, int
   }
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < md.n_pad; i += stride) {
     const int64_t o = (int64_t)slot * md.n_pad + i;
-    md.base0[o] = base0_cold[i];
-    if (md.loss != LOSS_LS) md.base1[o] = base1_cold[i];
+    if (md.loss == LOSS_LS) {
+      md.e0f[o] = (float)base0_cold[i];
+    } else {
+      md.base0[o] = base0_cold[i];
+      md.base1[o] = base1_cold[i];
+    }
     md.dU[o] = 0.f;
     md.dU[md.dU_ring + o] = 0.f;
     md.gop[frag_index(slot, i, md.S_pad >> 5)] = 0;

@@ -27,7 +27,9 @@ struct MixedDev {
   int64_t bring_stride; // S x ldp
   double* beta0;        // S x ldp base point
   double* H0;           // S x ldp: X^T grad f(X beta_0)
-  double* base0;        // S x n_pad: least squares e_0 = X beta_0 - y; logistic u_0 = X beta_0
+  double* base0;        // S x n_pad: u_0 = X beta_0 (losses other than least squares)
+  float* e0f;           // S x n_pad: least squares e_0 = X beta_0 - y, rounded to FP32 (its
+                        // rounding is the same in every cycle between re-centres)
   double* base1;        // S x n_pad: logistic r_0 = grad f(u_0)
   double* bres;         // S x ldp: best certified iterate
   uint16_t* dop;        // S_pad x ldp: bf16(beta - beta_0)

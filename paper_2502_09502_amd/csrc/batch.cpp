@@ -32,6 +32,9 @@ MixedWork::~MixedWork() {
   if (beta_host) (void)hipHostFree(beta_host);
   if (count_host) (void)hipHostFree(count_host);
   if (order_host) (void)hipHostFree(order_host);
+  if (ret_gathered) (void)hipEventDestroy(ret_gathered);
+  if (ret_copied) (void)hipEventDestroy(ret_copied);
+  if (copy_stream) (void)hipStreamDestroy(copy_stream);
 }
 
 static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -180,6 +183,10 @@ void MixedWork::ensure(Problem& P) {
   CGL_HIP(hipHostMalloc(&st_host, (size_t)S * sizeof(NodeDev), hipHostMallocDefault));
   CGL_HIP(hipHostMalloc(&beta_host, (size_t)S * P.p * sizeof(double), hipHostMallocDefault));
   CGL_HIP(hipHostMalloc(&count_host, sizeof(int), hipHostMallocDefault));
+  Bret.alloc((size_t)S * P.p * sizeof(double));
+  CGL_HIP(hipStreamCreateWithFlags(&copy_stream, hipStreamNonBlocking));
+  CGL_HIP(hipEventCreateWithFlags(&ret_gathered, hipEventDisableTiming));
+  CGL_HIP(hipEventCreateWithFlags(&ret_copied, hipEventDisableTiming));
   std::memset(st_host, 0, (size_t)S * sizeof(NodeDev));
   CGL_HIP(hipMemcpyAsync(st.ptr, st_host, (size_t)S * sizeof(NodeDev), hipMemcpyHostToDevice, s));
   cls_host.assign(Sp, CLS_PAD);
@@ -546,7 +553,7 @@ size_t MixedWork::device_bytes() const {
                           &bres, &dop, &gop, &dU, &dUp, &dH, &lpart, &fpart, &cycle, &prevsel, &B64,
                           &U64, &R64, &H64, &cpart, &list, &H0_cold, &base0_cold, &base1_cold,
                           &Xt, &part64, &sflag, &sidx, &scount, &Bu, &G, &pinv, &pinv_new,
-                          &perm, &perm_new, &keff, &dop_tmp, &pfx, &sn, &sj, &sv};
+                          &perm, &perm_new, &keff, &dop_tmp, &pfx, &sn, &sj, &sv, &Bret};
   size_t b = 0;
   for (const DevBuf* d : bufs) b += d->bytes;
   return b;
@@ -622,7 +629,8 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
 }
 
 void MixedWork::retire(Problem& P, const std::vector<int>& slots,
-                       const std::vector<cgl_result*>& res, const std::vector<double*>& beta_out) {
+                       const std::vector<cgl_result*>& res, const std::vector<double*>& beta_out,
+                       bool defer) {
   hipStream_t s = P.ctx->stream;
   std::vector<int> rows;  // slots whose iterate is wanted, in the order of their staging rows
   for (size_t i = 0; i < slots.size(); ++i) {
@@ -643,16 +651,28 @@ void MixedWork::retire(Problem& P, const std::vector<int>& slots,
     if (beta_out[i]) rows.push_back(sl);
   }
   if (!rows.empty()) {
+    flush_retired();  // the staging rows of the previous retirement are free again
     const int nq = (int)rows.size();
     CGL_HIP(hipMemcpyAsync(list.ptr, rows.data(), (size_t)nq * sizeof(int), hipMemcpyHostToDevice, s));
-    launch_gather_rows(bres.as<double>(), ldp, list.as<int>(), nq, P.p, B64.as<double>(), s);
-    CGL_HIP(hipMemcpyAsync(beta_host, B64.ptr, (size_t)nq * P.p * sizeof(double),
-                           hipMemcpyDeviceToHost, s));
-    CGL_HIP(hipStreamSynchronize(s));
-    size_t q = 0;
+    // the gather overwrites Bret: the previous deferred copy must have read it
+    if (ret_copy_recorded) CGL_HIP(hipStreamWaitEvent(s, ret_copied, 0));
+    launch_gather_rows(bres.as<double>(), ldp, list.as<int>(), nq, P.p, Bret.as<double>(), s);
+    const size_t bytes = (size_t)nq * P.p * sizeof(double);
     for (size_t i = 0; i < slots.size(); ++i)
-      if (beta_out[i])
-        std::memcpy(beta_out[i], beta_host + (q++) * P.p, (size_t)P.p * sizeof(double));
+      if (beta_out[i]) ret_pending.push_back(beta_out[i]);
+    if (defer) {
+      CGL_HIP(hipEventRecord(ret_gathered, s));
+      CGL_HIP(hipStreamWaitEvent(copy_stream, ret_gathered, 0));
+      CGL_HIP(hipMemcpyAsync(beta_host, Bret.ptr, bytes, hipMemcpyDeviceToHost, copy_stream));
+      CGL_HIP(hipEventRecord(ret_copied, copy_stream));
+      ret_copy_recorded = true;
+    } else {
+      CGL_HIP(hipMemcpyAsync(beta_host, Bret.ptr, bytes, hipMemcpyDeviceToHost, s));
+      CGL_HIP(hipStreamSynchronize(s));
+      ret_copy_recorded = false;
+    }
+    pending_p = P.p;
+    if (!defer) flush_retired();
   }
   for (int sl : slots) {
     st_host[sl].active = 0;
@@ -661,6 +681,14 @@ void MixedWork::retire(Problem& P, const std::vector<int>& slots,
 }
 
 // Upload the host image of the slot states (after retire/admit edits; the device is idle).
+void MixedWork::flush_retired() {
+  if (ret_pending.empty()) return;
+  if (ret_copy_recorded) CGL_HIP(hipEventSynchronize(ret_copied));
+  for (size_t q = 0; q < ret_pending.size(); ++q)
+    std::memcpy(ret_pending[q], beta_host + q * pending_p, (size_t)pending_p * sizeof(double));
+  ret_pending.clear();
+}
+
 void MixedWork::push_states(Problem& P) {
   CGL_HIP(hipMemcpyAsync(st.ptr, st_host, (size_t)S * sizeof(NodeDev), hipMemcpyHostToDevice,
                          P.ctx->stream));
@@ -727,7 +755,7 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
         bs.push_back(beta_out ? beta_out + (int64_t)owner * P.p : nullptr);
       }
       if (!done.empty()) {
-        W.retire(P, done, rs, bs);
+        W.retire(P, done, rs, bs, /*defer=*/true);
         finished += (int32_t)done.size();
         W.push_states(P);
         fill();
@@ -737,6 +765,7 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
     if (finished < count && W.free_slots() == W.S && next >= count) break;
   }
   CGL_HIP(hipStreamSynchronize(s));
+  W.flush_retired();
 }
 
 }  // namespace cgl

@@ -37,12 +37,17 @@ struct MixedWork {
   double f_cold = 0.0;
   DevBuf Xb, Xbt, ypad, st, cls, bring, beta0, H0, base0, base1, e0f, bres, dop, gop, dU, dUp, dH, lpart,
       fpart, cycle, prevsel, B64, U64, R64, H64, cpart, list, H0_cold, base0_cold, base1_cold, Xt, part64,
-      sflag, sidx, scount, Bu, G, pinv, pinv_new, perm, perm_new, keff, dop_tmp, pfx, sn, sj, sv;
+      sflag, sidx, scount, Bu, G, Bret, pinv, pinv_new, perm, perm_new, keff, dop_tmp, pfx, sn, sj, sv;
   int64_t ldg = 0;  // least squares: G = X^T X in FP64 (p x ldg), when built
   size_t part64_cap = 0;
   NodeDev* st_host = nullptr;
   double* beta_host = nullptr;  // pinned staging of retired iterates (S x p)
   int* count_host = nullptr;    // pinned: size of the support union of a certification round
+  hipStream_t copy_stream = nullptr;  // deferred copies of retired iterates (default priority)
+  hipEvent_t ret_gathered = nullptr, ret_copied = nullptr;
+  bool ret_copy_recorded = false;
+  std::vector<double*> ret_pending;  // callers' buffers of the staged rows, in row order
+  int64_t pending_p = 0;
   int64_t support_sum = 0;      // sum over certification rounds of the union size (statistics)
   int* order_host = nullptr;    // pinned: extent counters, support prefix, strays per slot, extent statistics
   bool reorder = true;          // CGL_NO_REORDER=1 keeps the natural coordinate order
@@ -78,9 +83,12 @@ struct MixedWork {
   void admit(Problem& P, const std::vector<Admission>& adm);
   // Results of finished slots and their best certified iterates (beta_out[i] may be null): one
   // gather of the iterates on the device, one copy to pinned host memory, then into the
-  // callers' buffers. The slots are freed.
+  // callers' buffers. The slots are freed. With defer, the copy runs on a stream of its own while
+  // the next launches proceed, and the iterates reach the callers' buffers at flush_retired()
+  // (called before the next retirement and before the solve returns).
   void retire(Problem& P, const std::vector<int>& slots, const std::vector<cgl_result*>& res,
-              const std::vector<double*>& beta_out);
+              const std::vector<double*>& beta_out, bool defer = false);
+  void flush_retired();
   void push_states(Problem& P);
   int free_slots() const;
   size_t device_bytes() const;  // device memory held by this engine

@@ -63,7 +63,7 @@ void MixedWork::ensure(Problem& P) {
   CGL_HIP(hipMemcpyAsync(ypad.ptr, P.y.ptr, (size_t)P.n * 8, hipMemcpyDeviceToDevice, s));
   // slots
   const size_t Sp = (size_t)S * ldp, Sn = (size_t)S * n_pad;
-  st.alloc((size_t)S * sizeof(NodeDev));
+  st.alloc(st_bytes());
   cls.alloc(Sp);
   bring.alloc(3 * Sp * 8);
   beta0.alloc(Sp * 8);
@@ -180,15 +180,15 @@ void MixedWork::ensure(Problem& P) {
       CGL_HIP(hipStreamSynchronize(s));  // the staging rows are released here
     }
   }
-  CGL_HIP(hipHostMalloc(&st_host, (size_t)S * sizeof(NodeDev), hipHostMallocDefault));
+  CGL_HIP(hipHostMalloc(&st_host, st_bytes(), hipHostMallocDefault));
   CGL_HIP(hipHostMalloc(&beta_host, (size_t)S * P.p * sizeof(double), hipHostMallocDefault));
   CGL_HIP(hipHostMalloc(&count_host, sizeof(int), hipHostMallocDefault));
   Bret.alloc((size_t)S * P.p * sizeof(double));
   CGL_HIP(hipStreamCreateWithFlags(&copy_stream, hipStreamNonBlocking));
   CGL_HIP(hipEventCreateWithFlags(&ret_gathered, hipEventDisableTiming));
   CGL_HIP(hipEventCreateWithFlags(&ret_copied, hipEventDisableTiming));
-  std::memset(st_host, 0, (size_t)S * sizeof(NodeDev));
-  CGL_HIP(hipMemcpyAsync(st.ptr, st_host, (size_t)S * sizeof(NodeDev), hipMemcpyHostToDevice, s));
+  std::memset(st_host, 0, st_bytes());
+  CGL_HIP(hipMemcpyAsync(st.ptr, st_host, st_bytes(), hipMemcpyHostToDevice, s));
   cls_host.assign(Sp, CLS_PAD);
   slot_owner.assign((size_t)S, -1);
   // device view
@@ -246,21 +246,21 @@ void MixedWork::ensure(Problem& P) {
     perm_new.alloc((size_t)ldp * sizeof(int));
     CGL_HIP(hipMemcpy(pinv.ptr, id.data(), (size_t)ldp * sizeof(int), hipMemcpyHostToDevice));
     CGL_HIP(hipMemcpy(perm.ptr, id.data(), (size_t)ldp * sizeof(int), hipMemcpyHostToDevice));
-    const int full[4] = {(int)ldp, (int)ldp, 0, 0};
-    keff.alloc(4 * sizeof(int));
-    CGL_HIP(hipMemcpy(keff.ptr, full, sizeof(full), hipMemcpyHostToDevice));
+    // the extent counters start at the full width (the strays per slot at zero, as the state)
+    int* tail = ctl_dev();
+    int* th = (int*)((char*)st_host + (size_t)S * sizeof(NodeDev));
+    th[kCtlExtent] = th[kCtlExtent + 1] = (int)ldp;
+    CGL_HIP(hipMemcpyAsync(tail, th, 2 * sizeof(int), hipMemcpyHostToDevice, s));  // after the zeros
     dop_tmp.alloc(dop.bytes);
-    CGL_HIP(hipHostMalloc(&order_host, (size_t)(6 + S) * sizeof(int), hipHostMallocDefault));
+    CGL_HIP(hipHostMalloc(&order_host, sizeof(int), hipHostMallocDefault));
     // no support prefix (and so no strays) until the first reorder
     pfx.alloc(sizeof(int));
     const int nopfx = (int)ldp;
     CGL_HIP(hipMemcpy(pfx.ptr, &nopfx, sizeof(int), hipMemcpyHostToDevice));
-    sn.alloc((size_t)S * sizeof(int));
-    CGL_HIP(hipMemset(sn.ptr, 0, (size_t)S * sizeof(int)));
     sj.alloc((size_t)S * kStrayCap * sizeof(int));
     sv.alloc((size_t)S * kStrayCap * sizeof(float));
     md.pfx = pfx.as<int>();
-    md.sn = sn.as<int>();
+    md.sn = tail + kCtlStrays;
     md.sj = sj.as<int>();
     md.sv = sv.as<float>();
     const char* e = std::getenv("CGL_NO_REORDER");
@@ -271,7 +271,7 @@ void MixedWork::ensure(Problem& P) {
     if (c && std::atoi(c) > 0) prefix_cap = round_up(std::atoi(c), 2 * GT_K);
     md.pinv = pinv.as<int>();
     md.perm = perm.as<int>();
-    md.keff = keff.as<int>();
+    md.keff = tail + kCtlExtent;
   }
   CGL_HIP(hipStreamSynchronize(s));
   tune_splits(P);
@@ -377,31 +377,28 @@ static bool mixed_graphs() {
 }
 
 void MixedWork::reorder_probe(Problem& P) {
+  // the counts reach the host with the chunk's state copy (the control tail of st)
   hipStream_t s = P.ctx->stream;
-  int* h = order_host;  // [0, 2): extent counters, [2]: union size, [4, 4 + S): strays per slot
   launch_perm_flags(md, sflag.as<uint8_t>(), s);
   launch_perm_build(sflag.as<uint8_t>(), P.p, ldp, perm_new.as<int>(), pinv_new.as<int>(),
-                    scount.as<int>(), s);
-  CGL_HIP(hipMemcpyAsync(h, keff.ptr, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-  CGL_HIP(hipMemcpyAsync(h + 2, scount.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
-  CGL_HIP(hipMemcpyAsync(h + 4, sn.ptr, (size_t)S * sizeof(int), hipMemcpyDeviceToHost, s));
+                    ctl_dev() + kCtlUnion, s);
 }
 
 void MixedWork::reorder_apply(Problem& P) {
   hipStream_t s = P.ctx->stream;
-  int* h = order_host;
+  const int* h = ctl_host();
   const int64_t grain = 2 * GT_K;
-  const int64_t now = round_up(std::max(h[0], h[1]), grain);
-  int64_t after = std::min(round_up(h[2], grain), ldp);
+  const int64_t now = round_up(std::max(h[kCtlExtent], h[kCtlExtent + 1]), grain);
+  int64_t after = std::min(round_up(h[kCtlUnion], grain), ldp);
   if (prefix_cap > 0) after = std::min(after, prefix_cap);
   int64_t strays = 0;
-  for (int i = 0; i < S; ++i) strays += h[4 + i];
+  for (int i = 0; i < S; ++i) strays += h[kCtlStrays + i];
   // a stray costs its slot a column of X~ every cycle (one row of X~^T read by the loss kernel);
   // a reorder rewrites X~ once (about 0.25 ms)
   const bool shorter = after <= now - std::max<int64_t>(2 * grain, now / 8);
   if (!shorter && strays <= S) return;  // the current order still serves
   CGL_HIP(hipMemcpyAsync(dop_tmp.ptr, dop.ptr, dop.bytes, hipMemcpyDeviceToDevice, s));
-  CGL_HIP(hipMemsetAsync(keff.ptr, 0, 2 * sizeof(int), s));  // the extent counters only
+  CGL_HIP(hipMemsetAsync(md.keff, 0, 2 * sizeof(int), s));  // the extent counters only
   launch_perm_operand(md, dop_tmp.as<uint16_t>(), pinv.as<int>(), pinv_new.as<int>(), s);
   launch_perm_design(Xbt.as<uint16_t>(), n_pad, perm_new.as<int>(), P.p, Xb.as<uint16_t>(), ldp,
                      s);
@@ -409,10 +406,10 @@ void MixedWork::reorder_apply(Problem& P) {
                          hipMemcpyDeviceToDevice, s));
   CGL_HIP(hipMemcpyAsync(perm.ptr, perm_new.ptr, (size_t)ldp * sizeof(int),
                          hipMemcpyDeviceToDevice, s));
-  // the union fills the prefix; later entrants behind it become strays (h[3] is rewritten only
-  // after the next chunk's synchronisation, when this copy has run)
-  h[3] = (int)after;
-  CGL_HIP(hipMemcpyAsync(pfx.ptr, h + 3, sizeof(int), hipMemcpyHostToDevice, s));
+  // the union fills the prefix; later entrants behind it become strays (the staging value is
+  // rewritten only after the next chunk's synchronisation, when this copy has run)
+  *order_host = (int)after;
+  CGL_HIP(hipMemcpyAsync(pfx.ptr, order_host, sizeof(int), hipMemcpyHostToDevice, s));
   reorders += 1;
 }
 
@@ -443,11 +440,13 @@ void MixedWork::run_chunk(Problem& P) {
   // before the next launches
   const bool probe = reorder && cycles + kChunk - reorder_checked >= kReorderEvery;
   if (probe) reorder_probe(P);
-  int* es = order_host + 4 + S;  // X-pass extent statistics of this chunk (kept when profiling)
-  CGL_HIP(hipMemcpyAsync(es, keff.as<int>() + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-  CGL_HIP(hipMemsetAsync(keff.as<int>() + 2, 0, 2 * sizeof(int), s));
-  CGL_HIP(hipMemcpyAsync(st_host, st.ptr, (size_t)S * sizeof(NodeDev), hipMemcpyDeviceToHost, s));
+  CGL_HIP(hipMemcpyAsync(st_host, st.ptr, st_bytes(), hipMemcpyDeviceToHost, s));
   CGL_HIP(hipStreamSynchronize(s));
+  // X-pass extent statistics (cumulative on the device): this chunk's share
+  const int* h = ctl_host();
+  const int es[2] = {h[kCtlExtent + 2] - ext_seen[0], h[kCtlExtent + 3] - ext_seen[1]};
+  ext_seen[0] = h[kCtlExtent + 2];
+  ext_seen[1] = h[kCtlExtent + 3];
   if (probe) {
     reorder_checked = cycles + kChunk;
     reorder_apply(P);
@@ -553,7 +552,7 @@ size_t MixedWork::device_bytes() const {
                           &bres, &dop, &gop, &dU, &dUp, &dH, &lpart, &fpart, &cycle, &prevsel, &B64,
                           &U64, &R64, &H64, &cpart, &list, &H0_cold, &base0_cold, &base1_cold,
                           &Xt, &part64, &sflag, &sidx, &scount, &Bu, &G, &pinv, &pinv_new,
-                          &perm, &perm_new, &keff, &dop_tmp, &pfx, &sn, &sj, &sv, &Bret};
+                          &perm, &perm_new, &dop_tmp, &pfx, &sj, &sv, &Bret};
   size_t b = 0;
   for (const DevBuf* d : bufs) b += d->bytes;
   return b;

@@ -37,7 +37,7 @@ struct MixedWork {
   double f_cold = 0.0;
   DevBuf Xb, Xbt, ypad, st, cls, bring, beta0, H0, base0, base1, e0f, bres, dop, gop, dU, dUp, dH, lpart,
       fpart, cycle, prevsel, B64, U64, R64, H64, cpart, list, H0_cold, base0_cold, base1_cold, Xt, part64,
-      sflag, sidx, scount, Bu, G, Bret, pinv, pinv_new, perm, perm_new, keff, dop_tmp, pfx, sn, sj, sv;
+      sflag, sidx, scount, Bu, G, Bret, pinv, pinv_new, perm, perm_new, dop_tmp, pfx, sj, sv;
   int64_t ldg = 0;  // least squares: G = X^T X in FP64 (p x ldg), when built
   size_t part64_cap = 0;
   NodeDev* st_host = nullptr;
@@ -49,7 +49,15 @@ struct MixedWork {
   std::vector<double*> ret_pending;  // callers' buffers of the staged rows, in row order
   int64_t pending_p = 0;
   int64_t support_sum = 0;      // sum over certification rounds of the union size (statistics)
-  int* order_host = nullptr;    // pinned: extent counters, support prefix, strays per slot, extent statistics
+  int* order_host = nullptr;    // pinned: staging of the support prefix
+  int ext_seen[2] = {0, 0};     // X-pass extent statistics already accounted
+  // st holds the S slot states and then a control tail of ints that every state copy to the host
+  // brings along: the X-pass extent counters and statistics, the union size of the last reorder
+  // check and the strays per slot (copies to the device write the states only)
+  static constexpr int kCtlExtent = 0, kCtlUnion = 4, kCtlStrays = 8;
+  size_t st_bytes() const { return (size_t)S * sizeof(NodeDev) + (size_t)(kCtlStrays + S) * sizeof(int); }
+  int* ctl_dev() const { return (int*)((char*)st.ptr + (size_t)S * sizeof(NodeDev)); }
+  const int* ctl_host() const { return (const int*)((const char*)st_host + (size_t)S * sizeof(NodeDev)); }
   bool reorder = true;          // CGL_NO_REORDER=1 keeps the natural coordinate order
   int64_t reorder_checked = 0;  // cycle of the last reorder check
   int64_t reorders = 0;

@@ -85,23 +85,50 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
     }
     __syncthreads();
   }
+  // four consecutive rows per thread and step (16-byte loads and stores; n_pad and the chunk
+  // bounds are multiples of 256)
   double ls = 0.0;
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
-    float du = 0.f;
-    for (int q = 0; q < md.ksx; ++q) du += md.dUp[(int64_t)q * md.dUp_split + (int64_t)slot * md.n_pad + i];
-    if (ns > 0) du += sdu[i - i0];
-    if (rebase) {
-      duo[i] -= du;
-      du = 0.f;
+  const float* dup = md.dUp + (int64_t)slot * md.n_pad;
+  for (int64_t i = i0 + 4 * (int64_t)threadIdx.x; i < i1; i += 4 * 256) {
+    float4 du = *reinterpret_cast<const float4*>(dup + i);
+    for (int q = 1; q < md.ksx; ++q) {
+      const float4 t = *reinterpret_cast<const float4*>(dup + (int64_t)q * md.dUp_split + i);
+      du.x += t.x;
+      du.y += t.y;
+      du.z += t.z;
+      du.w += t.w;
     }
-    dun[i] = du;
-    if (i < md.n) {
-      if (md.loss == LOSS_LS) {
-        const double e = (double)md.e0f[(int64_t)slot * md.n_pad + i] + (double)du;  // u - y
-        ls += e * e;
-      } else {
-        ls += loss_val(md.loss, md.base0[(int64_t)slot * md.n_pad + i] + (double)du, md.y[i]);
+    if (ns > 0) {
+      du.x += sdu[i - i0];
+      du.y += sdu[i - i0 + 1];
+      du.z += sdu[i - i0 + 2];
+      du.w += sdu[i - i0 + 3];
+    }
+    if (rebase) {
+      float4 o = *reinterpret_cast<const float4*>(duo + i);
+      o.x -= du.x;
+      o.y -= du.y;
+      o.z -= du.z;
+      o.w -= du.w;
+      *reinterpret_cast<float4*>(duo + i) = o;
+      du = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    *reinterpret_cast<float4*>(dun + i) = du;
+    const float dv[4] = {du.x, du.y, du.z, du.w};
+    if (md.loss == LOSS_LS) {
+      const float4 e4 = *reinterpret_cast<const float4*>(md.e0f + (int64_t)slot * md.n_pad + i);
+      const float ev[4] = {e4.x, e4.y, e4.z, e4.w};
+      for (int c = 0; c < 4; ++c) {
+        if (i + c < md.n) {
+          const double e = (double)ev[c] + (double)dv[c];  // u - y
+          ls += e * e;
+        }
       }
+    } else {
+      for (int c = 0; c < 4; ++c)
+        if (i + c < md.n)
+          ls += loss_val(md.loss, md.base0[(int64_t)slot * md.n_pad + i + c] + (double)dv[c],
+                         md.y[i + c]);
     }
   }
   ls = block_reduce(ls, red, OpAdd(), 0.0);
@@ -159,25 +186,43 @@ __global__ __launch_bounds__(256) void k_mixed_resid(MixedDev md) {
   const double c = cs;
   const int64_t i0 = (int64_t)blockIdx.x * md.rchunk;
   const int64_t i1 = min(md.n_pad, i0 + md.rchunk);
+  // four consecutive rows per thread and step (16-byte loads; 8-byte operand stores)
   double fs = 0.0;
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
-    uint16_t gv = 0;
-    if (i < md.n) {
-      const double dg = (double)dun[i] + c * ((double)dun[i] - (double)duo[i]);
-      const double y = md.y[i];
+  const int64_t nbk = md.S_pad >> 5;
+  for (int64_t i = i0 + 4 * (int64_t)threadIdx.x; i < i1; i += 4 * 256) {
+    const float4 n4 = *reinterpret_cast<const float4*>(dun + i);
+    const float4 o4 = *reinterpret_cast<const float4*>(duo + i);
+    const float nv[4] = {n4.x, n4.y, n4.z, n4.w}, ov[4] = {o4.x, o4.y, o4.z, o4.w};
+    float ev[4] = {0.f, 0.f, 0.f, 0.f};
+    if (md.loss == LOSS_LS) {
+      const float4 e4 = *reinterpret_cast<const float4*>(md.e0f + (int64_t)slot * md.n_pad + i);
+      ev[0] = e4.x;
+      ev[1] = e4.y;
+      ev[2] = e4.z;
+      ev[3] = e4.w;
+    }
+    uint16_t gv[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 4; ++k) {
+      if (i + k >= md.n) continue;
+      const double dg = (double)nv[k] + c * ((double)nv[k] - (double)ov[k]);
+      const double y = md.y[i + k];
       if (md.loss == LOSS_LS) {
-        const double e = (double)md.e0f[(int64_t)slot * md.n_pad + i] + dg;  // u_gamma - y
+        const double e = (double)ev[k] + dg;  // u_gamma - y
         const double r = 2.0 * e;
         fs += 0.25 * r * r + y * r;  // F*(-zeta), zeta = -r: ||zeta||^2/4 - y.zeta
-        gv = float_to_bf16((float)(2.0 * dg));
+        gv[k] = float_to_bf16((float)(2.0 * dg));
       } else {  // base0 holds u_0, base1 holds r_0 = grad f(u_0)
-        const double u = md.base0[(int64_t)slot * md.n_pad + i] + dg;
+        const double u = md.base0[(int64_t)slot * md.n_pad + i + k] + dg;
         const double r = loss_grad(md.loss, u, y);
         fs += fstar_term(md.loss, u, y);
-        gv = float_to_bf16((float)(r - md.base1[(int64_t)slot * md.n_pad + i]));
+        gv[k] = float_to_bf16((float)(r - md.base1[(int64_t)slot * md.n_pad + i + k]));
       }
     }
-    md.gop[frag_index(slot, i, md.S_pad >> 5)] = gv;
+    // rows i .. i + 3 are consecutive within one 8-row group of the fragment layout
+    uint2 w;
+    w.x = (uint32_t)gv[0] | ((uint32_t)gv[1] << 16);
+    w.y = (uint32_t)gv[2] | ((uint32_t)gv[3] << 16);
+    *reinterpret_cast<uint2*>(md.gop + frag_index(slot, i, nbk)) = w;
   }
   fs = block_reduce(fs, red, OpAdd(), 0.0);
   if (threadIdx.x == 0) md.fpart[(int64_t)slot * md.nrt + blockIdx.x] = fs;

@@ -440,6 +440,8 @@ void MixedWork::run_chunk(Problem& P) {
   // before the next launches
   const bool probe = reorder && cycles + kChunk - reorder_checked >= kReorderEvery;
   if (probe) reorder_probe(P);
+  // iterates retired before this chunk go to the callers' buffers while the chunk runs
+  flush_retired();
   CGL_HIP(hipMemcpyAsync(st_host, st.ptr, st_bytes(), hipMemcpyDeviceToHost, s));
   CGL_HIP(hipStreamSynchronize(s));
   // X-pass extent statistics (cumulative on the device): this chunk's share

@@ -32,6 +32,8 @@ MixedWork::~MixedWork() {
   if (beta_host) (void)hipHostFree(beta_host);
   if (count_host) (void)hipHostFree(count_host);
   if (order_host) (void)hipHostFree(order_host);
+  if (cls_host) (void)hipHostFree(cls_host);
+  if (list_host) (void)hipHostFree(list_host);
   if (ret_gathered) (void)hipEventDestroy(ret_gathered);
   if (ret_copied) (void)hipEventDestroy(ret_copied);
   if (copy_stream) (void)hipStreamDestroy(copy_stream);
@@ -189,7 +191,9 @@ void MixedWork::ensure(Problem& P) {
   CGL_HIP(hipEventCreateWithFlags(&ret_copied, hipEventDisableTiming));
   std::memset(st_host, 0, st_bytes());
   CGL_HIP(hipMemcpyAsync(st.ptr, st_host, st_bytes(), hipMemcpyHostToDevice, s));
-  cls_host.assign(Sp, CLS_PAD);
+  CGL_HIP(hipHostMalloc(&cls_host, Sp, hipHostMallocDefault));
+  std::memset(cls_host, CLS_PAD, Sp);
+  CGL_HIP(hipHostMalloc(&list_host, 3 * (size_t)S * sizeof(int), hipHostMallocDefault));
   slot_owner.assign((size_t)S, -1);
   // device view
   md.Xb = Xb.as<uint16_t>();
@@ -503,7 +507,7 @@ bool MixedWork::cert_round(Problem& P) {
   hipStream_t s = P.ctx->stream;
   cgl_ctx* ctx = P.ctx;
   for (int sl : want) want_since[sl] = -1;
-  CGL_HIP(hipMemcpyAsync(list.ptr, want.data(), (size_t)nq * sizeof(int), hipMemcpyHostToDevice, s));
+  upload_list(P, want, kListCert);
   hipEvent_t e0 = ctx->profiling ? ctx->event(100) : nullptr;
   hipEvent_t e1 = ctx->profiling ? ctx->event(101) : nullptr;
   // X beta in FP64 over the union of the iterates' supports (the other coordinates contribute
@@ -593,12 +597,12 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
       d.g_new = HUGE_VAL;
     }
     st_host[sl] = d;
-    std::copy(a.host.cls.begin(), a.host.cls.end(), cls_host.begin() + (int64_t)sl * ldp);
-    std::fill(cls_host.begin() + (int64_t)sl * ldp + P.p, cls_host.begin() + (int64_t)(sl + 1) * ldp,
+    std::copy(a.host.cls.begin(), a.host.cls.end(), cls_host + (int64_t)sl * ldp);
+    std::fill(cls_host + (int64_t)sl * ldp + P.p, cls_host + (int64_t)(sl + 1) * ldp,
               (uint8_t)CLS_PAD);
     admitted_at[sl] = cycles;
   }
-  CGL_HIP(hipMemcpyAsync(list.ptr, slots.data(), slots.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  upload_list(P, slots, kListAdmit);
   launch_admit(md, list.as<int>(), (int)slots.size(), H0_cold.as<double>(),
                base0_cold.as<double>(), base1_cold.as<double>(), s);
   // warm starts (fixed-zero coordinates set to 0) into the iterate ring, the base and the best
@@ -618,7 +622,18 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
     CGL_HIP(hipMemcpyAsync(bres.as<double>() + o, ws.data(), (size_t)P.p * 8,
                            hipMemcpyHostToDevice, s));
   }
-  CGL_HIP(hipMemcpyAsync(cls.ptr, cls_host.data(), cls_host.size(), hipMemcpyHostToDevice, s));
+  // the admitted slots' class rows, one copy per run of consecutive slots
+  {
+    std::vector<int> ss = slots;
+    std::sort(ss.begin(), ss.end());
+    for (size_t a = 0; a < ss.size();) {
+      size_t b = a + 1;
+      while (b < ss.size() && ss[b] == ss[b - 1] + 1) ++b;
+      const size_t off = (size_t)ss[a] * ldp, len = (b - a) * (size_t)ldp;
+      CGL_HIP(hipMemcpyAsync((uint8_t*)cls.ptr + off, cls_host + off, len, hipMemcpyHostToDevice, s));
+      a = b;
+    }
+  }
   CGL_HIP(hipMemcpyAsync(st.ptr, st_host, (size_t)S * sizeof(NodeDev), hipMemcpyHostToDevice, s));
   CGL_HIP(hipStreamSynchronize(s));
   if (reorder && (int)adm.size() >= S / 4) {
@@ -654,7 +669,7 @@ void MixedWork::retire(Problem& P, const std::vector<int>& slots,
   if (!rows.empty()) {
     flush_retired();  // the staging rows of the previous retirement are free again
     const int nq = (int)rows.size();
-    CGL_HIP(hipMemcpyAsync(list.ptr, rows.data(), (size_t)nq * sizeof(int), hipMemcpyHostToDevice, s));
+    upload_list(P, rows, kListRetire);
     // the gather overwrites Bret: the previous deferred copy must have read it
     if (ret_copy_recorded) CGL_HIP(hipStreamWaitEvent(s, ret_copied, 0));
     launch_gather_rows(bres.as<double>(), ldp, list.as<int>(), nq, P.p, Bret.as<double>(), s);
@@ -682,6 +697,13 @@ void MixedWork::retire(Problem& P, const std::vector<int>& slots,
 }
 
 // Upload the host image of the slot states (after retire/admit edits; the device is idle).
+void MixedWork::upload_list(Problem& P, const std::vector<int>& v, int region) {
+  int* h = list_host + (size_t)region * S;
+  std::copy(v.begin(), v.end(), h);
+  CGL_HIP(hipMemcpyAsync(list.ptr, h, v.size() * sizeof(int), hipMemcpyHostToDevice,
+                         P.ctx->stream));
+}
+
 void MixedWork::flush_retired() {
   if (ret_pending.empty()) return;
   if (ret_copy_recorded) CGL_HIP(hipEventSynchronize(ret_copied));

@@ -62,7 +62,12 @@ struct MixedWork {
   int64_t reorder_checked = 0;  // cycle of the last reorder check
   int64_t reorders = 0;
   int64_t prefix_cap = 0;       // CGL_PREFIX_CAP (tests): upper bound of the support prefix
-  std::vector<uint8_t> cls_host;
+  uint8_t* cls_host = nullptr;  // pinned: S x ldp node classes (rows uploaded at admission)
+  // pinned staging of slot lists, one region of S per caller (certification, retirement,
+  // admission); a region is reused only after a synchronisation that follows its copy
+  int* list_host = nullptr;
+  enum { kListCert = 0, kListRetire = 1, kListAdmit = 2 };
+  void upload_list(Problem& P, const std::vector<int>& v, int region);
   std::vector<int> slot_owner;
   int64_t admitted_at[kSlots] = {0};
   int64_t want_since[kSlots];  // cycle at which a slot's certification request was first seen

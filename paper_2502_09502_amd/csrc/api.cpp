@@ -16,10 +16,12 @@
 #include "losses.h"
 #include "prox.h"
 
+// Timing events: read only after the stream has been synchronised, so they need no system-scope
+// fence (which would write back caches at every record and delay the next kernel).
 hipEvent_t cgl_ctx::event(size_t i) {
   while (events.size() <= i) {
     hipEvent_t e;
-    CGL_HIP(hipEventCreate(&e));
+    CGL_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     events.push_back(e);
   }
   return events[i];

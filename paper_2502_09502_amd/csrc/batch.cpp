@@ -640,7 +640,7 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
     // many new supports: no prefix (no strays) until they have settled for two check intervals
     const int nopfx = (int)ldp;
     CGL_HIP(hipMemcpy(pfx.ptr, &nopfx, sizeof(int), hipMemcpyHostToDevice));
-    reorder_checked = cycles + kReorderEvery;
+    reorder_checked = cycles;
   }
 }
 

@@ -637,7 +637,7 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
   CGL_HIP(hipMemcpyAsync(st.ptr, st_host, (size_t)S * sizeof(NodeDev), hipMemcpyHostToDevice, s));
   CGL_HIP(hipStreamSynchronize(s));
   if (reorder && (int)adm.size() >= S / 4) {
-    // many new supports: no prefix (no strays) until they have settled for two check intervals
+    // many new supports: no prefix (no strays) until the next check has listed them
     const int nopfx = (int)ldp;
     CGL_HIP(hipMemcpy(pfx.ptr, &nopfx, sizeof(int), hipMemcpyHostToDevice));
     reorder_checked = cycles;

@@ -13,7 +13,7 @@ namespace cgl {
 
 constexpr int kSlots = 256;  // node slots per problem
 constexpr int kChunk = 4;    // iterations per graph launch between host checks
-constexpr int kCertBatch = 32;  // certification requests that trigger a round at once
+constexpr int kCertBatch = 16;  // certification requests that trigger a round at once
 constexpr int kCertWait = 1;    // chunks the oldest request may wait for others
 constexpr int kReorderEvery = 8;  // cycles between checks of the X-pass operand order
 constexpr int64_t kGramMaxP = 16384;  // least squares: largest p with an FP64 Gram matrix (2.1 GB)

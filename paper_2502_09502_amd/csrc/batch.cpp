@@ -47,10 +47,12 @@ void MixedWork::ensure(Problem& P) {
   std::fill(want_since, want_since + kSlots, (int64_t)-1);
   // batching of the certification rounds (tuning knobs; the defaults suit the 256-slot engine)
   for (auto [name, dst] : {std::pair<const char*, int*>{"CGL_CERT_BATCH", &cert_batch},
-                           std::pair<const char*, int*>{"CGL_CERT_WAIT", &cert_wait}}) {
+                           std::pair<const char*, int*>{"CGL_CERT_WAIT", &cert_wait},
+                           std::pair<const char*, int*>{"CGL_CHUNK", &chunk}}) {
     const char* e = std::getenv(name);
     if (e && std::atoi(e) > 0) *dst = std::atoi(e);
   }
+  chunk = std::min(chunk, 64);
   S = kSlots;
   S_pad = (int)round_up(S, 256);
   n_pad = round_up(P.n, GT_M);  // rows of X~: a multiple of the GEMM tile and of its k-chunk grain
@@ -424,7 +426,7 @@ void MixedWork::run_chunk(Problem& P) {
   // events on the stream (HIP cannot time events recorded inside a graph, so the cycles are then
   // launched one by one)
   if (ctx->profiling || !mixed_graphs()) {
-    for (int i = 0; i < kChunk; ++i) {
+    for (int i = 0; i < chunk; ++i) {
       hipEvent_t ev[4];
       for (int e = 0; e < 4; ++e) ev[e] = ctx->event((size_t)(4 * i + e));
       mixed_cycle(*this, s, ctx->profiling ? ev : nullptr, ctx->profile_x);
@@ -433,7 +435,7 @@ void MixedWork::run_chunk(Problem& P) {
     if (!graph_exec) {
       hipGraph_t graph;
       CGL_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      for (int i = 0; i < kChunk; ++i) mixed_cycle(*this, s);
+      for (int i = 0; i < chunk; ++i) mixed_cycle(*this, s);
       CGL_HIP(hipStreamEndCapture(s, &graph));
       CGL_HIP(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
       CGL_HIP(hipGraphDestroy(graph));
@@ -442,7 +444,7 @@ void MixedWork::run_chunk(Problem& P) {
   }
   // the operand order is checked with the chunk's own synchronisation and changed (if at all)
   // before the next launches
-  const bool probe = reorder && cycles + kChunk - reorder_checked >= kReorderEvery;
+  const bool probe = reorder && cycles + chunk - reorder_checked >= kReorderEvery;
   if (probe) reorder_probe(P);
   // iterates retired before this chunk go to the callers' buffers while the chunk runs
   flush_retired();
@@ -454,14 +456,14 @@ void MixedWork::run_chunk(Problem& P) {
   ext_seen[0] = h[kCtlExtent + 2];
   ext_seen[1] = h[kCtlExtent + 3];
   if (probe) {
-    reorder_checked = cycles + kChunk;
+    reorder_checked = cycles + chunk;
     reorder_apply(P);
   }
   if (ctx->profiling) {
     // mean X-pass operand extent: total = sum of the extents as fractions of ldp, count = passes
     ctx->kt_ms[9] += (double)es[0] * (2 * GT_K) / (double)ldp;
     ctx->kt_n[9] += es[1];
-    for (int i = 0; i < kChunk; ++i) {
+    for (int i = 0; i < chunk; ++i) {
       float a = 0.f, b = 0.f;
       if (ctx->profile_x) {
         CGL_HIP(hipEventElapsedTime(&a, ctx->event((size_t)(4 * i)), ctx->event((size_t)(4 * i + 1))));
@@ -473,7 +475,7 @@ void MixedWork::run_chunk(Problem& P) {
       ctx->kt_n[2] += 1;
     }
   }
-  cycles += kChunk;
+  cycles += chunk;
 }
 
 bool MixedWork::cert_round(Problem& P) {
@@ -502,7 +504,7 @@ bool MixedWork::cert_round(Problem& P) {
   const int nq = (int)want.size();
   bool parked = false;  // a warm start waiting for its base point cannot wait for others
   for (int sl : want) parked = parked || st_host[sl].need_base;
-  if (!parked && nq < cert_batch && nq < active && cycles - oldest < (int64_t)cert_wait * kChunk)
+  if (!parked && nq < cert_batch && nq < active && cycles - oldest < (int64_t)cert_wait * chunk)
     return false;
   hipStream_t s = P.ctx->stream;
   cgl_ctx* ctx = P.ctx;

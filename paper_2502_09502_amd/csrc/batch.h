@@ -75,7 +75,8 @@ struct MixedWork {
   int64_t cert_rounds = 0;
   int cert_batch = kCertBatch;  // CGL_CERT_BATCH overrides
   int cert_wait = kCertWait;    // CGL_CERT_WAIT overrides
-  hipGraphExec_t graph_exec = nullptr;  // kChunk cycles
+  int chunk = kChunk;           // CGL_CHUNK overrides (cycles per launch between host checks)
+  hipGraphExec_t graph_exec = nullptr;  // one chunk of cycles
   MixedDev md{};
 
   std::vector<int> split_cands_x, split_cands_xt;

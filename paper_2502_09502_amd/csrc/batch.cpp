@@ -706,6 +706,11 @@ void MixedWork::upload_list(Problem& P, const std::vector<int>& v, int region) {
                          P.ctx->stream));
 }
 
+void MixedWork::drop_retired() {
+  if (ret_copy_recorded) CGL_HIP(hipEventSynchronize(ret_copied));
+  ret_pending.clear();
+}
+
 void MixedWork::flush_retired() {
   if (ret_pending.empty()) return;
   if (ret_copy_recorded) CGL_HIP(hipEventSynchronize(ret_copied));
@@ -729,6 +734,8 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
   if (P.shift != 0.0)
     invalid("the eigen-perspective relaxation runs on the FP64 path (CGL_PREC_F64)");
   hipStream_t s = P.ctx->stream;
+  // a solve that failed part-way may have left staged iterates for buffers that are gone
+  W.drop_retired();
   std::vector<NodeHost> hosts;
   hosts.reserve((size_t)count);
   for (int32_t i = 0; i < count; ++i) {

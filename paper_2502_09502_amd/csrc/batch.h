@@ -103,6 +103,7 @@ struct MixedWork {
   void retire(Problem& P, const std::vector<int>& slots, const std::vector<cgl_result*>& res,
               const std::vector<double*>& beta_out, bool defer = false);
   void flush_retired();
+  void drop_retired();  // forget staged iterates (their copy is waited for first)
   void push_states(Problem& P);
   int free_slots() const;
   size_t device_bytes() const;  // device memory held by this engine

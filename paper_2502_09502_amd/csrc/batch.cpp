@@ -450,6 +450,7 @@ void MixedWork::run_chunk(Problem& P) {
   flush_retired();
   CGL_HIP(hipMemcpyAsync(st_host, st.ptr, st_bytes(), hipMemcpyDeviceToHost, s));
   CGL_HIP(hipStreamSynchronize(s));
+  close_round(P);  // a certification round queued before this chunk has finished too
   // X-pass extent statistics (cumulative on the device): this chunk's share
   const int* h = ctl_host();
   const int es[2] = {h[kCtlExtent + 2] - ext_seen[0], h[kCtlExtent + 3] - ext_seen[1]};
@@ -478,7 +479,7 @@ void MixedWork::run_chunk(Problem& P) {
   cycles += chunk;
 }
 
-bool MixedWork::cert_round(Problem& P) {
+int MixedWork::cert_round(Problem& P, bool overlap) {
   // Batch the FP64 rounds: a node that asks for certification keeps iterating until enough
   // nodes ask (cert_batch), the oldest request has waited cert_wait chunks, or every active node
   // is waiting, so each round's FP64 products are shared by more nodes.
@@ -500,12 +501,15 @@ bool MixedWork::cert_round(Problem& P) {
     oldest = std::min(oldest, want_since[sl]);
     want.push_back(sl);
   }
-  if (want.empty()) return false;
+  if (want.empty()) return kRoundNone;
   const int nq = (int)want.size();
   bool parked = false;  // a warm start waiting for its base point cannot wait for others
   for (int sl : want) parked = parked || st_host[sl].need_base;
   if (!parked && nq < cert_batch && nq < active && cycles - oldest < (int64_t)cert_wait * chunk)
-    return false;
+    return kRoundNone;
+  // left open when other nodes keep running: the next chunk is queued behind the round and its
+  // synchronisation brings the round's outcome too
+  overlap = overlap && nq < active;
   hipStream_t s = P.ctx->stream;
   cgl_ctx* ctx = P.ctx;
   for (int sl : want) want_since[sl] = -1;
@@ -541,18 +545,27 @@ bool MixedWork::cert_round(Problem& P) {
                     ldp, part64.as<double>(), part64_cap, s);
   launch_cert_finish(md, list.as<int>(), nq, B64.as<double>(), H64.as<double>(),
                      cpart.as<double>(), ncchunk, s);
+  round_open = true;
+  if (overlap) return kRoundOpen;
   CGL_HIP(hipMemcpyAsync(st_host, st.ptr, (size_t)S * sizeof(NodeDev), hipMemcpyDeviceToHost, s));
   CGL_HIP(hipStreamSynchronize(s));
+  close_round(P);
+  return kRoundDone;
+}
+
+void MixedWork::close_round(Problem& P) {
+  if (!round_open) return;
+  round_open = false;
   if (*count_host < 0 || *count_host > P.p) throw std::runtime_error("support union out of range");
   support_sum += *count_host;
-  if (e0) {
+  cgl_ctx* ctx = P.ctx;
+  if (ctx->profiling) {
     float a = 0.f;
-    CGL_HIP(hipEventElapsedTime(&a, e0, e1));
+    CGL_HIP(hipEventElapsedTime(&a, ctx->event(100), ctx->event(101)));
     ctx->kt_ms[4] += a;
     ctx->kt_n[4] += 1;
   }
   cert_rounds += 1;
-  return true;
 }
 
 size_t MixedWork::device_bytes() const {
@@ -772,9 +785,13 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
     ctx->kt_n[which] += 1;
   };
   phase(7, [&] { fill(); });
+  phase(5, [&] { W.run_chunk(P); });
   while (finished < count) {
-    phase(5, [&] { W.run_chunk(P); });
-    phase(6, [&] { W.cert_round(P); });
+    // a round left open runs ahead of the next chunk and shares its synchronisation; a closed
+    // round (no other node running, or none) is followed by the retirements first
+    int round = MixedWork::kRoundNone;
+    phase(6, [&] { round = W.cert_round(P, /*overlap=*/true); });
+    if (round == MixedWork::kRoundOpen) phase(5, [&] { W.run_chunk(P); });
     phase(7, [&] {
       std::vector<int> done;
       std::vector<cgl_result*> rs;
@@ -795,6 +812,7 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
     });
     // a run with nothing active and work pending would spin: guard
     if (finished < count && W.free_slots() == W.S && next >= count) break;
+    if (finished < count && round != MixedWork::kRoundOpen) phase(5, [&] { W.run_chunk(P); });
   }
   CGL_HIP(hipStreamSynchronize(s));
   W.flush_retired();

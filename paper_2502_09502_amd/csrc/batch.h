@@ -86,7 +86,13 @@ struct MixedWork {
   void tune_splits(Problem& P);
   void ensure(Problem& P);
   void run_chunk(Problem& P);
-  bool cert_round(Problem& P);
+  // Certification round for the nodes that asked (see the batching rule in the source). With
+  // overlap, a round that leaves other nodes running is only queued (kRoundOpen): the next
+  // run_chunk's synchronisation brings its outcome and closes it.
+  enum { kRoundNone = 0, kRoundDone = 1, kRoundOpen = 2 };
+  int cert_round(Problem& P, bool overlap = false);
+  void close_round(Problem& P);
+  bool round_open = false;
   // X-pass operand order. The probe (queued at the end of a chunk) lists the coordinates where a
   // running slot's recent iterates, base point or operand are nonzero and stages the extent and
   // stray counts for the host; after the chunk's synchronisation, apply puts those coordinates

@@ -806,7 +806,8 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
       if (!done.empty()) {
         W.retire(P, done, rs, bs, /*defer=*/true);
         finished += (int32_t)done.size();
-        W.push_states(P);
+        // the device states of the retired slots need no update: they are done and do not run,
+        // and an admission into the slot writes its state
         fill();
       }
     });

@@ -48,7 +48,8 @@ void MixedWork::ensure(Problem& P) {
   // batching of the certification rounds (tuning knobs; the defaults suit the 256-slot engine)
   for (auto [name, dst] : {std::pair<const char*, int*>{"CGL_CERT_BATCH", &cert_batch},
                            std::pair<const char*, int*>{"CGL_CERT_WAIT", &cert_wait},
-                           std::pair<const char*, int*>{"CGL_CHUNK", &chunk}}) {
+                           std::pair<const char*, int*>{"CGL_CHUNK", &chunk},
+                           std::pair<const char*, int*>{"CGL_REORDER_EVERY", &reorder_every}}) {
     const char* e = std::getenv(name);
     if (e && std::atoi(e) > 0) *dst = std::atoi(e);
   }
@@ -444,7 +445,7 @@ void MixedWork::run_chunk(Problem& P) {
   }
   // the operand order is checked with the chunk's own synchronisation and changed (if at all)
   // before the next launches
-  const bool probe = reorder && cycles + chunk - reorder_checked >= kReorderEvery;
+  const bool probe = reorder && cycles + chunk - reorder_checked >= reorder_every;
   if (probe) reorder_probe(P);
   // iterates retired before this chunk go to the callers' buffers while the chunk runs
   flush_retired();

@@ -76,6 +76,7 @@ struct MixedWork {
   int cert_batch = kCertBatch;  // CGL_CERT_BATCH overrides
   int cert_wait = kCertWait;    // CGL_CERT_WAIT overrides
   int chunk = kChunk;           // CGL_CHUNK overrides (cycles per launch between host checks)
+  int reorder_every = kReorderEvery;  // CGL_REORDER_EVERY overrides
   hipGraphExec_t graph_exec = nullptr;  // one chunk of cycles
   MixedDev md{};
 

@@ -781,6 +781,9 @@ void launch_perm_build(uint8_t* flag, int64_t p, int64_t ldp, int* perm, int* pi
 __global__ __launch_bounds__(256) void k_perm_operand(MixedDev md, const uint16_t* dop_old,
                                                       const int* pinv_old, const int* pinv_new) {
   const int slot = blockIdx.y;
+  // a slot that does not run keeps its operand where it is: it is zero (done, parked, free) or,
+  // for a slot at its iteration cap, never read again
+  if (!slot_running(md.st + slot)) return;
   const int64_t nbk = md.S_pad >> 5;
   int ext = 0;
   for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < md.p; j += (int64_t)gridDim.x * 256) {

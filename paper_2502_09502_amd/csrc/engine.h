@@ -19,7 +19,6 @@ struct cgl_ctx {
   bool own_stream = false;
   // kernel timing (cgl_ctx_set_profiling)
   bool profiling = false;
-  bool profile_x = false;  // the batched engine also brackets its X pass (level 2)
   double kt_ms[16] = {0};
   int64_t kt_n[16] = {0};
   std::vector<hipEvent_t> events;  // pool, grown on demand

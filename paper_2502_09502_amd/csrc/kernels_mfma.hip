@@ -20,6 +20,8 @@
 
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include "kernels.h"
 #include "gemm_bf16.h"
@@ -935,7 +937,7 @@ void launch_make_bf16(int xtype, const void* X, int64_t ldx, int64_t n, int64_t 
     hipLaunchKernelGGL(k_make_bf16<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)X, ldx, n, p, n_pad, ldp, Xb, Xbt);
 }
 
-void launch_gemm_x(const MixedDev& md, hipStream_t s, bool advance) {
+void launch_gemm_x(const MixedDev& md, hipStream_t s, bool advance, hipEvent_t e0, hipEvent_t e1) {
   GemmArgs g;
   g.A = md.Xb;
   g.lda = md.ldp;
@@ -949,11 +951,15 @@ void launch_gemm_x(const MixedDev& md, hipStream_t s, bool advance) {
   g.c_split_stride = md.dUp_split;
   const int mt = (int)(md.n_pad / GT_M), per = (mt * md.ksx + 7) / 8;
   dim3 grid((unsigned)(8 * per), (unsigned)(md.S_pad / GT_N));
-  hipLaunchKernelGGL(k_gemm_bf16<0>, grid, dim3(256), 0, s, g, mt, md.ksx, per,
-                     advance ? md.cycle : nullptr, md.keff);
+  int* bump = advance ? md.cycle : nullptr;
+  if (e0 != nullptr)  // the launch itself records its start and end (no separate event packets)
+    hipExtLaunchKernelGGL(k_gemm_bf16<0>, grid, dim3(256), 0, s, e0, e1, 0, g, mt, md.ksx, per,
+                          bump, md.keff);
+  else
+    hipLaunchKernelGGL(k_gemm_bf16<0>, grid, dim3(256), 0, s, g, mt, md.ksx, per, bump, md.keff);
 }
 
-void launch_gemm_xt(const MixedDev& md, hipStream_t s) {
+void launch_gemm_xt(const MixedDev& md, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   GemmArgs g;
   g.A = md.Xbt;
   g.lda = md.n_pad;
@@ -967,8 +973,12 @@ void launch_gemm_xt(const MixedDev& md, hipStream_t s) {
   g.c_split_stride = md.dH_split;
   const int mt = (int)(md.ldp / GT_M), per = (mt * md.ksplit + 7) / 8;
   dim3 grid((unsigned)(8 * per), (unsigned)(md.S_pad / GT_N));
-  hipLaunchKernelGGL(k_gemm_bf16<1>, grid, dim3(256), 0, s, g, mt, md.ksplit, per, nullptr,
-                     nullptr);
+  int* none = nullptr;
+  if (e0 != nullptr)
+    hipExtLaunchKernelGGL(k_gemm_bf16<1>, grid, dim3(256), 0, s, e0, e1, 0, g, mt, md.ksplit, per,
+                          none, none);
+  else
+    hipLaunchKernelGGL(k_gemm_bf16<1>, grid, dim3(256), 0, s, g, mt, md.ksplit, per, none, none);
 }
 
 void launch_mixed_loss(const MixedDev& md, hipStream_t s) {

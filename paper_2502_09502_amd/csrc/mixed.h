@@ -73,9 +73,12 @@ constexpr int kLossChunk = 2048;  // rows per block of the loss and residual ker
 
 void launch_make_bf16(int xtype, const void* X, int64_t ldx, int64_t n, int64_t p, int64_t n_pad,
                       int64_t ldp, uint16_t* Xb, uint16_t* Xbt, hipStream_t s);
-// advance: the launch also advances the cycle counter (the first launch of a cycle)
-void launch_gemm_x(const MixedDev& md, hipStream_t s, bool advance = false);
-void launch_gemm_xt(const MixedDev& md, hipStream_t s);
+// advance: the launch also advances the cycle counter (the first launch of a cycle). e0, e1
+// (optional): events that the launch itself updates with the kernel's start and end.
+void launch_gemm_x(const MixedDev& md, hipStream_t s, bool advance = false,
+                   hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_gemm_xt(const MixedDev& md, hipStream_t s, hipEvent_t e0 = nullptr,
+                    hipEvent_t e1 = nullptr);
 void launch_mixed_loss(const MixedDev& md, hipStream_t s);
 void launch_mixed_resid(const MixedDev& md, hipStream_t s);
 void launch_mixed_node(const MixedDev& md, hipStream_t s);

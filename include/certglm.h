@@ -129,11 +129,12 @@ const char* cgl_last_error(void);
 int cgl_ctx_create(int device, void* hip_stream, cgl_ctx** out);
 int cgl_ctx_destroy(cgl_ctx* ctx);
 
-/* Kernel timing (measurement support). While on (on = 1; 2 is accepted and means the same),
- * solves on this context time every launch of the listed kernels with HIP events on the
- * context's stream (both paths then launch without graph capture; the batched products are
- * launched with their start and stop events attached, the other kernels are bracketed) and
- * accumulate the elapsed time of launches that did work. CGL_E_INVAL for another value of on.
+/* Kernel timing (measurement support). While on (on = 1 or 2), solves on this context time
+ * every launch of the listed kernels with HIP events on the context's stream (both paths then
+ * launch without graph capture; the batched products are launched with their start and stop
+ * events attached, the other kernels are bracketed) and accumulate the elapsed time of launches
+ * that did work. The batched X pass (which = 3) is timed only at on = 2: a timed launch starts
+ * a few microseconds later. CGL_E_INVAL for another value of on.
  * which: 0 = X^T pass of the plain path (k_xt), 1 = X pass of the plain path (k_xb),
  *        2 = batched BF16 MFMA X^T pass, 3 = batched BF16 MFMA X pass, 4 = batched FP64 pass;
  *        and host wall time of the batched engine's phases (launch to completion):

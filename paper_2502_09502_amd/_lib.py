@@ -120,8 +120,9 @@ class Context:
             self.lib.cgl_ctx_destroy(self.h)
             self.h = C.c_void_p()
 
-    def set_profiling(self, on: bool):
-        check(self.lib.cgl_ctx_set_profiling(self.h, 1 if on else 0))
+    def set_profiling(self, on: bool, x_pass: bool = False):
+        """Kernel timing on or off; x_pass also times the batched X pass (level 2)."""
+        check(self.lib.cgl_ctx_set_profiling(self.h, (2 if x_pass else 1) if on else 0))
 
     def kernel_stats(self, which: int, reset: bool = False):
         """(total milliseconds, launches) of one timed kernel (see cgl_ctx_kernel_stats)."""

@@ -437,6 +437,7 @@ int cgl_ctx_set_profiling(cgl_ctx* ctx, int32_t on) {
   if (!ctx) invalid("ctx is NULL");
   if (on < 0 || on > 2) invalid("profiling level must be 0, 1 or 2");
   ctx->profiling = on != 0;
+  ctx->profile_x = on == 2;
   return CGL_OK;
   CGL_API_END
 }

@@ -19,6 +19,7 @@ struct cgl_ctx {
   bool own_stream = false;
   // kernel timing (cgl_ctx_set_profiling)
   bool profiling = false;
+  bool profile_x = false;  // level 2: the batched X pass is timed too
   double kt_ms[16] = {0};
   int64_t kt_n[16] = {0};
   std::vector<hipEvent_t> events;  // pool, grown on demand

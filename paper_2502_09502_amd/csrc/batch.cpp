@@ -53,7 +53,7 @@ void MixedWork::ensure(Problem& P) {
     const char* e = std::getenv(name);
     if (e && std::atoi(e) > 0) *dst = std::atoi(e);
   }
-  chunk = std::min(chunk, 64);
+  chunk = std::min(chunk, 16);  // its timing events (4 per cycle) stay below those of the FP64 rounds
   S = kSlots;
   S_pad = (int)round_up(S, 256);
   n_pad = round_up(P.n, GT_M);  // rows of X~: a multiple of the GEMM tile and of its k-chunk grain

@@ -651,10 +651,10 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
   CGL_HIP(hipMemcpyAsync(st.ptr, st_host, (size_t)S * sizeof(NodeDev), hipMemcpyHostToDevice, s));
   CGL_HIP(hipStreamSynchronize(s));
   if (reorder && (int)adm.size() >= S / 4) {
-    // many new supports: no prefix (no strays) until the next check has listed them
+    // many new supports: no prefix (no strays) until a check half an interval later lists them
     const int nopfx = (int)ldp;
     CGL_HIP(hipMemcpy(pfx.ptr, &nopfx, sizeof(int), hipMemcpyHostToDevice));
-    reorder_checked = cycles;
+    reorder_checked = cycles - kReorderEvery / 2;
   }
 }
 

@@ -279,8 +279,27 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
     pv.set(s, h);
     cb |= (uint64_t)cs << (2 * s);
   }
-  // split-K partials slab by slab, each a loop of independent loads (same summation order)
-  for (int q = 0; q < md.ksplit; ++q) {
+  // split-K partials two slabs at a time while the registers allow it (E <= 12): both slabs'
+  // loads are in flight together, and each value still takes the slabs in order (same
+  // summation order as one slab at a time)
+  int q = 0;
+  for (; E <= 12 && q + 2 <= md.ksplit; q += 2) {
+    const float* dq0 = md.dH + (int64_t)q * md.dH_split + (int64_t)slot * md.ldp;
+    const float* dq1 = dq0 + md.dH_split;
+    float a0[E], a1[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
+      a0[s] = j < p ? dq0[j] : 0.f;
+      a1[s] = j < p ? dq1[j] : 0.f;
+    }
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
+      if (j < p) pv.set(s, (pv.get(s) + (double)a0[s]) + (double)a1[s]);
+    }
+  }
+  for (; q < md.ksplit; ++q) {
     const float* dq = md.dH + (int64_t)q * md.dH_split + (int64_t)slot * md.ldp;
 #pragma unroll
     for (int s = 0; s < E; ++s) {

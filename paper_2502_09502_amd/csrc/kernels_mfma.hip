@@ -1017,6 +1017,7 @@ void launch_mixed_resid(const MixedDev& md, hipStream_t s) {
     case 4: { constexpr int EE = 4; CALL; break; }   \
     case 6: { constexpr int EE = 6; CALL; break; }   \
     case 8: { constexpr int EE = 8; CALL; break; }   \
+    case 10: { constexpr int EE = 10; CALL; break; } \
     case 12: { constexpr int EE = 12; CALL; break; } \
     case 16: { constexpr int EE = 16; CALL; break; } \
     case 24: { constexpr int EE = 24; CALL; break; } \

@@ -26,7 +26,7 @@ def _check(W, rho, M, k, sets=None, atol=1e-11):
         assert abs(g[i] - gref) <= 1e-10 * max(1.0, abs(gref)), (i, g[i], gref)
 
 
-@pytest.mark.parametrize("p", [1, 2, 7, 64, 1000, 1024, 1025, 3000, 5000, 10000, 20000])
+@pytest.mark.parametrize("p", [1, 2, 7, 64, 1000, 1024, 1025, 3000, 5000, 8193, 10000, 10240, 20000])
 @pytest.mark.parametrize("k", [1, 5, 10, 40])
 def test_prox_random(p, k):
     rng = np.random.default_rng(p * 100 + k)

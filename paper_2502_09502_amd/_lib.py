@@ -245,10 +245,20 @@ class Problem:
         check(self.lib.cgl_solve_node(self.h, C.byref(spec.c), _dptr(beta), C.byref(r)))
         return _result(r, beta)
 
-    def solve_batch(self, specs: list[NodeSpec]) -> list[Result]:
+    def solve_batch(self, specs: list[NodeSpec], out=None) -> list[Result]:
+        """Solves the nodes together. out: optional C-contiguous float64 array (len(specs), p)
+        that receives the solutions (a caller's persistent buffer); the results' beta arrays are
+        its rows."""
         arr = (CglNode * len(specs))(*[s.c for s in specs])
         res = (CglResult * len(specs))()
-        betas = np.empty((len(specs), self.p))
+        if out is None:
+            betas = np.empty((len(specs), self.p))
+        else:
+            betas = out
+            if (betas.dtype != np.float64 or betas.shape != (len(specs), self.p)
+                    or not betas.flags.c_contiguous or not betas.flags.writeable):
+                raise ValueError(f"out must be a writeable C-contiguous float64 array of shape "
+                                 f"{(len(specs), self.p)}")
         check(self.lib.cgl_solve_batch(self.h, arr, len(specs), _dptr(betas), res))
         return [_result(res[i], betas[i]) for i in range(len(specs))]
 

@@ -203,6 +203,29 @@ def test_same_inputs_same_bits():
         assert np.array_equal(x.beta, y.beta)
 
 
+def test_caller_output_buffer():
+    """solve_batch into a caller's persistent buffer: the same bits as into fresh ones, on two
+    calls in a row, the second overwriting the first; wrong buffers are refused. (An engine keeps
+    its column order from one call to the next, which moves the rounding, so the comparison is
+    between two engines with the same history.)"""
+    d = synth.make_dataset(500, 300, 6, config_id=89)
+    sets = synth.node_sets(d.p, d.k, 12, 15, config_id=89)
+    a = _problem(d)
+    prob = _problem(d)
+    out = np.full((len(sets), d.p), np.nan)
+    for _ in range(2):
+        ref = a.solve_batch(_specs(a, sets))
+        res = prob.solve_batch(_specs(prob, sets), out=out)
+        for i, (x, y) in enumerate(zip(ref, res)):
+            assert (x.primal, x.lower_bound, x.iters) == (y.primal, y.lower_bound, y.iters)
+            assert np.array_equal(x.beta, out[i]) and np.shares_memory(y.beta, out)
+        out[:] = np.nan
+    for bad in (np.zeros((len(sets), d.p), dtype=np.float32), np.zeros((len(sets) + 1, d.p)),
+                np.zeros((d.p, len(sets))).T):
+        with pytest.raises(ValueError):
+            prob.solve_batch(_specs(prob, sets), out=bad)
+
+
 def test_wide_least_squares_mixed():
     """p > n: no Gram matrix; the certificate comes from the FP64 product with X^T."""
     d = synth.make_dataset(120, 300, 5, config_id=86)

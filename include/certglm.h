@@ -160,9 +160,11 @@ int cgl_ctx_kernel_stats(cgl_ctx* ctx, int32_t which, int32_t reset, double* tot
  *            / 4 for logistic, then enlarged by a safety factor of 1.002); Poisson and Gamma
  *            have no global constant and need L > 0.
  * The library copies X (in its stored precision, plus a transposed BF16 copy for the mixed
- * path) and y into device memory it owns. Errors: CGL_E_INVAL (n, p < 1; p > 32768; ldx < p;
- * lambda2 <= 0; M <= 0; k < 1; non-finite y; y outside the loss's range; L <= 0 for Poisson
- * or Gamma), CGL_E_NOMEM. */
+ * path) and y into device memory it owns. The values of the arguments (host X and y included)
+ * are checked before ctx, so that a NULL ctx with a bad argument reports the argument. Errors: CGL_E_INVAL (n, p < 1; p > 32768; ldx < p;
+ * lambda2 <= 0; M <= 0; k < 1; a non-finite entry of X (NaN or infinity in any dtype, checked
+ * on the device copy whether X was given in host or in device memory); non-finite y; y outside
+ * the loss's range; L <= 0 for Poisson or Gamma), CGL_E_NOMEM. */
 int cgl_problem_create(cgl_ctx* ctx, const void* X, int32_t x_dtype, int32_t x_mem, int64_t n,
                        int64_t p, int64_t ldx, const double* y, int32_t loss, double lambda2,
                        double M, int32_t k, double L, cgl_problem** out);
@@ -181,6 +183,12 @@ int cgl_problem_lipschitz(const cgl_problem* prob, double* L);
  * solves and cgl_certify reject a shifted problem; shift = 0 restores the perspective one. */
 int cgl_problem_set_eigen(cgl_problem* prob, double shift);
 
+/* Check a node against a problem's p and k on the host (no device work): the rules of
+ * cgl_node above, tol >= 0, max_iter >= 1, check_every >= 1, a known precision, a finite warm
+ * start (p doubles) and a non-NaN incumbent. CGL_OK or CGL_E_INVAL with the reason;
+ * *infeasible (nullable) receives 1 when |Z1| > k (a valid node whose bound is +inf). */
+int cgl_node_validate(const cgl_node* node, int64_t p, int32_t k, int32_t* infeasible);
+
 /* ------------------------------------------------------------------ solves */
 
 /* Solve one node relaxation (blocking). beta_out: NULL or p host doubles (the best-primal
@@ -193,6 +201,15 @@ int cgl_solve_node(cgl_problem* prob, const cgl_node* node, double* beta_out, cg
  * equals the cgl_solve_node result of the same node within the tolerances. */
 int cgl_solve_batch(cgl_problem* prob, const cgl_node* nodes, int32_t count, double* beta_out,
                     cgl_result* res);
+
+/* cgl_solve_batch that also returns each bound's witness. For a node with CGL_PREC_MIXED, row i
+ * of dual_beta_out (count x p host doubles, required) receives the iterate beta_D whose dual
+ * point zeta = -grad f(X beta_D) gave res[i].lower_bound = D(zeta) (Sec. 3.4, evaluated in
+ * FP64), so that a caller can re-evaluate the bound on its own. The rows of other nodes are set
+ * to NaN: the F64 path takes its bound at the momentum point of Alg. 3, and infeasible nodes
+ * have none. */
+int cgl_solve_batch_dual(cgl_problem* prob, const cgl_node* nodes, int32_t count,
+                         double* beta_out, cgl_result* res, double* dual_beta_out);
 
 /* ------------------------------------------------------------------ certification utilities */
 
@@ -228,9 +245,12 @@ int cgl_server_create(cgl_ctx* ctx, size_t hbm_budget_bytes, int32_t max_slots,
 int cgl_server_submit(cgl_server* srv, cgl_problem* prob, const cgl_node* node,
                       uint64_t* ticket);
 /* Advance the device work by one scheduling round (admit, run one chunk per active problem,
- * retire), then return up to max finished results: tickets[i], res[i], and, if betas is not
- * NULL, betas[i * p_i ...] for each (the caller sizes betas for its largest p). got receives the
- * count. latency_s (nullable) receives submit-to-completion wall seconds per result. */
+ * retire), then return up to max finished results in completion order: tickets[i], res[i],
+ * and, if betas is not NULL, the p_i doubles of result i's solution at betas + i * betas_stride
+ * (the rest of that row is left as it was). A result whose p exceeds betas_stride stays queued:
+ * the call returns the results before it (CGL_E_INVAL, with nothing taken, when it is the first
+ * one). got receives the count. latency_s (nullable) receives submit-to-completion wall seconds
+ * per result. */
 int cgl_server_poll(cgl_server* srv, int32_t max, uint64_t* tickets, cgl_result* res,
                     double* betas, int64_t betas_stride, double* latency_s, int32_t* got);
 /* Cancel a queued or running request; it is returned by poll with status CGL_CANCELLED. */

@@ -24,7 +24,8 @@ STATUS = {0: "converged", 1: "not_converged", 2: "infeasible", 3: "numeric", 4: 
 EXPORTS = [
     "cgl_version", "cgl_status_str", "cgl_last_error", "cgl_node_init", "cgl_ctx_create",
     "cgl_ctx_destroy", "cgl_ctx_set_profiling", "cgl_ctx_kernel_stats", "cgl_problem_create", "cgl_problem_destroy", "cgl_problem_lipschitz",
-    "cgl_solve_node", "cgl_solve_batch", "cgl_certify", "cgl_problem_matvec",
+    "cgl_node_validate", "cgl_solve_node", "cgl_solve_batch", "cgl_solve_batch_dual",
+    "cgl_certify", "cgl_problem_matvec",
     "cgl_prox_node_batch", "cgl_problem_set_eigen", "cgl_server_create", "cgl_server_submit", "cgl_server_poll",
     "cgl_server_cancel", "cgl_server_stats", "cgl_server_destroy",
 ]
@@ -83,6 +84,9 @@ def load(path: str = LIB_PATH):
     lib.cgl_problem_lipschitz.argtypes = [P, pd]
     lib.cgl_solve_node.argtypes = [P, C.POINTER(CglNode), pd, C.POINTER(CglResult)]
     lib.cgl_solve_batch.argtypes = [P, C.POINTER(CglNode), i32, pd, C.POINTER(CglResult)]
+    lib.cgl_solve_batch_dual.argtypes = [P, C.POINTER(CglNode), i32, pd, C.POINTER(CglResult),
+                                         pd]
+    lib.cgl_node_validate.argtypes = [C.POINTER(CglNode), i64, i32, C.POINTER(i32)]
     lib.cgl_certify.argtypes = [P, C.POINTER(CglNode), pd, pd, pd]
     lib.cgl_problem_matvec.argtypes = [P, i32, pd, pd]
     lib.cgl_prox_node_batch.argtypes = [P, dbl, dbl, i32, C.POINTER(CglNode), pd, i32, i64, pd, pd]
@@ -262,6 +266,18 @@ class Problem:
         check(self.lib.cgl_solve_batch(self.h, arr, len(specs), _dptr(betas), res))
         return [_result(res[i], betas[i]) for i in range(len(specs))]
 
+    def solve_batch_dual(self, specs: list[NodeSpec]):
+        """solve_batch plus each bound's witness: returns (results, dual_betas), where row i of
+        dual_betas is the iterate whose dual point -grad f(X beta) gave results[i].lower_bound
+        (NaN rows for nodes that are not on the batched engine)."""
+        arr = (CglNode * len(specs))(*[s.c for s in specs])
+        res = (CglResult * len(specs))()
+        betas = np.empty((len(specs), self.p))
+        duals = np.empty((len(specs), self.p))
+        check(self.lib.cgl_solve_batch_dual(self.h, arr, len(specs), _dptr(betas), res,
+                                            _dptr(duals)))
+        return [_result(res[i], betas[i]) for i in range(len(specs))], duals
+
     def certify(self, beta, Z0=(), Z1=()):
         spec = NodeSpec(self.p, Z0=Z0, Z1=Z1)
         b = np.ascontiguousarray(beta, dtype=np.float64)
@@ -274,6 +290,14 @@ class Problem:
         out = np.empty(self.p if trans else self.n)
         check(self.lib.cgl_problem_matvec(self.h, 1 if trans else 0, _dptr(v), _dptr(out)))
         return out
+
+
+def node_validate(spec: NodeSpec, p: int, k: int) -> bool:
+    """Host-side check of a node against (p, k) (cgl_node_validate; no device needed). Raises
+    CglError for an invalid node; returns True when the node is infeasible (|Z1| > k)."""
+    inf = C.c_int32()
+    check(load().cgl_node_validate(C.byref(spec.c), int(p), int(k), C.byref(inf)))
+    return bool(inf.value)
 
 
 def prox_node_batch(ctx: Context, W, rho, M, k, sets=None):

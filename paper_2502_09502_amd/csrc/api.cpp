@@ -142,6 +142,26 @@ void infeasible_result(cgl_result* r, double* beta_out, int64_t p) {
 
 // ------------------------------------------------------------------ problem setup
 
+// Non-finite entries of a host X (n x p, leading dimension ldx): NaN or infinity; for BF16 the
+// exponent bits all set.
+static int64_t count_nonfinite_host(const void* X, int32_t x_dtype, int64_t n, int64_t p,
+                                    int64_t ldx) {
+  int64_t bad = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (x_dtype == CGL_F64) {
+      const double* r = static_cast<const double*>(X) + i * ldx;
+      for (int64_t j = 0; j < p; ++j) bad += std::isfinite(r[j]) ? 0 : 1;
+    } else if (x_dtype == CGL_F32) {
+      const float* r = static_cast<const float*>(X) + i * ldx;
+      for (int64_t j = 0; j < p; ++j) bad += std::isfinite(r[j]) ? 0 : 1;
+    } else {
+      const uint16_t* r = static_cast<const uint16_t*>(X) + i * ldx;
+      for (int64_t j = 0; j < p; ++j) bad += (r[j] & 0x7f80u) == 0x7f80u ? 1 : 0;
+    }
+  }
+  return bad;
+}
+
 static void upload_X(Problem& P, const void* X, int32_t x_mem, int64_t ldx) {
   const size_t es = P.xtype == XT_F64 ? 8 : (P.xtype == XT_F32 ? 4 : 2);
   P.X.alloc((size_t)P.n * P.ldx * es);
@@ -457,13 +477,24 @@ int cgl_ctx_kernel_stats(cgl_ctx* ctx, int32_t which, int32_t reset, double* tot
   CGL_API_END
 }
 
+int cgl_node_validate(const cgl_node* node, int64_t p, int32_t k, int32_t* infeasible) {
+  CGL_API_BEGIN
+  if (!node) invalid("node is NULL");
+  if (p < 1 || k < 1) invalid("p and k must be >= 1");
+  const NodeHost h = make_node_host(*node, p, k);
+  if (infeasible) *infeasible = h.infeasible ? 1 : 0;
+  return CGL_OK;
+  CGL_API_END
+}
+
 int cgl_problem_create(cgl_ctx* ctx, const void* X, int32_t x_dtype, int32_t x_mem, int64_t n,
                        int64_t p, int64_t ldx, const double* y, int32_t loss, double lambda2,
                        double M, int32_t k, double L, cgl_problem** out) {
   CGL_API_BEGIN
+  // the arguments' values are checked before the context, so that these checks run (and can be
+  // tested) without a device
   if (!out) invalid("out is NULL");
   *out = nullptr;
-  if (!ctx) invalid("ctx is NULL");
   if (!X || !y) invalid("X or y is NULL");
   if (n < 1 || p < 1) invalid("n and p must be >= 1");
   if (p > 32768) invalid("p > 32768 is not supported by this build");
@@ -483,6 +514,11 @@ int cgl_problem_create(cgl_ctx* ctx, const void* X, int32_t x_dtype, int32_t x_m
     if (loss == CGL_LOSS_POISSON && y[i] < 0.0) invalid("Poisson responses must be >= 0");
     if (loss == CGL_LOSS_GAMMA && !(y[i] > 0.0)) invalid("Gamma responses must be > 0");
   }
+  if (x_mem == CGL_MEM_HOST) {
+    const int64_t nbad = count_nonfinite_host(X, x_dtype, n, p, ldx);
+    if (nbad > 0) invalid("X has " + std::to_string(nbad) + " non-finite entries");
+  }
+  if (!ctx) invalid("ctx is NULL");
   CGL_HIP(hipSetDevice(ctx->device));
   std::unique_ptr<Problem> P(new Problem());
   P->ctx = ctx;
@@ -495,6 +531,17 @@ int cgl_problem_create(cgl_ctx* ctx, const void* X, int32_t x_dtype, int32_t x_m
   P->M = M;
   P->k = k;
   upload_X(*P, X, x_mem, ldx);
+  if (x_mem == CGL_MEM_DEVICE) {
+    // non-finite entries of a device X, counted on the device copy
+    DevBuf bad;
+    bad.alloc(sizeof(int));
+    int nbad = 0;
+    CGL_HIP(hipMemsetAsync(bad.ptr, 0, sizeof(int), ctx->stream));
+    launch_count_nonfinite(P->xtype, P->X.ptr, n * P->ldx, bad.as<int>(), ctx->stream);
+    CGL_HIP(hipMemcpyAsync(&nbad, bad.ptr, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    CGL_HIP(hipStreamSynchronize(ctx->stream));
+    if (nbad > 0) invalid("X has " + std::to_string(nbad) + " non-finite entries");
+  }
   P->y.alloc((size_t)n * 8);
   CGL_HIP(hipMemcpy(P->y.ptr, y, (size_t)n * 8, hipMemcpyHostToDevice));
   if (L > 0.0) {
@@ -570,8 +617,8 @@ int cgl_problem_set_eigen(cgl_problem* prob, double shift) {
   CGL_API_END
 }
 
-int cgl_solve_batch(cgl_problem* prob, const cgl_node* nodes, int32_t count, double* beta_out,
-                    cgl_result* res) {
+static int solve_batch_impl(cgl_problem* prob, const cgl_node* nodes, int32_t count,
+                            double* beta_out, cgl_result* res, double* dual_out) {
   CGL_API_BEGIN
   if (!prob || (count > 0 && (!nodes || !res))) invalid("NULL argument");
   if (count < 0) invalid("count < 0");
@@ -585,6 +632,8 @@ int cgl_solve_batch(cgl_problem* prob, const cgl_node* nodes, int32_t count, dou
   std::vector<int32_t> mixed_idx;
   for (int32_t i = 0; i < count; ++i) {
     double* bo = beta_out ? beta_out + (int64_t)i * P.p : nullptr;
+    if (dual_out && (hosts[(size_t)i].infeasible || nodes[i].precision != CGL_PREC_MIXED))
+      std::fill(dual_out + (int64_t)i * P.p, dual_out + (int64_t)(i + 1) * P.p, std::nan(""));
     if (hosts[(size_t)i].infeasible) {
       infeasible_result(&res[i], bo, P.p);
     } else if (nodes[i].precision == CGL_PREC_MIXED) {
@@ -594,20 +643,26 @@ int cgl_solve_batch(cgl_problem* prob, const cgl_node* nodes, int32_t count, dou
       solve_plain(P, nodes[i], hosts[(size_t)i], bo, &res[i]);
     }
   }
-  if (!mixed.empty()) {
-    std::vector<cgl_result> mres(mixed.size());
-    std::vector<double> mbeta(beta_out ? mixed.size() * (size_t)P.p : 0);
-    solve_mixed(P, mixed.data(), (int32_t)mixed.size(), beta_out ? mbeta.data() : nullptr,
-                mres.data());
-    for (size_t q = 0; q < mixed.size(); ++q) {
-      res[mixed_idx[q]] = mres[q];
-      if (beta_out)
-        std::copy(mbeta.begin() + (int64_t)q * P.p, mbeta.begin() + (int64_t)(q + 1) * P.p,
-                  beta_out + (int64_t)mixed_idx[q] * P.p);
-    }
-  }
+  // the batched engine writes each node's result and solution straight into the caller's row
+  if (!mixed.empty())
+    solve_mixed(P, mixed.data(), (int32_t)mixed.size(), beta_out, res, mixed_idx.data(),
+                dual_out);
   return CGL_OK;
   CGL_API_END
+}
+
+int cgl_solve_batch(cgl_problem* prob, const cgl_node* nodes, int32_t count, double* beta_out,
+                    cgl_result* res) {
+  return solve_batch_impl(prob, nodes, count, beta_out, res, nullptr);
+}
+
+int cgl_solve_batch_dual(cgl_problem* prob, const cgl_node* nodes, int32_t count,
+                         double* beta_out, cgl_result* res, double* dual_beta_out) {
+  if (!dual_beta_out && count > 0) {
+    set_error("dual_beta_out is NULL");
+    return CGL_E_INVAL;
+  }
+  return solve_batch_impl(prob, nodes, count, beta_out, res, dual_beta_out);
 }
 
 int cgl_certify(cgl_problem* prob, const cgl_node* node, const double* beta, double* primal,

@@ -77,6 +77,7 @@ void MixedWork::ensure(Problem& P) {
   base1.alloc(P.loss == LOSS_LS ? 8 : Sn * 8);
   e0f.alloc(P.loss == LOSS_LS ? Sn * 4 : 8);
   bres.alloc(Sp * 8);
+  bdual.alloc(Sp * 8);
   dop.alloc((size_t)S_pad * ldp * 2);
   gop.alloc((size_t)S_pad * n_pad * 2);
   dU.alloc(2 * (size_t)S_pad * n_pad * 4);
@@ -223,6 +224,7 @@ void MixedWork::ensure(Problem& P) {
   md.base1 = base1.as<double>();
   md.e0f = e0f.as<float>();
   md.bres = bres.as<double>();
+  md.bdual = bdual.as<double>();
   md.dop = dop.as<uint16_t>();
   md.gop = gop.as<uint16_t>();
   md.dU = dU.as<float>();
@@ -569,7 +571,7 @@ void MixedWork::close_round(Problem& P) {
 
 size_t MixedWork::device_bytes() const {
   const DevBuf* bufs[] = {&Xb, &Xbt, &ypad, &st, &cls, &bring, &beta0, &H0, &base0, &base1, &e0f,
-                          &bres, &dop, &gop, &dU, &dUp, &dH, &lpart, &fpart, &cycle, &prevsel, &B64,
+                          &bres, &bdual, &dop, &gop, &dU, &dUp, &dH, &lpart, &fpart, &cycle, &prevsel, &B64,
                           &U64, &R64, &H64, &cpart, &list, &H0_cold, &base0_cold, &base1_cold,
                           &Xt, &part64, &sflag, &sidx, &scount, &Bu, &G, &pinv, &pinv_new,
                           &perm, &perm_new, &dop_tmp, &pfx, &sj, &sv, &Bret};
@@ -660,8 +662,15 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
 
 void MixedWork::retire(Problem& P, const std::vector<int>& slots,
                        const std::vector<cgl_result*>& res, const std::vector<double*>& beta_out,
-                       bool defer) {
+                       bool defer, const std::vector<double*>* dual_out) {
   hipStream_t s = P.ctx->stream;
+  if (dual_out) {
+    for (size_t i = 0; i < slots.size(); ++i)
+      if ((*dual_out)[i])
+        CGL_HIP(hipMemcpyAsync((*dual_out)[i], bdual.as<double>() + (int64_t)slots[i] * ldp,
+                               (size_t)P.p * 8, hipMemcpyDeviceToHost, s));
+    CGL_HIP(hipStreamSynchronize(s));
+  }
   std::vector<int> rows;  // slots whose iterate is wanted, in the order of their staging rows
   for (size_t i = 0; i < slots.size(); ++i) {
     const int sl = slots[i];
@@ -737,7 +746,9 @@ void MixedWork::push_states(Problem& P) {
 }
 
 void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_out,
-                 cgl_result* res) {
+                 cgl_result* res, const int32_t* rows, double* dual_out) {
+  // node i reports into the caller's row rows[i] (res and beta_out), or row i
+  auto row = [&](int32_t i) -> int64_t { return rows ? rows[i] : i; };
   if (!P.mixed) P.mixed = new MixedWork();
   MixedWork& W = *P.mixed;
   W.ensure(P);
@@ -758,7 +769,7 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
   std::vector<char> handled((size_t)count, 0);
   for (int32_t i = 0; i < count; ++i) {
     if (hosts[(size_t)i].infeasible) {
-      infeasible_result(&res[i], beta_out ? beta_out + (int64_t)i * P.p : nullptr, P.p);
+      infeasible_result(&res[row(i)], beta_out ? beta_out + row(i) * P.p : nullptr, P.p);
       handled[(size_t)i] = 1;
       ++finished;
     }
@@ -794,16 +805,17 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
     phase(7, [&] {
       std::vector<int> done;
       std::vector<cgl_result*> rs;
-      std::vector<double*> bs;
+      std::vector<double*> bs, ds;
       for (int sl = 0; sl < W.S; ++sl) {
         const int owner = W.slot_owner[(size_t)sl];
         if (owner < 0 || !W.st_host[sl].done) continue;
         done.push_back(sl);
-        rs.push_back(&res[owner]);
-        bs.push_back(beta_out ? beta_out + (int64_t)owner * P.p : nullptr);
+        rs.push_back(&res[row(owner)]);
+        bs.push_back(beta_out ? beta_out + row(owner) * P.p : nullptr);
+        ds.push_back(dual_out ? dual_out + row(owner) * P.p : nullptr);
       }
       if (!done.empty()) {
-        W.retire(P, done, rs, bs, /*defer=*/true);
+        W.retire(P, done, rs, bs, /*defer=*/true, dual_out ? &ds : nullptr);
         finished += (int32_t)done.size();
         // the device states of the retired slots need no update: they are done and do not run,
         // and an admission into the slot writes its state

@@ -35,7 +35,7 @@ struct MixedWork {
   int64_t x_kchunk = 0;
   int64_t rchunk = 0, cchunk = 0;
   double f_cold = 0.0;
-  DevBuf Xb, Xbt, ypad, st, cls, bring, beta0, H0, base0, base1, e0f, bres, dop, gop, dU, dUp, dH, lpart,
+  DevBuf Xb, Xbt, ypad, st, cls, bring, beta0, H0, base0, base1, e0f, bres, bdual, dop, gop, dU, dUp, dH, lpart,
       fpart, cycle, prevsel, B64, U64, R64, H64, cpart, list, H0_cold, base0_cold, base1_cold, Xt, part64,
       sflag, sidx, scount, Bu, G, Bret, pinv, pinv_new, perm, perm_new, dop_tmp, pfx, sj, sv;
   int64_t ldg = 0;  // least squares: G = X^T X in FP64 (p x ldg), when built
@@ -107,8 +107,11 @@ struct MixedWork {
   // callers' buffers. The slots are freed. With defer, the copy runs on a stream of its own while
   // the next launches proceed, and the iterates reach the callers' buffers at flush_retired()
   // (called before the next retirement and before the solve returns).
+  // dual_out (optional, entries may be null): the iterate whose dual point gave each slot's
+  // certified bound, copied synchronously.
   void retire(Problem& P, const std::vector<int>& slots, const std::vector<cgl_result*>& res,
-              const std::vector<double*>& beta_out, bool defer = false);
+              const std::vector<double*>& beta_out, bool defer = false,
+              const std::vector<double*>* dual_out = nullptr);
   void flush_retired();
   void drop_retired();  // forget staged iterates (their copy is waited for first)
   void push_states(Problem& P);

@@ -99,8 +99,11 @@ struct Problem {
 
 void solve_plain(Problem& P, const cgl_node& nd, const NodeHost& nh, double* beta_out,
                  cgl_result* res);
+// Batched solve of count mixed-precision nodes; node i's result and solution go to row rows[i]
+// of res and beta_out (row i when rows is null), and with dual_out the iterate whose dual point
+// gave its certified bound to the same row of dual_out.
 void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_out,
-                 cgl_result* res);
+                 cgl_result* res, const int32_t* rows = nullptr, double* dual_out = nullptr);
 void certify_host_beta(Problem& P, const NodeHost& nh, const double* beta, double* primal,
                        double* dual);
 

@@ -47,5 +47,8 @@ void launch_resid(const double* u, const double* y, int64_t n, int loss, double*
 void launch_g_gstar(int nodes, const double* beta, int64_t b_ld, const double* h, int64_t h_ld,
                     const uint8_t* cls, int64_t cls_ld, const NodeDev* st, int64_t p, double M,
                     double two_l2, double* out, hipStream_t stream);
+// *bad += number of non-finite values among the count stored elements of X (BF16: exponent all
+// ones); *bad must start at zero.
+void launch_count_nonfinite(int xtype, const void* X, int64_t count, int* bad, hipStream_t s);
 
 }  // namespace cgl

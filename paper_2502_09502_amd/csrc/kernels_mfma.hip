@@ -619,7 +619,7 @@ __global__ __launch_bounds__(1024) void k_cert_finish(MixedDev md, const int* li
     const double D = -acc[1] - 2.0 * md.lam2 * gs;
     int improve = 0;
     if (P < st->P_cert) { st->P_cert = P; improve = 1; }
-    if (D > st->D_cert) st->D_cert = D;
+    if (D > st->D_cert) { st->D_cert = D; improve |= 2; }
     st->b_int0 = improve;
     const double gap = (st->P_cert - st->D_cert) / fmax(fabs(st->P_cert), 1.0);
     int status = kRunning;
@@ -652,12 +652,14 @@ __global__ __launch_bounds__(1024) void k_cert_finish(MixedDev md, const int* li
     st->need_base = 0;
   }
   __syncthreads();
-  const bool improve = st->b_int0 != 0;
+  const bool improve = (st->b_int0 & 1) != 0;
+  const bool improve_d = (st->b_int0 & 2) != 0;
   const bool done = st->done != 0;
   const bool fresh = !done && !keep;  // the ring, the operand and the products start at the base
   for (int64_t j = threadIdx.x; j < md.ldp; j += blockDim.x) {
     const double bj = B64[(int64_t)q * md.ldp + j];
     if (improve) md.bres[(int64_t)slot * md.ldp + j] = bj;
+    if (improve_d) md.bdual[(int64_t)slot * md.ldp + j] = bj;
     if (!done) {
       md.beta0[(int64_t)slot * md.ldp + j] = bj;
       md.H0[(int64_t)slot * md.ldp + j] = H64[(int64_t)q * md.ldp + j];
@@ -694,6 +696,7 @@ __global__ __launch_bounds__(256) void k_admit(MixedDev md, const int* list, int
     for (int r = 0; r < 3; ++r) md.bring[(int64_t)r * md.bring_stride + o] = 0.0;
     md.beta0[o] = 0.0;
     md.bres[o] = 0.0;
+    md.bdual[o] = 0.0;
     md.H0[o] = H0_cold[j];
     md.dop[frag_index(slot, j, md.S_pad >> 5)] = 0;
   }

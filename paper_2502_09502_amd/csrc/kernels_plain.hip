@@ -6,6 +6,8 @@
 //   k_xb         u^{t+1} = X beta^{t+1} and the loss terms f_i(u^{t+1}) (HBM pass over X)
 //   k_finish     L^{t+1}, value restart (Alg. 3), best primal, dual bound (Sec. 3.4), stopping
 // X gamma is never formed: by linearity X gamma = u^t + c (u^t - u^{t-1}).
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 #include "losses.h"
@@ -678,6 +680,47 @@ void launch_g_gstar(int nodes, const double* beta, int64_t b_ld, const double* h
       break;
   }
 #undef CGL_G_CASE
+}
+
+// =====================================================================================
+// Count of non-finite entries of a stored design (any precision; padding is zero). The counter
+// starts at zero; each workgroup adds its count once.
+// =====================================================================================
+template <typename XT>
+__device__ __forceinline__ bool not_finite(XT v);
+template <>
+__device__ __forceinline__ bool not_finite<double>(double v) { return !isfinite(v); }
+template <>
+__device__ __forceinline__ bool not_finite<float>(float v) { return !isfinite(v); }
+template <>
+__device__ __forceinline__ bool not_finite<uint16_t>(uint16_t v) { return (v & 0x7f80u) == 0x7f80u; }
+
+template <typename XT>
+__global__ __launch_bounds__(256) void k_count_nonfinite(const XT* __restrict__ X, int64_t count,
+                                                         int* bad) {
+  __shared__ int sbad;
+  if (threadIdx.x == 0) sbad = 0;
+  __syncthreads();
+  int c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256)
+    c += not_finite<XT>(X[i]) ? 1 : 0;
+  if (c) atomicAdd(&sbad, c);
+  __syncthreads();
+  if (threadIdx.x == 0 && sbad) atomicAdd(bad, sbad);
+}
+
+void launch_count_nonfinite(int xtype, const void* X, int64_t count, int* bad, hipStream_t s) {
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (count + 255) / 256));
+  if (xtype == XT_F64)
+    hipLaunchKernelGGL(k_count_nonfinite<double>, dim3(grid), dim3(256), 0, s,
+                       (const double*)X, count, bad);
+  else if (xtype == XT_F32)
+    hipLaunchKernelGGL(k_count_nonfinite<float>, dim3(grid), dim3(256), 0, s, (const float*)X,
+                       count, bad);
+  else
+    hipLaunchKernelGGL(k_count_nonfinite<uint16_t>, dim3(grid), dim3(256), 0, s,
+                       (const uint16_t*)X, count, bad);
 }
 
 }  // namespace cgl

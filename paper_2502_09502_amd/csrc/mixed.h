@@ -32,6 +32,8 @@ struct MixedDev {
                         // rounding is the same in every cycle between re-centres)
   double* base1;        // S x n_pad: logistic r_0 = grad f(u_0)
   double* bres;         // S x ldp: best certified iterate
+  double* bdual;        // S x ldp: the iterate whose dual point zeta = -grad f(X beta) gave the
+                        // best certified bound
   uint16_t* dop;        // S_pad x ldp: bf16(beta - beta_0)
   uint16_t* gop;        // S_pad x n_pad: bf16(grad f(u_gamma) - r_0)
   float* dU;            // 2 rings x S_pad x n_pad

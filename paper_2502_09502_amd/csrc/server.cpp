@@ -302,15 +302,18 @@ int cgl_server_poll(cgl_server* srv, int32_t max, uint64_t* tickets, cgl_result*
   admit_round(*srv);
   plain_round(*srv);
   run_round(*srv);
+  // results are taken in completion order while their solution fits the caller's stride: the
+  // first one that does not stays queued (and is refused here only when it is the first)
+  if (betas && max > 0 && !srv->done.empty() &&
+      betas_stride < (int64_t)srv->done.front().beta.size())
+    invalid("betas_stride is smaller than the p of the next result");
   int32_t n = 0;
   while (n < max && !srv->done.empty()) {
     Finished& f = srv->done.front();
+    if (betas && betas_stride < (int64_t)f.beta.size()) break;
     tickets[n] = f.ticket;
     res[n] = f.res;
-    if (betas) {
-      if (betas_stride < (int64_t)f.beta.size()) invalid("betas_stride is smaller than p");
-      std::copy(f.beta.begin(), f.beta.end(), betas + (int64_t)n * betas_stride);
-    }
+    if (betas) std::copy(f.beta.begin(), f.beta.end(), betas + (int64_t)n * betas_stride);
     if (latency_s) latency_s[n] = f.latency;
     srv->done.pop_front();
     ++n;

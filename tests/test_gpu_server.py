@@ -145,3 +145,41 @@ def test_server_rejects_bad_arguments():
     out = _drain(srv, 1)
     assert out[t][0].status == "converged"
     srv.close()
+
+
+def test_poll_stride_keeps_results_that_do_not_fit():
+    """Results wait in completion order; one whose p exceeds the caller's stride stays queued
+    (refused with nothing taken when it comes first) and the ones before it are returned."""
+    import ctypes as C
+
+    a = synth.make_dataset(120, 50, 3, config_id=31)
+    b = synth.make_dataset(120, 80, 3, config_id=32)
+    pa = _lib.Problem(ctx(), a.X_store, a.y, loss="ls", lam2=a.lam2, M=a.M, k=a.k)
+    pb = _lib.Problem(ctx(), b.X_store, b.y, loss="ls", lam2=b.lam2, M=b.M, k=b.k)
+    srv = _lib.Server(ctx(), 0, 4)
+    lib = srv.lib
+    # infeasible nodes (|Z1| > k) finish at submit, in submission order
+    ta = srv.submit(pa, pa.node(Z1=[0, 1, 2, 3], precision="mixed"))
+    tb = srv.submit(pb, pb.node(Z1=[0, 1, 2, 3], precision="mixed"))
+    ta2 = srv.submit(pa, pa.node(Z1=[5, 6, 7, 8], precision="mixed"))
+
+    def poll(mx, stride):
+        tickets = (C.c_uint64 * 4)()
+        res = (_lib.CglResult * 4)()
+        betas = np.full((4, stride), 7.0)
+        got = C.c_int32(-1)
+        st = lib.cgl_server_poll(srv.h, mx, tickets, res, _lib._dptr(betas), stride, None,
+                                 C.byref(got))
+        return st, [int(tickets[i]) for i in range(got.value)], betas
+
+    st, got, betas = poll(4, 50)  # a's result fits, b's does not: only a's comes back
+    assert st == _lib.OK and got == [ta]
+    assert np.all(betas[0] == 0.0) and np.all(betas[1:] == 7.0)
+    assert srv.stats()["done"] == 2
+    st, got, _ = poll(4, 50)  # b's result is first now and does not fit: refused, nothing taken
+    assert st == _lib.E_INVAL and got == [] and srv.stats()["done"] == 2
+    st, got, betas = poll(4, 80)
+    assert st == _lib.OK and got == [tb, ta2]
+    assert np.all(betas[1, :50] == 0.0) and np.all(betas[1, 50:] == 7.0)
+    assert srv.stats() == {"queued": 0, "running": 0, "done": 0}
+    srv.close()

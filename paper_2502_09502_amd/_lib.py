@@ -187,18 +187,16 @@ class NodeSpec:
 class Problem:
     """A problem (X, y, loss, lambda2, M, k) resident on the device.
 
-    X: numpy array (float64, float32, or uint16 bfloat16 patterns), or a torch CUDA tensor of
-    one of those dtypes (then no host copy is made)."""
+    X: numpy array (float64, float32, or uint16 bfloat16 patterns), or a C-contiguous array in
+    device memory of one of those dtypes (a devmem.DeviceArray; then no host copy is made)."""
 
     def __init__(self, ctx: Context, X, y, loss="ls", lam2=1e-3, M=2.0, k=10, L=0.0):
         self.ctx = ctx
         self.lib = ctx.lib
         mem = MEM_HOST
-        if hasattr(X, "data_ptr"):  # torch tensor on the device
-            import torch
-
-            assert X.is_cuda and X.is_contiguous()
-            dt = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}[X.dtype]
+        if hasattr(X, "data_ptr"):  # device memory
+            dt = {np.dtype(np.float64): F64, np.dtype(np.float32): F32,
+                  np.dtype(np.uint16): BF16}[np.dtype(X.dtype)]
             n, p = X.shape
             ptr = C.c_void_p(X.data_ptr())
             mem = MEM_DEVICE

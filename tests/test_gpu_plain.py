@@ -172,21 +172,22 @@ def test_eigen_perspective_relaxation():
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_non_finite_device_X_rejected(dtype):
     """A design given in device memory is checked for NaN and infinity on the device."""
-    import torch
+    from paper_2502_09502_amd.devmem import DeviceArray
 
     d = synth.make_dataset(64, 24, 3, dtype=dtype, config_id=93)
-    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype]
-    if dtype == "bf16":
-        Xd = torch.from_numpy(d.X_store.view(np.int16)).view(torch.bfloat16).to("cuda")
-    else:
-        Xd = torch.from_numpy(d.X_store).to("cuda")
-    assert Xd.dtype == tdt
-    ok = _lib.Problem(ctx(), Xd.contiguous(), d.y, loss="ls", lam2=d.lam2, M=d.M, k=d.k)
+    Xd = DeviceArray.from_numpy(d.X_store)
+    ok = _lib.Problem(ctx(), Xd, d.y, loss="ls", lam2=d.lam2, M=d.M, k=d.k)
     assert ok.L > 0
     ok.close()
-    for bad in (float("nan"), float("inf")):
-        Xb = Xd.clone()
-        Xb[5, 7] = bad
+    # bit patterns of NaN and +infinity in the stored type (BF16: exponent all ones)
+    bads = {"f64": (np.nan, np.inf), "f32": (np.float32(np.nan), np.float32(np.inf)),
+            "bf16": (np.uint16(0x7FC0), np.uint16(0x7F80))}[dtype]
+    for bad in bads:
+        Xh = d.X_store.copy()
+        Xh[5, 7] = bad
+        Xb = DeviceArray.from_numpy(Xh)
         with pytest.raises(_lib.CglError) as e:
             _lib.Problem(ctx(), Xb, d.y, loss="ls", lam2=d.lam2, M=d.M, k=d.k)
         assert e.value.code == _lib.E_INVAL and "non-finite" in str(e.value)
+        Xb.free()
+    Xd.free()

@@ -231,6 +231,23 @@ int cgl_prox_node_batch(cgl_ctx* ctx, double rho, double M, int32_t k, const cgl
                         const double* W, int32_t count, int64_t p, double* beta_out,
                         double* gval_out);
 
+/* cgl_prox_node_batch for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same prox kernel for nodes
+ * without fixed sets (k' = k, every coordinate free), with device buffers in and out and no
+ * allocation, host copy or synchronisation inside the call.
+ *   W: count x p device doubles (row-major); beta_out: count x p device doubles; gval_out: NULL
+ *   or count device doubles (g(beta_i), Alg. 2).
+ * The work is enqueued on the context's stream and the call returns without waiting: the
+ * outputs are ready once that stream has been synchronised (or a later call on it ordered after
+ * them). The per-vector states live in a fixed device array of 992 KiB per GPU (reserved
+ * for the life of the process), shared by every call on that GPU and rewritten by each: calls
+ * that overlap on one GPU (other streams or other contexts) race and must be serialised by the
+ * caller.
+ * Errors (CGL_E_INVAL, nothing enqueued): NULL ctx, W or beta_out; count < 0 or count > 4096;
+ * p < 1 or p > 32768; rho <= 0, M <= 0 or k < 0; 256 < k < p. */
+int cgl_prox_batch_noalloc(cgl_ctx* ctx, double rho, double M, int32_t k, const double* W,
+                           int32_t count, int64_t p, double* beta_out, double* gval_out);
+
 /* ------------------------------------------------------------------ serving */
 
 /* A request loop over resident problems: submitted node relaxations are admitted into device

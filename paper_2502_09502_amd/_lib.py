@@ -26,7 +26,7 @@ EXPORTS = [
     "cgl_ctx_destroy", "cgl_ctx_set_profiling", "cgl_ctx_kernel_stats", "cgl_problem_create", "cgl_problem_destroy", "cgl_problem_lipschitz",
     "cgl_node_validate", "cgl_solve_node", "cgl_solve_batch", "cgl_solve_batch_dual",
     "cgl_certify", "cgl_problem_matvec",
-    "cgl_prox_node_batch", "cgl_problem_set_eigen", "cgl_server_create", "cgl_server_submit", "cgl_server_poll",
+    "cgl_prox_node_batch", "cgl_prox_batch_noalloc", "cgl_problem_set_eigen", "cgl_server_create", "cgl_server_submit", "cgl_server_poll",
     "cgl_server_cancel", "cgl_server_stats", "cgl_server_destroy",
 ]
 
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH):
     lib.cgl_certify.argtypes = [P, C.POINTER(CglNode), pd, pd, pd]
     lib.cgl_problem_matvec.argtypes = [P, i32, pd, pd]
     lib.cgl_prox_node_batch.argtypes = [P, dbl, dbl, i32, C.POINTER(CglNode), pd, i32, i64, pd, pd]
+    lib.cgl_prox_batch_noalloc.argtypes = [P, dbl, dbl, i32, P, i32, i64, P, P]
     lib.cgl_problem_set_eigen.argtypes = [P, dbl]
     if hasattr(lib, "cgl_server_create"):
         lib.cgl_server_create.argtypes = [P, C.c_size_t, i32, C.POINTER(P)]
@@ -309,6 +310,19 @@ def prox_node_batch(ctx: Context, W, rho, M, k, sets=None):
     check(ctx.lib.cgl_prox_node_batch(ctx.h, float(rho), float(M), int(k), arr, _dptr(W), count,
                                       p, _dptr(beta), _dptr(g)))
     return beta, g
+
+
+def prox_batch_noalloc(ctx: Context, W, beta, g, rho, M, k):
+    """cgl_prox_batch_noalloc on device buffers (objects with data_ptr() and shape): W and beta
+    (count, p) float64, g None or (count,) float64. Enqueued on the context's stream; the caller
+    synchronises that stream before reading the outputs."""
+    count, p = (int(s) for s in W.shape)
+    if tuple(beta.shape) != (count, p) or (g is not None and tuple(g.shape) != (count,)):
+        raise ValueError("output shapes do not match W")
+    check(ctx.lib.cgl_prox_batch_noalloc(ctx.h, float(rho), float(M), int(k),
+                                         C.c_void_p(W.data_ptr()), count, p,
+                                         C.c_void_p(beta.data_ptr()),
+                                         C.c_void_p(g.data_ptr()) if g is not None else None))
 
 
 class Server:

@@ -429,6 +429,7 @@ int cgl_ctx_create(int device, void* hip_stream, cgl_ctx** out) {
   CGL_HIP(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) invalid("device ordinal out of range");
   CGL_HIP(hipSetDevice(device));
+  noalloc_setup(device);  // this device's address of the allocation-free prox's scratch
   std::unique_ptr<cgl_ctx> c(new cgl_ctx());
   c->device = device;
   if (hip_stream) {

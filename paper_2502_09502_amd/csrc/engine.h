@@ -63,6 +63,9 @@ struct NodeHost {
 NodeHost make_node_host(const cgl_node& nd, int64_t p, int k);
 NodeDev make_node_dev(const cgl_node& nd, const NodeHost& h);
 void fill_result(const NodeDev& s, cgl_result* r);
+// Takes this device's address of the allocation-free prox's scratch array (noalloc.hip); called
+// once per context creation with the device current.
+void noalloc_setup(int device);
 void infeasible_result(cgl_result* r, double* beta_out, int64_t p);
 
 struct Problem;

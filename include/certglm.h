@@ -134,7 +134,9 @@ int cgl_ctx_destroy(cgl_ctx* ctx);
  * launch without graph capture; the batched products are launched with their start and stop
  * events attached, the other kernels are bracketed) and accumulate the elapsed time of launches
  * that did work. The batched X pass (which = 3) is timed only at on = 2: a timed launch starts
- * a few microseconds later. CGL_E_INVAL for another value of on.
+ * a few microseconds later. on = 3 records only the host wall time of the batched engine's
+ * phases (which = 5, 6, 7 below) and leaves the launches as they run unprofiled (graph-captured
+ * chunks). CGL_E_INVAL for another value of on.
  * which: 0 = X^T pass of the plain path (k_xt), 1 = X pass of the plain path (k_xb),
  *        2 = batched BF16 MFMA X^T pass, 3 = batched BF16 MFMA X pass, 4 = batched FP64 pass;
  *        and host wall time of the batched engine's phases (launch to completion):
@@ -177,11 +179,20 @@ int cgl_problem_lipschitz(const cgl_problem* prob, double* L);
  * (between the perspective relaxation, shift = 0, and the k-sparse optimum) and certify it with
  *   ||y||^2 - beta^T Q beta - 2 lambda_eig g_node*((X^T y - Q beta) / lambda_eig)
  * evaluated at the iteration's momentum point. The bound is valid for 0 <= shift <=
- * lambda_min(X^T X): the caller supplies the shift (e.g. from an eigen-solver, with a margin);
- * the library does not verify it. L becomes 2 (1.002 lambda_max(X^T X) - shift).
- * Errors: CGL_E_INVAL for another loss, shift < 0 or shift >= lambda_max. Batched (MIXED)
- * solves and cgl_certify reject a shifted problem; shift = 0 restores the perspective one. */
+ * lambda_min(X^T X), and the library accepts a shift only when it proves that: an FP64 Cholesky
+ * factorisation of G - (shift + delta) I, G = X^T X formed in FP64 from the stored X, runs to
+ * completion on the device (delta = 4 (n + p + 2) 2^-53 trace(G) covers the rounding of G and of
+ * the factorisation; cgl_problem_eigen_shift finds the largest such shift). With n < p only
+ * shift 0 is valid. L becomes 2 (1.002 lambda_max(X^T X) - shift).
+ * Errors: CGL_E_INVAL for another loss, shift < 0, shift >= lambda_max, or a shift the
+ * factorisation does not prove. Batched (MIXED) solves and cgl_certify reject a shifted problem;
+ * shift = 0 restores the perspective one. */
 int cgl_problem_set_eigen(cgl_problem* prob, double shift);
+
+/* The largest shift that the Cholesky test of cgl_problem_set_eigen proves, found by bisection
+ * on [0, lambda_max] to a width of 1e-7 of the proved shift (one FP64 factorisation of the
+ * p x p Gram matrix per step; 0 when n < p). Least squares only (CGL_E_INVAL otherwise). */
+int cgl_problem_eigen_shift(cgl_problem* prob, double* shift);
 
 /* Check a node against a problem's p and k on the host (no device work): the rules of
  * cgl_node above, tol >= 0, max_iter >= 1, check_every >= 1, a known precision, a finite warm
@@ -226,7 +237,10 @@ int cgl_problem_matvec(cgl_problem* prob, int32_t trans, const double* v, double
 /* The node prox on the device (Alg. 1 via the Moreau identity, node form): for each of count
  * rows w_i (host, count x p doubles), beta_i = prox_{g_node/rho}(w_i) with k' = k - |Z1_i|, and
  * gval_i = g_node(beta_i) (Alg. 2). nodes may be NULL (no fixed sets, only k used). beta_out:
- * count x p doubles; gval_out: NULL or count doubles. */
+ * count x p doubles; gval_out: NULL or count doubles. p <= 1048576 (above 32768 each vector is
+ * streamed from device memory by its workgroup instead of held per thread; the standalone
+ * workload of Sec. 4.1 runs to p = 102400). Errors (CGL_E_INVAL): NULL ctx, W or beta_out;
+ * count < 0; p < 1 or p > 1048576; rho <= 0, M <= 0 or k < 0; an invalid node; 256 < k' < |F|. */
 int cgl_prox_node_batch(cgl_ctx* ctx, double rho, double M, int32_t k, const cgl_node* nodes,
                         const double* W, int32_t count, int64_t p, double* beta_out,
                         double* gval_out);

@@ -26,7 +26,8 @@ EXPORTS = [
     "cgl_ctx_destroy", "cgl_ctx_set_profiling", "cgl_ctx_kernel_stats", "cgl_problem_create", "cgl_problem_destroy", "cgl_problem_lipschitz",
     "cgl_node_validate", "cgl_solve_node", "cgl_solve_batch", "cgl_solve_batch_dual",
     "cgl_certify", "cgl_problem_matvec",
-    "cgl_prox_node_batch", "cgl_prox_batch_noalloc", "cgl_problem_set_eigen", "cgl_server_create", "cgl_server_submit", "cgl_server_poll",
+    "cgl_prox_node_batch", "cgl_prox_batch_noalloc", "cgl_problem_set_eigen",
+    "cgl_problem_eigen_shift", "cgl_server_create", "cgl_server_submit", "cgl_server_poll",
     "cgl_server_cancel", "cgl_server_stats", "cgl_server_destroy",
 ]
 
@@ -92,6 +93,7 @@ def load(path: str = LIB_PATH):
     lib.cgl_prox_node_batch.argtypes = [P, dbl, dbl, i32, C.POINTER(CglNode), pd, i32, i64, pd, pd]
     lib.cgl_prox_batch_noalloc.argtypes = [P, dbl, dbl, i32, P, i32, i64, P, P]
     lib.cgl_problem_set_eigen.argtypes = [P, dbl]
+    lib.cgl_problem_eigen_shift.argtypes = [P, pd]
     if hasattr(lib, "cgl_server_create"):
         lib.cgl_server_create.argtypes = [P, C.c_size_t, i32, C.POINTER(P)]
         lib.cgl_server_submit.argtypes = [P, P, C.POINTER(CglNode), C.POINTER(C.c_uint64)]
@@ -125,9 +127,11 @@ class Context:
             self.lib.cgl_ctx_destroy(self.h)
             self.h = C.c_void_p()
 
-    def set_profiling(self, on: bool, x_pass: bool = False):
-        """Kernel timing on or off; x_pass also times the batched X pass (level 2)."""
-        check(self.lib.cgl_ctx_set_profiling(self.h, (2 if x_pass else 1) if on else 0))
+    def set_profiling(self, on: bool, x_pass: bool = False, phases_only: bool = False):
+        """Kernel timing on or off; x_pass also times the batched X pass (level 2);
+        phases_only records only the batched engine's phase wall times (level 3, graphs on)."""
+        level = 0 if not on else (3 if phases_only else (2 if x_pass else 1))
+        check(self.lib.cgl_ctx_set_profiling(self.h, level))
 
     def kernel_stats(self, which: int, reset: bool = False):
         """(total milliseconds, launches) of one timed kernel (see cgl_ctx_kernel_stats)."""
@@ -237,6 +241,12 @@ class Problem:
     def set_eigen(self, shift: float) -> None:
         """Eigen-perspective relaxation with Q = X^T X - shift I (0 <= shift <= lambda_min)."""
         check(self.lib.cgl_problem_set_eigen(self.h, float(shift)))
+
+    def eigen_shift(self) -> float:
+        """The largest shift the library's Cholesky test proves (<= lambda_min(X^T X))."""
+        v = C.c_double()
+        check(self.lib.cgl_problem_eigen_shift(self.h, C.byref(v)))
+        return v.value
 
     def node(self, **kw) -> NodeSpec:
         return NodeSpec(self.p, **kw)

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcertglm.so")
-SOURCES = ["kernels_plain.hip", "kernels_mfma.hip", "api.cpp", "batch.cpp", "server.cpp", "noalloc.hip"]
+SOURCES = ["kernels_plain.hip", "kernels_mfma.hip", "api.cpp", "batch.cpp", "server.cpp", "noalloc.hip", "prox_paged.hip", "chol.hip",
+           "eigen.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-function", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -58,6 +58,9 @@ void DevBuf::alloc(size_t b) {
 
 int64_t pad_cols(int64_t p) { return (p + 511) / 512 * 512; }
 
+// Longest vector of the standalone prox (cgl_prox_node_batch); problems stop at 32768.
+constexpr int64_t kProxMaxP = 1 << 20;
+
 // ------------------------------------------------------------------ node validation
 
 NodeHost make_node_host(const cgl_node& nd, int64_t p, int k) {
@@ -456,9 +459,10 @@ int cgl_ctx_destroy(cgl_ctx* ctx) {
 int cgl_ctx_set_profiling(cgl_ctx* ctx, int32_t on) {
   CGL_API_BEGIN
   if (!ctx) invalid("ctx is NULL");
-  if (on < 0 || on > 2) invalid("profiling level must be 0, 1 or 2");
-  ctx->profiling = on != 0;
+  if (on < 0 || on > 3) invalid("profiling level must be 0, 1, 2 or 3");
+  ctx->profiling = on == 1 || on == 2;
   ctx->profile_x = on == 2;
+  ctx->phase_timing = on != 0;
   return CGL_OK;
   CGL_API_END
 }
@@ -605,6 +609,10 @@ int cgl_problem_set_eigen(cgl_problem* prob, double shift) {
   CGL_HIP(hipSetDevice(P.ctx->device));
   if (P.lam_max <= 0.0) P.lam_max = power_lambda_max(P);
   if (shift >= P.lam_max) invalid("shift must be below lambda_max(X^T X)");
+  if (!eigen_shift_proved(P, shift))
+    invalid(P.n < P.p ? "X^T X is singular (n < p): only shift 0 is valid"
+                      : "shift not certified: an FP64 Cholesky factorisation of X^T X - (shift + "
+                        "rounding margin) I fails, so shift <= lambda_min(X^T X) is not proved");
   // L = 2 lambda_max(Q), Q = X^T X - s I, with the same safety factor on lambda_max; a graph
   // captured with the previous parameters is dropped
   if (P.plain.graph_exec) {
@@ -614,6 +622,18 @@ int cgl_problem_set_eigen(cgl_problem* prob, double shift) {
   P.shift = shift;
   P.L = 2.0 * (1.002 * P.lam_max - shift);
   P.rho = P.L / (2.0 * (P.lam2 + shift));
+  return CGL_OK;
+  CGL_API_END
+}
+
+int cgl_problem_eigen_shift(cgl_problem* prob, double* shift) {
+  CGL_API_BEGIN
+  if (!prob || !shift) invalid("NULL argument");
+  Problem& P = *reinterpret_cast<Problem*>(prob);
+  if (P.loss != LOSS_LS) invalid("the eigen-perspective relaxation is for least squares");
+  CGL_HIP(hipSetDevice(P.ctx->device));
+  if (P.lam_max <= 0.0) P.lam_max = power_lambda_max(P);
+  *shift = eigen_shift_certified(P, 1e-7);
   return CGL_OK;
   CGL_API_END
 }
@@ -726,7 +746,7 @@ int cgl_prox_node_batch(cgl_ctx* ctx, double rho, double M, int32_t k, const cgl
   CGL_API_BEGIN
   if (!ctx || !W || !beta_out) invalid("NULL argument");
   if (count < 0 || p < 1) invalid("count < 0 or p < 1");
-  if (p > 32768) invalid("p > 32768 is not supported by this build");
+  if (p > kProxMaxP) invalid("p > 1048576 is not supported by this build");
   if (!(rho > 0.0) || !(M > 0.0) || k < 0) invalid("need rho > 0, M > 0, k >= 0");
   if (count == 0) return CGL_OK;
   CGL_HIP(hipSetDevice(ctx->device));
@@ -757,8 +777,12 @@ int cgl_prox_node_batch(cgl_ctx* ctx, double rho, double M, int32_t k, const cgl
   CGL_HIP(hipMemcpyAsync(dS.ptr, st.data(), (size_t)count * sizeof(NodeDev),
                          hipMemcpyHostToDevice, s));
   if (ctx->profiling) CGL_HIP(hipEventRecord(ctx->event(0), s));
-  launch_prox(count, dW.as<double>(), p, nullptr, 0, dC.as<uint8_t>(), p, p, rho, M, 1.0,
-              dS.as<NodeDev>(), dB.as<double>(), 0, p, s);
+  if (prox_elems(p) > 0)
+    launch_prox(count, dW.as<double>(), p, nullptr, 0, dC.as<uint8_t>(), p, p, rho, M, 1.0,
+                dS.as<NodeDev>(), dB.as<double>(), 0, p, s);
+  else  // beyond one workgroup's per-thread values: the kernel that streams each vector
+    launch_prox_paged(count, dW.as<double>(), p, dC.as<uint8_t>(), p, p, rho, M,
+                      dS.as<NodeDev>(), dB.as<double>(), p, s);
   if (ctx->profiling) CGL_HIP(hipEventRecord(ctx->event(1), s));
   CGL_HIP(hipMemcpyAsync(beta_out, dB.ptr, (size_t)count * p * 8, hipMemcpyDeviceToHost, s));
   CGL_HIP(hipMemcpyAsync(st.data(), dS.ptr, (size_t)count * sizeof(NodeDev),

@@ -171,19 +171,8 @@ void MixedWork::ensure(Problem& P) {
       ldg = round_up(P.p, 256);
       G.alloc((size_t)P.p * ldg * 8);
       CGL_HIP(hipMemsetAsync(G.ptr, 0, G.bytes, s));
-      const char* xt = (const char*)(P.xtype == XT_BF16 ? Xbt.ptr : Xt.ptr);
-      const size_t esz = P.xtype == XT_F64 ? 8 : (P.xtype == XT_F32 ? 4 : 2);
-      const int64_t rows = 256;
-      DevBuf wide;
-      wide.alloc((size_t)rows * n_pad * 8);
-      for (int64_t j0 = 0; j0 < P.p; j0 += rows) {  // G rows j0 .. j0 + r
-        const int64_t r = std::min(rows, P.p - j0);
-        launch_widen(P.xtype, xt + (size_t)j0 * n_pad * esz, n_pad, r, n_pad, wide.as<double>(),
-                     n_pad, s);
-        launch_gemm_f64(P.xtype, xt, n_pad, P.p, P.n, wide.as<double>(), n_pad, (int)r,
-                        G.as<double>() + j0 * ldg, ldg, part64.as<double>(), part64_cap, s);
-      }
-      CGL_HIP(hipStreamSynchronize(s));  // the staging rows are released here
+      build_gram(P.xtype, P.xtype == XT_BF16 ? Xbt.ptr : Xt.ptr, n_pad, P.n, P.p,
+                 G.as<double>(), ldg, part64.as<double>(), part64_cap, s);
     }
   }
   CGL_HIP(hipHostMalloc(&st_host, st_bytes(), hipHostMallocDefault));
@@ -787,7 +776,7 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
   };
   cgl_ctx* ctx = P.ctx;
   auto phase = [&](int which, auto&& fn) {
-    if (!ctx->profiling) return fn();
+    if (!ctx->phase_timing) return fn();
     const auto t0 = std::chrono::steady_clock::now();
     fn();
     ctx->kt_ms[which] +=

@@ -18,8 +18,9 @@ struct cgl_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   // kernel timing (cgl_ctx_set_profiling)
-  bool profiling = false;
-  bool profile_x = false;  // level 2: the batched X pass is timed too
+  bool profiling = false;    // levels 1 and 2: kernel events (launches outside graphs)
+  bool profile_x = false;    // level 2: the batched X pass is timed too
+  bool phase_timing = false; // levels 1 to 3: host wall time of the batched engine's phases
   double kt_ms[16] = {0};
   int64_t kt_n[16] = {0};
   std::vector<hipEvent_t> events;  // pool, grown on demand
@@ -109,6 +110,15 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
                  cgl_result* res, const int32_t* rows = nullptr, double* dual_out = nullptr);
 void certify_host_beta(Problem& P, const NodeHost& nh, const double* beta, double* primal,
                        double* dual);
+// G = X^T X in FP64 (p rows, leading dimension ldg), from the transposed design xt (p x n_pad,
+// the stored precision, zero past column n): rows of 256 widened, then the FP64 MFMA product
+// (part: split-K scratch of cap bytes). Synchronises the stream before it returns.
+void build_gram(int xtype, const void* xt, int64_t n_pad, int64_t n, int64_t p, double* G,
+                int64_t ldg, double* part, size_t cap, hipStream_t s);
+// Eigen-perspective shift (App. D.2): whether s <= lambda_min(X^T X) is proved by an FP64
+// Cholesky factorisation (eigen.cpp), and the largest shift such a factorisation proves.
+bool eigen_shift_proved(Problem& P, double shift);
+double eigen_shift_certified(Problem& P, double rel_tol);
 
 }  // namespace cgl
 

@@ -33,6 +33,17 @@ void launch_prox(int nodes, const double* w, int64_t w_ld, const double* h, int6
                  const uint8_t* cls, int64_t cls_ld, int64_t p, double rho, double M,
                  double two_l2, NodeDev* st, double* b_base, int64_t b_stride,
                  int64_t b_node_stride, hipStream_t stream, int want_bsq = 0);
+// The node prox for p beyond one workgroup's per-thread values (prox_paged.hip): w, cls and b
+// rows of the nodes at strides w_ld, cls_ld, b_ld; the states give k' and |F| and receive g and
+// v*.
+void launch_prox_paged(int nodes, const double* w, int64_t w_ld, const uint8_t* cls,
+                       int64_t cls_ld, int64_t p, double rho, double M, NodeDev* st, double* b,
+                       int64_t b_ld, hipStream_t stream);
+// In-place FP64 Cholesky factorisation of A - shift I (p x p, lower triangle, leading dimension
+// lda) on the stream; *fail (zero on entry) becomes 1 at the first non-positive pivot
+// (chol.hip).
+void launch_chol_factor(double* A, int64_t lda, int64_t p, double shift, int* fail,
+                        hipStream_t s);
 void launch_finish(const double* loss_part, int nloss, const double* fstar_part, int nfstar,
                    double two_l2, NodeDev* st, const double* b_base, int64_t b_stride,
                    double* b_best, int64_t p, hipStream_t stream, double shift = 0.0,

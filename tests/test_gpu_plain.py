@@ -191,3 +191,27 @@ def test_non_finite_device_X_rejected(dtype):
         assert e.value.code == _lib.E_INVAL and "non-finite" in str(e.value)
         Xb.free()
     Xd.free()
+
+
+@pytest.mark.parametrize("n,p,dtype", [(300, 60, "f64"), (2000, 1000, "f32"), (1500, 777, "bf16")])
+def test_eigen_shift_is_certified(n, p, dtype):
+    """The library proves an eigen-perspective shift before it accepts it (App. D.2 needs
+    shift <= lambda_min(X^T X)): the largest shift its FP64 Cholesky test proves lies just below
+    the exact lambda_min of the stored design (a dense eigen-solver on the CPU), a shift above
+    lambda_min is refused, and a design with n < p accepts only 0."""
+    d = synth.make_dataset(n, p, 5, loss="ls", dtype=dtype, config_id=78, k_true=5)
+    lmin = oracle.lambda_min_gram(d.X)
+    prob = _problem(d)
+    auto = prob.eigen_shift()
+    assert lmin * (1.0 - 1e-5) <= auto <= lmin, (auto, lmin)
+    prob.set_eigen(auto)
+    prob.set_eigen(lmin * (1.0 - 1e-4))
+    with pytest.raises(_lib.CglError) as e:
+        prob.set_eigen(lmin * (1.0 + 1e-4))
+    assert e.value.code == _lib.E_INVAL and "not certified" in str(e.value)
+    prob.set_eigen(0.0)
+    wide = synth.make_dataset(40, 60, 5, loss="ls", config_id=79, k_true=5)
+    pw = _problem(wide)
+    assert pw.eigen_shift() == 0.0
+    with pytest.raises(_lib.CglError):
+        pw.set_eigen(1e-3)

@@ -37,13 +37,15 @@ MixedWork::~MixedWork() {
   if (ret_gathered) (void)hipEventDestroy(ret_gathered);
   if (ret_copied) (void)hipEventDestroy(ret_copied);
   if (copy_stream) (void)hipStreamDestroy(copy_stream);
+  if (chunk_done) (void)hipEventDestroy(chunk_done);
 }
 
 static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 void MixedWork::ensure(Problem& P) {
   if (ready) return;
-  hipStream_t s = P.ctx->stream;
+  if (!stream) stream = P.ctx->stream;
+  hipStream_t s = stream;
   std::fill(want_since, want_since + kSlots, (int64_t)-1);
   // batching of the certification rounds (tuning knobs; the defaults suit the 256-slot engine)
   for (auto [name, dst] : {std::pair<const char*, int*>{"CGL_CERT_BATCH", &cert_batch},
@@ -182,6 +184,7 @@ void MixedWork::ensure(Problem& P) {
   CGL_HIP(hipStreamCreateWithFlags(&copy_stream, hipStreamNonBlocking));
   CGL_HIP(hipEventCreateWithFlags(&ret_gathered, hipEventDisableTiming));
   CGL_HIP(hipEventCreateWithFlags(&ret_copied, hipEventDisableTiming));
+  CGL_HIP(hipEventCreateWithFlags(&chunk_done, hipEventDisableTiming));
   std::memset(st_host, 0, st_bytes());
   CGL_HIP(hipMemcpyAsync(st.ptr, st_host, st_bytes(), hipMemcpyHostToDevice, s));
   CGL_HIP(hipHostMalloc(&cls_host, Sp, hipHostMallocDefault));
@@ -311,7 +314,7 @@ void MixedWork::set_split_xt(int ks) {
 // round.
 void MixedWork::tune_splits(Problem& P) {
   cgl_ctx* ctx = P.ctx;
-  hipStream_t s = ctx->stream;
+  hipStream_t s = stream;
   const char* env = std::getenv("CGL_AUTOTUNE");
   const bool tune = !(env && env[0] == '0');
   for (int pass = 0; pass < 2; ++pass) {
@@ -374,14 +377,14 @@ static bool mixed_graphs() {
 
 void MixedWork::reorder_probe(Problem& P) {
   // the counts reach the host with the chunk's state copy (the control tail of st)
-  hipStream_t s = P.ctx->stream;
+  hipStream_t s = stream;
   launch_perm_flags(md, sflag.as<uint8_t>(), s);
   launch_perm_build(sflag.as<uint8_t>(), P.p, ldp, perm_new.as<int>(), pinv_new.as<int>(),
                     ctl_dev() + kCtlUnion, s);
 }
 
 void MixedWork::reorder_apply(Problem& P) {
-  hipStream_t s = P.ctx->stream;
+  hipStream_t s = stream;
   const int* h = ctl_host();
   const int64_t grain = 2 * GT_K;
   const int64_t now = round_up(std::max(h[kCtlExtent], h[kCtlExtent + 1]), grain);
@@ -409,8 +412,8 @@ void MixedWork::reorder_apply(Problem& P) {
   reorders += 1;
 }
 
-void MixedWork::run_chunk(Problem& P) {
-  hipStream_t s = P.ctx->stream;
+void MixedWork::launch_chunk(Problem& P) {
+  hipStream_t s = stream;
   cgl_ctx* ctx = P.ctx;
   // with profiling on, each cycle's X^T pass (and at level 2 its X pass) is bracketed by HIP
   // events on the stream (HIP cannot time events recorded inside a graph, so the cycles are then
@@ -434,19 +437,25 @@ void MixedWork::run_chunk(Problem& P) {
   }
   // the operand order is checked with the chunk's own synchronisation and changed (if at all)
   // before the next launches
-  const bool probe = reorder && cycles + chunk - reorder_checked >= reorder_every;
-  if (probe) reorder_probe(P);
+  chunk_probe = reorder && cycles + chunk - reorder_checked >= reorder_every;
+  if (chunk_probe) reorder_probe(P);
   // iterates retired before this chunk go to the callers' buffers while the chunk runs
   flush_retired();
   CGL_HIP(hipMemcpyAsync(st_host, st.ptr, st_bytes(), hipMemcpyDeviceToHost, s));
-  CGL_HIP(hipStreamSynchronize(s));
+  CGL_HIP(hipEventRecord(chunk_done, s));
+  in_flight = true;
+}
+
+void MixedWork::finish_chunk(Problem& P) {
+  cgl_ctx* ctx = P.ctx;
+  in_flight = false;
   close_round(P);  // a certification round queued before this chunk has finished too
   // X-pass extent statistics (cumulative on the device): this chunk's share
   const int* h = ctl_host();
   const int es[2] = {h[kCtlExtent + 2] - ext_seen[0], h[kCtlExtent + 3] - ext_seen[1]};
   ext_seen[0] = h[kCtlExtent + 2];
   ext_seen[1] = h[kCtlExtent + 3];
-  if (probe) {
+  if (chunk_probe) {
     reorder_checked = cycles + chunk;
     reorder_apply(P);
   }
@@ -467,6 +476,12 @@ void MixedWork::run_chunk(Problem& P) {
     }
   }
   cycles += chunk;
+}
+
+void MixedWork::run_chunk(Problem& P) {
+  launch_chunk(P);
+  CGL_HIP(hipEventSynchronize(chunk_done));
+  finish_chunk(P);
 }
 
 int MixedWork::cert_round(Problem& P, bool overlap) {
@@ -500,7 +515,7 @@ int MixedWork::cert_round(Problem& P, bool overlap) {
   // left open when other nodes keep running: the next chunk is queued behind the round and its
   // synchronisation brings the round's outcome too
   overlap = overlap && nq < active;
-  hipStream_t s = P.ctx->stream;
+  hipStream_t s = stream;
   cgl_ctx* ctx = P.ctx;
   for (int sl : want) want_since[sl] = -1;
   upload_list(P, want, kListCert);
@@ -577,7 +592,7 @@ int MixedWork::free_slots() const {
 
 void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
   if (adm.empty()) return;
-  hipStream_t s = P.ctx->stream;
+  hipStream_t s = stream;
   std::vector<int> slots;
   for (const Admission& a : adm) {
     const int sl = a.slot;
@@ -652,7 +667,7 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
 void MixedWork::retire(Problem& P, const std::vector<int>& slots,
                        const std::vector<cgl_result*>& res, const std::vector<double*>& beta_out,
                        bool defer, const std::vector<double*>* dual_out) {
-  hipStream_t s = P.ctx->stream;
+  hipStream_t s = stream;
   if (dual_out) {
     for (size_t i = 0; i < slots.size(); ++i)
       if ((*dual_out)[i])
@@ -713,7 +728,7 @@ void MixedWork::upload_list(Problem& P, const std::vector<int>& v, int region) {
   int* h = list_host + (size_t)region * S;
   std::copy(v.begin(), v.end(), h);
   CGL_HIP(hipMemcpyAsync(list.ptr, h, v.size() * sizeof(int), hipMemcpyHostToDevice,
-                         P.ctx->stream));
+                         stream));
 }
 
 void MixedWork::drop_retired() {
@@ -731,7 +746,7 @@ void MixedWork::flush_retired() {
 
 void MixedWork::push_states(Problem& P) {
   CGL_HIP(hipMemcpyAsync(st.ptr, st_host, (size_t)S * sizeof(NodeDev), hipMemcpyHostToDevice,
-                         P.ctx->stream));
+                         stream));
 }
 
 void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_out,
@@ -745,7 +760,9 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
     invalid("the problem's batched engine is in use by a server; solve through the server");
   if (P.shift != 0.0)
     invalid("the eigen-perspective relaxation runs on the FP64 path (CGL_PREC_F64)");
-  hipStream_t s = P.ctx->stream;
+  if (W.in_flight) invalid("the problem's batched engine is in use by a server");
+  W.stream = P.ctx->stream;  // a server may have run it on a stream of its own
+  hipStream_t s = W.stream;
   // a solve that failed part-way may have left staged iterates for buffers that are gone
   W.drop_retired();
   std::vector<NodeHost> hosts;

@@ -86,6 +86,18 @@ struct MixedWork {
   void set_split_xt(int ks);
   void tune_splits(Problem& P);
   void ensure(Problem& P);
+  // All of the engine's device work goes to `stream`: the context's stream, or a stream of its
+  // own while a server holds the engine (set only while no work of the engine is in flight).
+  hipStream_t stream = nullptr;
+  // One chunk of cycles: launch_chunk queues it (with the reorder probe and the copy of the slot
+  // states to the host) and records chunk_done; finish_chunk, once that event has completed,
+  // takes the chunk's outcome (the open certification round, the operand order, statistics).
+  // run_chunk does both and waits in between.
+  hipEvent_t chunk_done = nullptr;
+  bool in_flight = false;
+  bool chunk_probe = false;
+  void launch_chunk(Problem& P);
+  void finish_chunk(Problem& P);
   void run_chunk(Problem& P);
   // Certification round for the nodes that asked (see the batching rule in the source). With
   // overlap, a round that leaves other nodes running is only queued (kRoundOpen): the next

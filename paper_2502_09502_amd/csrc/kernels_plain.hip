@@ -94,20 +94,47 @@ __global__ __launch_bounds__(256) void k_xb(const XT* __restrict__ X, int64_t ld
   double acc[kXbRows];
 #pragma unroll
   for (int r = 0; r < kXbRows; ++r) acc[r] = 0.0;
-  for (int64_t c0 = (int64_t)lane * N; c0 < p_pad; c0 += 64 * N) {
-    double bv[N];
-    load_dvec<N>(b + c0, bv);
+  // Rows past n read row n - 1 (a valid address) and are dropped at the store, so the loop has
+  // no branches; the next column chunk of every row is loaded before the current one is used
+  // (the last iteration reloads its own chunk), so two chunks of each row are in flight.
+  const XT* xr[kXbRows];
 #pragma unroll
-    for (int r = 0; r < kXbRows; ++r) {
-      const int64_t row = row0 + r;
-      if (row < n) {
-        double xv[N];
-        XVec<XT>::load(X + row * ldx + c0, xv);
+  for (int r = 0; r < kXbRows; ++r) xr[r] = X + min(row0 + r, n - 1) * ldx;
+  int64_t c0 = (int64_t)lane * N;
+  if (c0 < p_pad) {
+    // two register sets used in turn: one chunk is summed while the next is loading (the last
+    // chunk loads itself again, a valid address, in place of the chunk past the end)
+    double b0[N], x0[kXbRows][N], b1[N], x1[kXbRows][N];
+    auto load = [&](double (&bv)[N], double (&xv)[kXbRows][N], int64_t c) {
+      load_dvec<N>(b + c, bv);
+#pragma unroll
+      for (int r = 0; r < kXbRows; ++r) XVec<XT>::load(xr[r] + c, xv[r]);
+    };
+    auto sum = [&](const double (&bv)[N], const double (&xv)[kXbRows][N]) {
+#pragma unroll
+      for (int r = 0; r < kXbRows; ++r) {
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < N; ++i) s = fma(xv[i], bv[i], s);
+        for (int i = 0; i < N; ++i) s = fma(xv[r][i], bv[i], s);
         acc[r] += s;
       }
+    };
+    load(b0, x0, c0);
+    for (;;) {
+      int64_t c1 = c0 + 64 * N;
+      bool more = c1 < p_pad;
+      load(b1, x1, more ? c1 : c0);
+      __builtin_amdgcn_sched_barrier(0);
+      sum(b0, x0);
+      if (!more) break;
+      c0 = c1;
+      c1 = c0 + 64 * N;
+      more = c1 < p_pad;
+      load(b0, x0, more ? c1 : c0);
+      __builtin_amdgcn_sched_barrier(0);
+      sum(b1, x1);
+      if (!more) break;
+      c0 = c1;
     }
   }
   double lsum = 0.0;

@@ -1,15 +1,16 @@
 // Request server: continuous batching of node relaxations over resident problems.
 //
-// Submitted nodes wait in a FIFO queue. Each poll runs one scheduling round:
-//   1. admission: queued mixed-precision nodes take free device slots of their problem's batched
-//      engine (at most max_slots per problem); a problem whose engine is not resident yet is
-//      brought in only while the device memory of all resident engines stays within the budget
-//      (an idle engine is released when another problem needs the room);
-//   2. one FP64-path node (precision F64) is solved to completion, if one is queued;
-//   3. every engine with running slots advances one chunk of iterations and its certification
-//      round; finished, cancelled or certified slots are retired and refilled on the next round.
-// Results wait in a completion list until polled. Everything runs on the context's stream from
-// the calling thread; calls on one server must be serialised by the caller.
+// Submitted nodes wait in a FIFO queue. Every problem with queued or running mixed-precision
+// nodes holds its batched engine (brought in while the device memory of the resident engines
+// stays within the budget; an idle engine is released when another problem needs the room), and
+// each resident engine runs on a HIP stream of its own, so engines of different designs advance
+// independently and overlap on the device. An engine's turn, taken whenever its previous chunk
+// has completed: take the chunk's outcome, run or queue its certification round, retire finished,
+// certified or cancelled slots, admit queued nodes into free slots (at most max_slots per
+// problem), and launch the next chunk of iterations. A poll starts the idle engines, solves one
+// queued FP64-path node on the context's stream while the engines run, and then serves the
+// engines whose chunks have completed (waiting for the first one if none has). Results wait in a
+// completion list until polled. Calls on one server must be serialised by the caller.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,6 +18,7 @@
 #include <cmath>
 #include <deque>
 #include <memory>
+#include <thread>
 #include <vector>
 
 #include "batch.h"
@@ -50,9 +52,11 @@ struct Finished {
   double latency = 0.0;
 };
 
-// A problem whose batched engine is resident, with the request held by each of its slots.
+// A problem whose batched engine is resident, with the request held by each of its slots and
+// the stream the engine runs on while the server holds it.
 struct Resident {
   Problem* P = nullptr;
+  hipStream_t stream = nullptr;
   std::vector<std::unique_ptr<Request>> slot_req;  // kSlots entries
   int running() const {
     int c = 0;
@@ -103,6 +107,17 @@ size_t resident_bytes(const cgl_server& S) {
   return b;
 }
 
+// Hand the engine back to the context's stream and drop the server's stream (nothing of the
+// engine is in flight).
+void release_stream(Resident& R) {
+  if (R.P->mixed) R.P->mixed->stream = R.P->ctx->stream;
+  if (R.stream) {
+    (void)hipStreamSynchronize(R.stream);
+    (void)hipStreamDestroy(R.stream);
+    R.stream = nullptr;
+  }
+}
+
 bool has_queued(const cgl_server& S, const Problem* P) {
   for (const auto& r : S.queue)
     if (r->P == P && r->node.precision == CGL_PREC_MIXED) return true;
@@ -117,7 +132,8 @@ Resident* make_resident(cgl_server& S, Problem* P) {
     // release idle engines (no running slot, nothing queued)
     for (size_t i = 0; i < S.resident.size();) {
       Resident& R = S.resident[i];
-      if (R.running() == 0 && !has_queued(S, R.P)) {
+      if (R.running() == 0 && !has_queued(S, R.P) && !(R.P->mixed && R.P->mixed->in_flight)) {
+        release_stream(R);
         delete R.P->mixed;
         R.P->mixed = nullptr;
         S.resident.erase(S.resident.begin() + (ptrdiff_t)i);
@@ -142,44 +158,86 @@ Resident* make_resident(cgl_server& S, Problem* P) {
   Resident R;
   R.P = P;
   R.slot_req.resize((size_t)P->mixed->S);
+  CGL_HIP(hipStreamCreateWithFlags(&R.stream, hipStreamNonBlocking));  // default priority
   S.resident.push_back(std::move(R));
   return &S.resident.back();
 }
 
-void admit_round(cgl_server& S) {
-  // reserve slots in queue order, then admit per problem in one call each
-  std::vector<Problem*> blocked;
-  std::vector<std::pair<Problem*, std::vector<Admission>>> batches;
+// Engines for the problems of queued mixed-precision nodes, in queue order, as the budget allows.
+void bring_in(cgl_server& S) {
+  std::vector<Problem*> seen;
+  for (const auto& q : S.queue) {
+    if (q->node.precision != CGL_PREC_MIXED) continue;
+    if (std::find(seen.begin(), seen.end(), q->P) != seen.end()) continue;
+    seen.push_back(q->P);
+    make_resident(S, q->P);
+  }
+}
+
+// Queued nodes of R's problem into its free slots (the engine is idle), in queue order.
+void admit_for(cgl_server& S, Resident& R) {
+  MixedWork& W = *R.P->mixed;
+  std::vector<Admission> adm;
   for (auto it = S.queue.begin(); it != S.queue.end();) {
     Request& q = **it;
-    if (q.node.precision != CGL_PREC_MIXED ||
-        std::find(blocked.begin(), blocked.end(), q.P) != blocked.end()) {
+    if (q.P != R.P || q.node.precision != CGL_PREC_MIXED) {
       ++it;
       continue;
     }
-    Resident* R = make_resident(S, q.P);
+    if (R.running() >= S.max_slots) break;
     int slot = -1;
-    if (R && R->running() < S.max_slots) {
-      const MixedWork& W = *q.P->mixed;
-      for (int sl = 0; sl < W.S; ++sl)
-        if (W.slot_owner[(size_t)sl] < 0 && !R->slot_req[(size_t)sl]) { slot = sl; break; }
-    }
-    if (slot < 0) {
-      blocked.push_back(q.P);
-      ++it;
-      continue;
-    }
-    auto bt = std::find_if(batches.begin(), batches.end(),
-                           [&](const auto& b) { return b.first == q.P; });
-    if (bt == batches.end()) {
-      batches.emplace_back(q.P, std::vector<Admission>());
-      bt = batches.end() - 1;
-    }
-    bt->second.push_back(Admission{slot, slot, q.node, q.host});
-    R->slot_req[(size_t)slot] = std::move(*it);
+    for (int sl = 0; sl < W.S; ++sl)
+      if (W.slot_owner[(size_t)sl] < 0 && !R.slot_req[(size_t)sl]) { slot = sl; break; }
+    if (slot < 0) break;
+    adm.push_back(Admission{slot, slot, q.node, q.host});
+    R.slot_req[(size_t)slot] = std::move(*it);
     it = S.queue.erase(it);
   }
-  for (auto& b : batches) b.first->mixed->admit(*b.first, b.second);
+  W.admit(*R.P, adm);
+}
+
+// Finished, certified or cancelled slots of R to the completion list (the engine is idle).
+void retire_for(cgl_server& S, Resident& R) {
+  Problem& P = *R.P;
+  MixedWork& W = *P.mixed;
+  std::vector<int> done;
+  for (int sl = 0; sl < W.S; ++sl) {
+    const std::unique_ptr<Request>& r = R.slot_req[(size_t)sl];
+    if (r && (W.st_host[sl].done || r->cancelled)) done.push_back(sl);
+  }
+  if (done.empty()) return;
+  std::vector<cgl_result> res(done.size());
+  std::vector<std::vector<double>> betas(done.size(), std::vector<double>((size_t)P.p));
+  std::vector<cgl_result*> rs;
+  std::vector<double*> bs;
+  for (size_t i = 0; i < done.size(); ++i) {
+    rs.push_back(&res[i]);
+    bs.push_back(betas[i].data());
+  }
+  W.retire(P, done, rs, bs);
+  for (size_t i = 0; i < done.size(); ++i) {
+    std::unique_ptr<Request>& r = R.slot_req[(size_t)done[i]];
+    if (r->cancelled) res[i].status = CGL_CANCELLED;
+    finish(S, std::move(r), res[i], std::move(betas[i]));
+  }
+  // a cancelled slot still runs on the device until its state says inactive
+  W.push_states(P);
+  CGL_HIP(hipStreamSynchronize(W.stream));
+}
+
+// One turn of an engine that has no work in flight (see the file comment).
+void engine_turn(cgl_server& S, Resident& R) {
+  Problem& P = *R.P;
+  MixedWork& W = *P.mixed;
+  W.stream = R.stream;
+  if (W.in_flight) W.finish_chunk(P);
+  if (W.cert_round(P, /*overlap=*/true) == MixedWork::kRoundOpen) {
+    W.launch_chunk(P);  // queued behind the round; retirement after it
+    return;
+  }
+  retire_for(S, R);
+  admit_for(S, R);
+  if (R.running() > 0) W.launch_chunk(P);
 }
 
 void plain_round(cgl_server& S) {
@@ -191,40 +249,31 @@ void plain_round(cgl_server& S) {
     std::vector<double> beta((size_t)r->P->p);
     solve_plain(*r->P, r->node, r->host, beta.data(), &res);
     finish(S, std::move(r), res, std::move(beta));
-    return;  // one per round keeps the batched slots moving
+    return;  // one per poll
   }
 }
 
 void run_round(cgl_server& S) {
-  for (auto& R : S.resident) {
-    if (R.running() == 0) continue;
-    Problem& P = *R.P;
-    MixedWork& W = *P.mixed;
-    W.run_chunk(P);
-    W.cert_round(P);
-    std::vector<int> done;
-    for (int sl = 0; sl < W.S; ++sl) {
-      const std::unique_ptr<Request>& r = R.slot_req[(size_t)sl];
-      if (r && (W.st_host[sl].done || r->cancelled)) done.push_back(sl);
+  // idle engines with work take a turn (their chunks then run while the host goes on)
+  for (auto& R : S.resident)
+    if (!R.P->mixed->in_flight && (R.running() > 0 || has_queued(S, R.P))) engine_turn(S, R);
+  // an FP64-path node on the context's stream, beside the engines' chunks
+  plain_round(S);
+  // engines whose chunks have completed take their turn; wait for the first one if none has
+  for (;;) {
+    bool any = false, served = false;
+    for (auto& R : S.resident) {
+      MixedWork& W = *R.P->mixed;
+      if (!W.in_flight) continue;
+      any = true;
+      const hipError_t q = hipEventQuery(W.chunk_done);
+      if (q == hipErrorNotReady) continue;
+      CGL_HIP(q);
+      engine_turn(S, R);
+      served = true;
     }
-    if (!done.empty()) {
-      std::vector<cgl_result> res(done.size());
-      std::vector<std::vector<double>> betas(done.size(), std::vector<double>((size_t)P.p));
-      std::vector<cgl_result*> rs;
-      std::vector<double*> bs;
-      for (size_t i = 0; i < done.size(); ++i) {
-        rs.push_back(&res[i]);
-        bs.push_back(betas[i].data());
-      }
-      W.retire(P, done, rs, bs);
-      for (size_t i = 0; i < done.size(); ++i) {
-        std::unique_ptr<Request>& r = R.slot_req[(size_t)done[i]];
-        if (r->cancelled) res[i].status = CGL_CANCELLED;
-        finish(S, std::move(r), res[i], std::move(betas[i]));
-      }
-      W.push_states(P);
-      CGL_HIP(hipStreamSynchronize(P.ctx->stream));
-    }
+    if (!any || served) return;
+    std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
 }
 
@@ -299,8 +348,7 @@ int cgl_server_poll(cgl_server* srv, int32_t max, uint64_t* tickets, cgl_result*
   if (max < 0) invalid("max < 0");
   if (max > 0 && (!tickets || !res)) invalid("tickets and res are required when max > 0");
   CGL_HIP(hipSetDevice(srv->ctx->device));
-  admit_round(*srv);
-  plain_round(*srv);
+  bring_in(*srv);
   run_round(*srv);
   // results are taken in completion order while their solution fits the caller's stride: the
   // first one that does not stays queued (and is refused here only when it is the first)
@@ -371,13 +419,19 @@ int cgl_server_destroy(cgl_server* srv) {
     // free the slots held by unfinished requests so the problem's engine stays usable
     MixedWork* W = R.P->mixed;
     if (!W) continue;
+    W->stream = R.stream;
+    if (W->in_flight) {
+      CGL_HIP(hipEventSynchronize(W->chunk_done));
+      W->finish_chunk(*R.P);
+    }
     for (int sl = 0; sl < W->S; ++sl)
       if (R.slot_req[(size_t)sl]) {
         W->st_host[sl].active = 0;
         W->slot_owner[(size_t)sl] = -1;
       }
     W->push_states(*R.P);
-    CGL_HIP(hipStreamSynchronize(R.P->ctx->stream));
+    CGL_HIP(hipStreamSynchronize(R.stream));
+    release_stream(R);
   }
   delete srv;
   return CGL_OK;

@@ -184,9 +184,12 @@ int cgl_problem_lipschitz(const cgl_problem* prob, double* L);
  * completion on the device (delta = 4 (n + p + 2) 2^-53 trace(G) covers the rounding of G and of
  * the factorisation; cgl_problem_eigen_shift finds the largest such shift). With n < p only
  * shift 0 is valid. L becomes 2 (1.002 lambda_max(X^T X) - shift).
- * Errors: CGL_E_INVAL for another loss, shift < 0, shift >= lambda_max, or a shift the
- * factorisation does not prove. Batched (MIXED) solves and cgl_certify reject a shifted problem;
- * shift = 0 restores the perspective one. */
+ * Both paths solve the shifted problem: the FP64 path, and the batched engine (CGL_PREC_MIXED,
+ * also through a server), whose FP64 certificate and bound witness (cgl_solve_batch_dual) then
+ * follow the bound above at the certified iterate. cgl_certify rejects a shifted problem;
+ * shift = 0 restores the perspective one.
+ * Errors: CGL_E_INVAL for another loss, shift < 0, shift >= lambda_max, a shift the
+ * factorisation does not prove, or while a server runs nodes of the problem. */
 int cgl_problem_set_eigen(cgl_problem* prob, double shift);
 
 /* The largest shift that the Cholesky test of cgl_problem_set_eigen proves, found by bisection

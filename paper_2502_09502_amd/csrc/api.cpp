@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/certglm.h"
+#include "batch.h"
 #include "engine.h"
 #include "kernels.h"
 #include "losses.h"
@@ -606,6 +607,8 @@ int cgl_problem_set_eigen(cgl_problem* prob, double shift) {
   Problem& P = *reinterpret_cast<Problem*>(prob);
   if (P.loss != LOSS_LS) invalid("the eigen-perspective relaxation is for least squares");
   if (!(shift >= 0.0) || !std::isfinite(shift)) invalid("shift must be >= 0");
+  if (P.mixed && (P.mixed->in_flight || P.mixed->free_slots() != P.mixed->S))
+    invalid("the problem's batched engine holds running nodes (a server's)");
   CGL_HIP(hipSetDevice(P.ctx->device));
   if (P.lam_max <= 0.0) P.lam_max = power_lambda_max(P);
   if (shift >= P.lam_max) invalid("shift must be below lambda_max(X^T X)");

@@ -204,6 +204,7 @@ void MixedWork::ensure(Problem& P) {
   md.M = P.M;
   md.L = P.L;
   md.rho = P.rho;
+  md.shift = P.shift;
   md.slots = S;
   md.S_pad = S_pad;
   md.st = st.as<NodeDev>();
@@ -277,6 +278,18 @@ void MixedWork::ensure(Problem& P) {
   CGL_HIP(hipStreamSynchronize(s));
   tune_splits(P);
   ready = true;
+}
+
+void MixedWork::set_relaxation(Problem& P) {
+  if (md.L == P.L && md.rho == P.rho && md.shift == P.shift) return;
+  md.L = P.L;
+  md.rho = P.rho;
+  md.shift = P.shift;
+  // the kernels of a captured chunk hold the old values
+  if (graph_exec) {
+    CGL_HIP(hipGraphExecDestroy(graph_exec));
+    graph_exec = nullptr;
+  }
 }
 
 std::vector<int> MixedWork::split_candidates(int64_t m_tiles, int64_t K) {
@@ -758,9 +771,10 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
   W.ensure(P);
   if (W.free_slots() != W.S)
     invalid("the problem's batched engine is in use by a server; solve through the server");
-  if (P.shift != 0.0)
-    invalid("the eigen-perspective relaxation runs on the FP64 path (CGL_PREC_F64)");
+  if (P.shift != 0.0 && P.loss != LOSS_LS)
+    invalid("the eigen-perspective relaxation is for least squares");
   if (W.in_flight) invalid("the problem's batched engine is in use by a server");
+  W.set_relaxation(P);
   W.stream = P.ctx->stream;  // a server may have run it on a stream of its own
   hipStream_t s = W.stream;
   // a solve that failed part-way may have left staged iterates for buffers that are gone

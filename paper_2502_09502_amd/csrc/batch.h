@@ -86,6 +86,9 @@ struct MixedWork {
   void set_split_xt(int ks);
   void tune_splits(Problem& P);
   void ensure(Problem& P);
+  // Take the problem's step size and eigen-perspective shift (they change with
+  // cgl_problem_set_eigen); a captured chunk is re-captured. Only while nothing is in flight.
+  void set_relaxation(Problem& P);
   // All of the engine's device work goes to `stream`: the context's stream, or a stream of its
   // own while a server holds the engine (set only while no work of the engine is in flight).
   hipStream_t stream = nullptr;

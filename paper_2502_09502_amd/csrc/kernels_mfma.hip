@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void k_mixed_resid(MixedDev md) {
     for (int i = threadIdx.x; i < md.nrt; i += 64) a += md.lpart[(int64_t)slot * md.nrt + i];
     a = wave_sum(a);
     if (threadIdx.x == 0) {
-      const double Lnew = a + 2.0 * md.lam2 * st->g_new;
+      const double Lnew = a - md.shift * st->bsq_new + 2.0 * (md.lam2 + md.shift) * st->g_new;
       double phi = st->phi;
       int primed = st->primed, restarts = st->restarts;
       if (!primed) {
@@ -307,12 +307,30 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
       if (j < p) pv.set(s, pv.get(s) + (double)dq[j]);
     }
   }
+  // eigen-perspective shift: the gradient at gamma is X^T grad f(X gamma) - 2 s gamma, and the
+  // bound gains s ||gamma||^2 (uniform branch: the shift is a launch argument)
+  const double shift = md.shift;
+  const double two_le = 2.0 * (md.lam2 + shift);
+  double gsq = 0.0;
+  if (shift != 0.0) {
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
+      if (j < p) {
+        const double x1 = bt1[j];
+        const double gam = x1 + c * (x1 - bt0[j]);
+        pv.set(s, pv.get(s) - 2.0 * shift * gam);
+        gsq += gam * gam;
+      }
+    }
+    gsq = bsum(gsq, sm);
+  }
   // dual monitor at gamma: D = -F*(-zeta) - 2 lambda2 g_node*(-grad F(gamma) / (2 lambda2))
   // element-indexed view of the LDS slice for the warm-started selections
   const double* slice = ProxVals<E>::lds ? vbuf : nullptr;
   double gs = 0.0;
   if (check)
-    gs = gstar_node<E>([&](int s) { return fabs(pv.get(s)); }, 2.0 * md.lam2, cb, st->kp,
+    gs = gstar_node<E>([&](int s) { return fabs(pv.get(s)); }, two_le, cb, st->kp,
                        st->nfree, md.M, sm, slice, md.prevtop + (int64_t)slot * 65);
   // gradient step w = gamma - H / L; the slice then holds u = rho |w|, the signs a mask
   uint32_t neg = 0;
@@ -333,10 +351,12 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
   __shared__ int ext_s;
   if (threadIdx.x == 0) ext_s = 0;
   __syncthreads();
+  double bsq = 0.0;
   const ProxOut po = node_prox<E>(
       [&](int s) { return pv.get(s); }, neg, cb, st->kp, st->nfree, md.rho, md.M, st->vstar,
       [&](int s, double b) {
         const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
+        bsq += b * b;
         if (j < p) {
           bout[j] = b;
           const int pos = md.pinv[j];
@@ -409,11 +429,13 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
       fs += md.fpart[(int64_t)slot * md.nrt + i];
     fs = bsum(fs, sm);
   }
+  if (shift != 0.0) bsq = bsum(bsq, sm);
   if (threadIdx.x == 0) {
     st->g_new = po.gval;
+    st->bsq_new = shift != 0.0 ? bsq : 0.0;
     st->vstar = po.vstar;
     if (check) {
-      const double D = -fs - 2.0 * md.lam2 * gs;
+      const double D = -fs - two_le * gs + shift * gsq;
       if (D > st->D_best) st->D_best = D;  // working-precision monitor
     }
     const double Pw = st->P_best, Dw = st->D_best;
@@ -595,28 +617,37 @@ __global__ __launch_bounds__(1024) void k_cert_finish(MixedDev md, const int* li
   ProxVals<E> hv;
   hv.sl = vbuf;
   uint64_t cb = 0;
+  // eigen-perspective shift s: the gradient at beta is X^T grad f(X beta) - 2 s beta, the
+  // objective loses s ||beta||^2 and the bound gains it (App. D.2); 0 for the perspective bound
+  const double shift = md.shift;
+  const double two_le = 2.0 * (md.lam2 + shift);
+  double bsq = 0.0;
 #pragma unroll
   for (int s = 0; s < E; ++s) {
     const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
     if (j < p) {
-      hv.set(s, fabs(H64[(int64_t)q * md.ldp + j]));
+      const double b = B64[(int64_t)q * md.ldp + j];
+      hv.set(s, fabs(H64[(int64_t)q * md.ldp + j] - 2.0 * shift * b));
+      bsq += b * b;
       cb |= (uint64_t)cl[j] << (2 * s);
     } else {
       hv.set(s, 0.0);
       cb |= (uint64_t)CLS_PAD << (2 * s);
     }
   }
-  const double gs = gstar_node<E>([&](int s) { return hv.get(s); }, 2.0 * md.lam2, cb, st->kp,
+  const double gs = gstar_node<E>([&](int s) { return hv.get(s); }, two_le, cb, st->kp,
                                   st->nfree, md.M, sm);
-  double acc[2] = {0.0, 0.0};
+  double acc[3] = {0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < nchunk; i += blockDim.x) {
     acc[0] += part[((int64_t)q * nchunk + i) * 2];
     acc[1] += part[((int64_t)q * nchunk + i) * 2 + 1];
   }
-  block_sum_n<2>(acc, sm);
+  acc[2] = bsq;
+  block_sum_n<3>(acc, sm);
   if (threadIdx.x == 0) {
-    const double P = acc[0] + 2.0 * md.lam2 * st->g_new;  // g of the gathered iterate
-    const double D = -acc[1] - 2.0 * md.lam2 * gs;
+    const double sq = shift != 0.0 ? acc[2] : 0.0;
+    const double P = acc[0] - shift * sq + two_le * st->g_new;  // g of the gathered iterate
+    const double D = -acc[1] + shift * sq - two_le * gs;
     int improve = 0;
     if (P < st->P_cert) { st->P_cert = P; improve = 1; }
     if (D > st->D_cert) { st->D_cert = D; improve |= 2; }

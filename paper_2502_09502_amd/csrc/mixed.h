@@ -18,6 +18,9 @@ struct MixedDev {
   const double* y;      // n_pad (zero padded)
   int loss;
   double lam2, M, L, rho;
+  double shift;         // eigen-perspective shift s (App. D.2; least squares), 0 otherwise: the
+                        // gradient gains -2 s gamma, the objective -s ||beta||^2, the regulariser
+                        // weight is 2 (lambda2 + s) and the bound gains s ||point||^2
   // slots
   int slots;            // S
   int S_pad;            // operand rows, multiple of 256

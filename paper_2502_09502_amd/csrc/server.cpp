@@ -231,6 +231,7 @@ void engine_turn(cgl_server& S, Resident& R) {
   MixedWork& W = *P.mixed;
   W.stream = R.stream;
   if (W.in_flight) W.finish_chunk(P);
+  W.set_relaxation(P);  // the shift changes only while the engine holds no node
   if (W.cert_round(P, /*overlap=*/true) == MixedWork::kRoundOpen) {
     W.launch_chunk(P);  // queued behind the round; retirement after it
     return;
@@ -307,8 +308,6 @@ int cgl_server_submit(cgl_server* srv, cgl_problem* prob, const cgl_node* node,
   if (!srv || !prob || !node || !ticket) invalid("NULL argument");
   Problem* P = reinterpret_cast<Problem*>(prob);
   if (P->ctx != srv->ctx) invalid("the problem belongs to another context");
-  if (P->shift != 0.0 && node->precision == CGL_PREC_MIXED)
-    invalid("the eigen-perspective relaxation runs on the FP64 path (CGL_PREC_F64)");
   if (srv->queue.size() >= kQueueCap) {
     set_error("server queue is full");
     return CGL_E_BUSY;

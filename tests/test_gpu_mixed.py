@@ -313,3 +313,48 @@ def test_poisson_gamma_with_given_L_plain_and_mixed(loss):
             assert rel(r.primal, ref.primal) <= 1e-6, (prec, r.primal, ref.primal)
             # the relaxation can be exact (box binding on k coordinates): equal up to rounding
             assert r.lower_bound <= ref.primal + 1e-12 * max(1.0, abs(ref.primal))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "bf16"])
+def test_eigen_perspective_on_the_batched_engine(dtype):
+    """The eigen-perspective relaxation (App. D.2) on the batched engine, with the shift the
+    library proves (cgl_problem_eigen_shift): every node's certified objective matches the
+    oracle's eigen-perspective optimum, its bound is the oracle's D_eig at the returned witness and
+    never above that optimum, it is at least the perspective bound of the same node, and a server
+    gives the same results; shift 0 restores the perspective relaxation on the engine."""
+    d = synth.make_dataset(600, 120, 5, loss="ls", dtype=dtype, config_id=81, k_true=5)
+    prob = _problem(d)
+    sets = [((), ())] + synth.node_sets(d.p, d.k, 6, 10, config_id=81)
+    persp = prob.solve_batch(_specs(prob, sets))
+    shift = prob.eigen_shift()
+    assert 0.0 < shift <= oracle.lambda_min_gram(d.X)
+    prob.set_eigen(shift)
+    res, duals = prob.solve_batch_dual(_specs(prob, sets))
+    for (z0, z1), r, wd, r0 in zip(sets, res, duals, persp):
+        ns = oracle.node_sets(d.p, z0, z1)
+        ref = oracle.solve_node_eig(d.X, d.y, d.lam2, d.M, d.k, shift, z0, z1, tol=1e-10)
+        assert r.status == "converged" and r.gap_rel <= 1e-6, r
+        assert rel(r.primal, ref.primal) <= 1e-6, (r.primal, ref.primal)
+        assert r.lower_bound <= ref.primal
+        Pb = oracle.eig_primal_value(d.X, d.y, d.lam2, d.M, d.k, ns, r.beta, shift)
+        assert rel(Pb, r.primal) <= 1e-10, (Pb, r.primal)
+        Dw = oracle.eig_dual_value(d.X, d.y, d.lam2, d.M, d.k, ns, wd, shift)
+        assert abs(Dw - r.lower_bound) <= 1e-10 * max(abs(r.primal), 1.0), (Dw, r.lower_bound)
+        assert r.lower_bound >= r0.lower_bound - 2e-6 * max(abs(r0.primal), 1.0)
+    srv = _lib.Server(ctx(), 0, 256)
+    tickets = [srv.submit(prob, s) for s in _specs(prob, sets)]
+    out = {}
+    for _ in range(20000):
+        for t, r, _ in srv.poll(64):
+            out[t] = r
+        if len(out) == len(tickets):
+            break
+    srv.close()
+    for t, r in zip(tickets, res):
+        assert out[t].status == "converged"
+        assert rel(out[t].primal, r.primal) <= 1e-6
+        assert abs(out[t].lower_bound - r.lower_bound) <= 2e-6 * max(abs(r.primal), 1.0)
+    prob.set_eigen(0.0)
+    back = prob.solve_batch(_specs(prob, sets[:2]))
+    for r, r0 in zip(back, persp[:2]):
+        assert rel(r.primal, r0.primal) <= 1e-6

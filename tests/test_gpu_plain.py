@@ -139,7 +139,7 @@ def test_config2_full_size_properties():
 def test_eigen_perspective_relaxation():
     """Eigen-perspective relaxation (App. D.2) on the FP64 path: the certified objective matches
     the oracle's, the bound is at least the perspective one and never above the oracle's optimum;
-    other losses, negative shifts, batched solves and cgl_certify reject it."""
+    other losses, negative shifts and cgl_certify reject it."""
     d = synth.make_dataset(300, 60, 5, loss="ls", config_id=77, k_true=5)
     lmin = oracle.lambda_min_gram(d.X)
     assert lmin > 0
@@ -155,8 +155,6 @@ def test_eigen_perspective_relaxation():
         assert rel(r.primal, ref.primal) <= 1e-6, (r.primal, ref.primal)
         assert r.lower_bound <= ref.primal
         assert r.lower_bound >= s0.lower_bound - 1e-6 * abs(s0.primal)
-    with pytest.raises(_lib.CglError):
-        prob.solve_batch([prob.node(precision="mixed")])
     with pytest.raises(_lib.CglError):
         prob.certify(np.zeros(d.p))
     with pytest.raises(_lib.CglError):

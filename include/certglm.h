@@ -278,8 +278,11 @@ int cgl_server_create(cgl_ctx* ctx, size_t hbm_budget_bytes, int32_t max_slots,
  * queue is full. */
 int cgl_server_submit(cgl_server* srv, cgl_problem* prob, const cgl_node* node,
                       uint64_t* ticket);
-/* Advance the device work by one scheduling round (admit, run one chunk per active problem,
- * retire), then return up to max finished results in completion order: tickets[i], res[i],
+/* Advance the device work: resident engines (each on a stream of its own) and queued FP64-path
+ * nodes that are idle start their next chunk of iterations (after retiring finished slots and
+ * admitting queued nodes), then every engine or node whose chunk has completed is served; the
+ * call waits for the first completion when none has happened yet. Then it returns up to max
+ * finished results in completion order: tickets[i], res[i],
  * and, if betas is not NULL, the p_i doubles of result i's solution at betas + i * betas_stride
  * (the rest of that row is left as it was). A result whose p exceeds betas_stride stays queued:
  * the call returns the results before it (CGL_E_INVAL, with nothing taken, when it is the first

@@ -2,8 +2,12 @@
 // utilities. The batched mixed-precision engine and the server live in batch.cpp / server.cpp.
 #include <hip/hip_runtime.h>
 
+#include <sys/stat.h>
+
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
@@ -26,6 +30,46 @@ hipEvent_t cgl_ctx::event(size_t i) {
     events.push_back(e);
   }
   return events[i];
+}
+
+// Tuning cache: one line per choice, "<arch> <pass> <M> <K> <nodes> <split>". CGL_TUNE_CACHE
+// names the file ("0" or an empty value: no file); otherwise $XDG_CACHE_HOME/certglm/splits.txt
+// or $HOME/.cache/certglm/splits.txt. A file that cannot be read or written is ignored.
+static std::string tune_cache_path() {
+  const char* e = std::getenv("CGL_TUNE_CACHE");
+  if (e) return (e[0] == '\0' || (e[0] == '0' && e[1] == '\0')) ? std::string() : std::string(e);
+  if (const char* x = std::getenv("XDG_CACHE_HOME")) return std::string(x) + "/certglm/splits.txt";
+  if (const char* h = std::getenv("HOME")) return std::string(h) + "/.cache/certglm/splits.txt";
+  return std::string();
+}
+
+void cgl_ctx::load_tuning() {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  char a[64];
+  long long pass, m, k, nodes;
+  int ks;
+  while (std::fscanf(f, "%63s %lld %lld %lld %lld %d", a, &pass, &m, &k, &nodes, &ks) == 6)
+    if (arch == a && ks >= 1) tuned_split[{pass, m, k, nodes}] = ks;
+  std::fclose(f);
+}
+
+void cgl_ctx::save_tuning(const std::array<int64_t, 4>& key, int choice) const {
+  const std::string path = tune_cache_path();
+  if (path.empty() || arch.empty()) return;
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos && slash > 0) {
+    // create the directory chain (one level per component; errors are ignored)
+    for (size_t q = path.find('/', 1); q != std::string::npos && q <= slash; q = path.find('/', q + 1))
+      (void)mkdir(path.substr(0, q).c_str(), 0755);
+  }
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "%s %lld %lld %lld %lld %d\n", arch.c_str(), (long long)key[0],
+               (long long)key[1], (long long)key[2], (long long)key[3], choice);
+  std::fclose(f);
 }
 
 cgl_ctx::~cgl_ctx() {
@@ -229,12 +273,14 @@ void PlainWork::ensure(Problem& P) {
   st.alloc(sizeof(NodeDev));
   gsq.alloc((size_t)((P.ldx + 255) / 256) * 8);
   CGL_HIP(hipHostMalloc(&st_host, sizeof(NodeDev), hipHostMallocDefault));
+  CGL_HIP(hipEventCreateWithFlags(&chunk_ev, hipEventDisableTiming));
   ready = true;
 }
 
 PlainWork::~PlainWork() {
   if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
   if (st_host) (void)hipHostFree(st_host);
+  if (chunk_ev) (void)hipEventDestroy(chunk_ev);
 }
 
 // One iteration of Alg. 3 on the plain path. ev (optional): four events bracketing the X^T pass
@@ -267,11 +313,14 @@ static bool use_graphs() {
   return !(e && e[0] == '1');
 }
 
-void solve_plain(Problem& P, const cgl_node& nd, const NodeHost& nh, double* beta_out,
-                 cgl_result* res) {
+// The plain solve in steps, so that a caller (the server) can advance it between other work:
+// plain_begin sets the node up and queues its first objective, plain_launch queues a chunk of
+// iterations with the copy of the state to the host and the chunk event, plain_after_chunk (once
+// the event has completed) books the kernel timing and says whether the node is finished, and
+// plain_end writes the result and the solution.
+void plain_begin(Problem& P, const cgl_node& nd, const NodeHost& nh, hipStream_t s) {
   PlainWork& W = P.plain;
   W.ensure(P);
-  hipStream_t s = P.ctx->stream;
   const int64_t p = P.p;
   // state, classes, initial iterate (ring slots 0 and 1 hold beta^0 = beta^1)
   NodeDev st0 = make_node_dev(nd, nh);
@@ -280,68 +329,91 @@ void solve_plain(Problem& P, const cgl_node& nd, const NodeHost& nh, double* bet
   CGL_HIP(hipMemsetAsync(W.bbest.ptr, 0, P.ldx * 8, s));
   double L0_g = 0.0;
   if (nd.warm_start) {
-    std::vector<double> ws(nd.warm_start, nd.warm_start + p);
+    W.warm.assign(nd.warm_start, nd.warm_start + p);
     for (int64_t j = 0; j < p; ++j)
-      if (nh.cls[(size_t)j] == CLS_ZERO) ws[(size_t)j] = 0.0;
+      if (nh.cls[(size_t)j] == CLS_ZERO) W.warm[(size_t)j] = 0.0;
     for (int slot = 0; slot < 2; ++slot)
-      CGL_HIP(hipMemcpyAsync(W.bring.as<double>() + slot * P.ldx, ws.data(), p * 8,
+      CGL_HIP(hipMemcpyAsync(W.bring.as<double>() + slot * P.ldx, W.warm.data(), p * 8,
                              hipMemcpyHostToDevice, s));
     L0_g = HUGE_VAL;  // the objective of an arbitrary start is not used for the restart test
   }
-  CGL_HIP(hipMemcpyAsync(W.st.ptr, &st0, sizeof(NodeDev), hipMemcpyHostToDevice, s));
+  W.st0 = st0;
+  CGL_HIP(hipMemcpyAsync(W.st.ptr, &W.st0, sizeof(NodeDev), hipMemcpyHostToDevice, s));
   launch_xb(P.xtype, P.X.ptr, P.ldx, P.n, P.ldx, W.bring.as<double>() + P.ldx, 0,
             W.uring.as<double>() + P.n, 0, nullptr, P.y.as<double>(), P.loss,
             W.lpart.as<double>(), s);
   CGL_HIP(hipMemcpyAsync(W.uring.as<double>(), W.uring.as<double>() + P.n, P.n * 8,
                          hipMemcpyDeviceToDevice, s));
   launch_init_state(W.lpart.as<double>(), W.geom.nxb, L0_g, W.st.as<NodeDev>(), s);
-
-  const int chunk = 8;
   if (use_graphs() && !W.graph_exec) {
     hipGraph_t graph;
     CGL_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < chunk; ++i) plain_iteration(P, W, s);
+    for (int i = 0; i < PlainWork::kChunk; ++i) plain_iteration(P, W, s);
     CGL_HIP(hipStreamEndCapture(s, &graph));
     CGL_HIP(hipGraphInstantiate(&W.graph_exec, graph, nullptr, nullptr, 0));
     CGL_HIP(hipGraphDestroy(graph));
   }
-  NodeDev* sh = W.st_host;
+  W.iter_before = 1;
+}
+
+void plain_launch(Problem& P, hipStream_t s) {
+  PlainWork& W = P.plain;
   cgl_ctx* ctx = P.ctx;
-  int iter_before = 1;
-  for (;;) {
-    if (ctx->profiling) {
-      for (int i = 0; i < chunk; ++i) {
-        hipEvent_t ev[4] = {ctx->event(4 * i), ctx->event(4 * i + 1), ctx->event(4 * i + 2),
-                            ctx->event(4 * i + 3)};
-        plain_iteration(P, W, s, ev);
-      }
-    } else if (W.graph_exec) {
-      CGL_HIP(hipGraphLaunch(W.graph_exec, s));
-    } else {
-      for (int i = 0; i < chunk; ++i) plain_iteration(P, W, s);
+  if (ctx->profiling) {
+    for (int i = 0; i < PlainWork::kChunk; ++i) {
+      hipEvent_t ev[4] = {ctx->event(4 * i), ctx->event(4 * i + 1), ctx->event(4 * i + 2),
+                          ctx->event(4 * i + 3)};
+      plain_iteration(P, W, s, ev);
     }
-    CGL_HIP(hipMemcpyAsync(sh, W.st.ptr, sizeof(NodeDev), hipMemcpyDeviceToHost, s));
-    CGL_HIP(hipStreamSynchronize(s));
-    if (ctx->profiling) {
-      // only launches of iterations that ran (the rest returned at once) are counted
-      const int ran = std::min(chunk, sh->iter - iter_before);
-      for (int i = 0; i < ran; ++i) {
-        float a = 0.f, b = 0.f;
-        CGL_HIP(hipEventElapsedTime(&a, ctx->event(4 * i), ctx->event(4 * i + 1)));
-        CGL_HIP(hipEventElapsedTime(&b, ctx->event(4 * i + 2), ctx->event(4 * i + 3)));
-        ctx->kt_ms[0] += a;
-        ctx->kt_ms[1] += b;
-        ctx->kt_n[0] += 1;
-        ctx->kt_n[1] += 1;
-      }
-    }
-    iter_before = sh->iter;
-    if (sh->done) break;
+  } else if (W.graph_exec) {
+    CGL_HIP(hipGraphLaunch(W.graph_exec, s));
+  } else {
+    for (int i = 0; i < PlainWork::kChunk; ++i) plain_iteration(P, W, s);
   }
-  fill_result(*sh, res);
+  CGL_HIP(hipMemcpyAsync(W.st_host, W.st.ptr, sizeof(NodeDev), hipMemcpyDeviceToHost, s));
+  CGL_HIP(hipEventRecord(W.chunk_ev, s));
+}
+
+bool plain_after_chunk(Problem& P) {
+  PlainWork& W = P.plain;
+  cgl_ctx* ctx = P.ctx;
+  NodeDev* sh = W.st_host;
+  if (ctx->profiling) {
+    // only launches of iterations that ran (the rest returned at once) are counted
+    const int ran = std::min(PlainWork::kChunk, sh->iter - W.iter_before);
+    for (int i = 0; i < ran; ++i) {
+      float a = 0.f, b = 0.f;
+      CGL_HIP(hipEventElapsedTime(&a, ctx->event(4 * i), ctx->event(4 * i + 1)));
+      CGL_HIP(hipEventElapsedTime(&b, ctx->event(4 * i + 2), ctx->event(4 * i + 3)));
+      ctx->kt_ms[0] += a;
+      ctx->kt_ms[1] += b;
+      ctx->kt_n[0] += 1;
+      ctx->kt_n[1] += 1;
+    }
+  }
+  W.iter_before = sh->iter;
+  return sh->done != 0;
+}
+
+void plain_end(Problem& P, cgl_result* res, double* beta_out, hipStream_t s) {
+  PlainWork& W = P.plain;
+  fill_result(*W.st_host, res);
   if (beta_out)
-    CGL_HIP(hipMemcpyAsync(beta_out, W.bbest.ptr, p * 8, hipMemcpyDeviceToHost, s));
+    CGL_HIP(hipMemcpyAsync(beta_out, W.bbest.ptr, P.p * 8, hipMemcpyDeviceToHost, s));
   CGL_HIP(hipStreamSynchronize(s));
+}
+
+void solve_plain(Problem& P, const cgl_node& nd, const NodeHost& nh, double* beta_out,
+                 cgl_result* res) {
+  if (P.plain.busy) invalid("the problem's FP64 path is in use by a server");
+  hipStream_t s = P.ctx->stream;
+  plain_begin(P, nd, nh, s);
+  for (;;) {
+    plain_launch(P, s);
+    CGL_HIP(hipEventSynchronize(P.plain.chunk_ev));
+    if (plain_after_chunk(P)) break;
+  }
+  plain_end(P, res, beta_out, s);
 }
 
 // ------------------------------------------------------------------ FP64 certificate at beta
@@ -436,6 +508,14 @@ int cgl_ctx_create(int device, void* hip_stream, cgl_ctx** out) {
   noalloc_setup(device);  // this device's address of the allocation-free prox's scratch
   std::unique_ptr<cgl_ctx> c(new cgl_ctx());
   c->device = device;
+  {
+    hipDeviceProp_t prop;
+    CGL_HIP(hipGetDeviceProperties(&prop, device));
+    c->arch = prop.gcnArchName;
+    const size_t colon = c->arch.find(':');
+    if (colon != std::string::npos) c->arch.resize(colon);
+    c->load_tuning();
+  }
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
     c->own_stream = false;
@@ -607,8 +687,8 @@ int cgl_problem_set_eigen(cgl_problem* prob, double shift) {
   Problem& P = *reinterpret_cast<Problem*>(prob);
   if (P.loss != LOSS_LS) invalid("the eigen-perspective relaxation is for least squares");
   if (!(shift >= 0.0) || !std::isfinite(shift)) invalid("shift must be >= 0");
-  if (P.mixed && (P.mixed->in_flight || P.mixed->free_slots() != P.mixed->S))
-    invalid("the problem's batched engine holds running nodes (a server's)");
+  if ((P.mixed && (P.mixed->in_flight || P.mixed->free_slots() != P.mixed->S)) || P.plain.busy)
+    invalid("a server runs nodes of the problem");
   CGL_HIP(hipSetDevice(P.ctx->device));
   if (P.lam_max <= 0.0) P.lam_max = power_lambda_max(P);
   if (shift >= P.lam_max) invalid("shift must be below lambda_max(X^T X)");

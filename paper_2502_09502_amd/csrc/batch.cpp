@@ -323,8 +323,9 @@ void MixedWork::set_split_xt(int ks) {
 // Its cost is that time plus the reading of its partial sums by the next kernel (one FP32 slab
 // of nodes x rows per chunk, charged at 4 TB/s, about what the consumers achieve); the cheapest
 // wins, a larger split only when it is 2% cheaper. Results are kept on the context per (pass,
-// rows, k-length, nodes); CGL_AUTOTUNE=0 keeps the first candidate that fills the chip in one
-// round.
+// rows, k-length, nodes) and in the tuning cache file of the device's architecture, which later
+// contexts load (CGL_TUNE_CACHE); CGL_AUTOTUNE=0 keeps the first candidate that fills the chip in
+// one round.
 void MixedWork::tune_splits(Problem& P) {
   cgl_ctx* ctx = P.ctx;
   hipStream_t s = stream;
@@ -366,6 +367,7 @@ void MixedWork::tune_splits(Problem& P) {
     }
     set(choice);
     ctx->tuned_split[key] = choice;
+    if (tune && cand.size() > 1) ctx->save_tuning(key, choice);
   }
 }
 

@@ -25,8 +25,12 @@ struct cgl_ctx {
   int64_t kt_n[16] = {0};
   std::vector<hipEvent_t> events;  // pool, grown on demand
   hipEvent_t event(size_t i);
-  // split-K choices of the batched products found by timing, by (pass, M, K, nodes)
+  // split-K choices of the batched products found by timing, by (pass, M, K, nodes); loaded
+  // from and appended to the tuning cache file (tune_cache_path) for this device's architecture
   std::map<std::array<int64_t, 4>, int> tuned_split;
+  std::string arch;  // gcnArchName up to the first ':' (e.g. "gfx950")
+  void load_tuning();
+  void save_tuning(const std::array<int64_t, 4>& key, int choice) const;
   ~cgl_ctx();
 };
 
@@ -73,11 +77,17 @@ struct Problem;
 
 // Workspace of the plain per-node path (reused across solves of one problem).
 struct PlainWork {
+  static constexpr int kChunk = 8;  // iterations per launch between host checks
   bool ready = false;
+  bool busy = false;  // a server's plain solve of this problem is in progress
   PlainGeom geom{};
   DevBuf bring, uring, bbest, w, h, part, fpart, lpart, cls, st, gsq;
   NodeDev* st_host = nullptr;
+  NodeDev st0{};              // staging of the initial state (read by an asynchronous copy)
+  std::vector<double> warm;   // staging of a warm start
   hipGraphExec_t graph_exec = nullptr;
+  hipEvent_t chunk_ev = nullptr;
+  int iter_before = 1;
   void ensure(Problem& P);
   ~PlainWork();
 };
@@ -103,6 +113,12 @@ struct Problem {
 
 void solve_plain(Problem& P, const cgl_node& nd, const NodeHost& nh, double* beta_out,
                  cgl_result* res);
+// solve_plain in steps on a stream (see api.cpp): begin, then launch / (chunk_ev completes) /
+// after_chunk until it returns true, then end.
+void plain_begin(Problem& P, const cgl_node& nd, const NodeHost& nh, hipStream_t s);
+void plain_launch(Problem& P, hipStream_t s);
+bool plain_after_chunk(Problem& P);
+void plain_end(Problem& P, cgl_result* res, double* beta_out, hipStream_t s);
 // Batched solve of count mixed-precision nodes; node i's result and solution go to row rows[i]
 // of res and beta_out (row i when rows is null), and with dual_out the iterate whose dual point
 // gave its certified bound to the same row of dual_out.

@@ -209,20 +209,42 @@ __global__ __launch_bounds__(256) void k_xt(const XT* __restrict__ X, int64_t ld
   for (int i = 0; i < N; ++i) acc[i] = 0.0;
   const XT* xp = X + r0 * ldx + col;
   int i = wid;
-  for (; i + 3 * kXtWaves < nr; i += 4 * kXtWaves) {
-    double x0[N], x1[N], x2[N], x3[N];
-    XVec<XT>::load(xp + (int64_t)i * ldx, x0);
-    XVec<XT>::load(xp + (int64_t)(i + kXtWaves) * ldx, x1);
-    XVec<XT>::load(xp + (int64_t)(i + 2 * kXtWaves) * ldx, x2);
-    XVec<XT>::load(xp + (int64_t)(i + 3 * kXtWaves) * ldx, x3);
-    const double a0 = rs[i], a1 = rs[i + kXtWaves], a2 = rs[i + 2 * kXtWaves],
-                 a3 = rs[i + 3 * kXtWaves];
+  // groups of four rows (one per wave stride); two register sets used in turn, so the next
+  // group is loading while the current one is summed (a last group reloads itself, a valid
+  // address, in place of the group past the end); the sum runs over the rows in order
+  auto load4 = [&](double (&x)[4][N], int r) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) XVec<XT>::load(xp + (int64_t)(r + q * kXtWaves) * ldx, x[q]);
+  };
+  auto sum4 = [&](const double (&x)[4][N], int r) {
+    const double a0 = rs[r], a1 = rs[r + kXtWaves], a2 = rs[r + 2 * kXtWaves],
+                 a3 = rs[r + 3 * kXtWaves];
 #pragma unroll
     for (int e = 0; e < N; ++e) {
-      acc[e] = fma(x0[e], a0, acc[e]);
-      acc[e] = fma(x1[e], a1, acc[e]);
-      acc[e] = fma(x2[e], a2, acc[e]);
-      acc[e] = fma(x3[e], a3, acc[e]);
+      acc[e] = fma(x[0][e], a0, acc[e]);
+      acc[e] = fma(x[1][e], a1, acc[e]);
+      acc[e] = fma(x[2][e], a2, acc[e]);
+      acc[e] = fma(x[3][e], a3, acc[e]);
+    }
+  };
+  if (i + 3 * kXtWaves < nr) {
+    double xa[4][N], xb[4][N];
+    load4(xa, i);
+    for (;;) {
+      int nx = i + 4 * kXtWaves;
+      bool more = nx + 3 * kXtWaves < nr;
+      load4(xb, more ? nx : i);
+      __builtin_amdgcn_sched_barrier(0);
+      sum4(xa, i);
+      i = nx;
+      if (!more) break;
+      nx = i + 4 * kXtWaves;
+      more = nx + 3 * kXtWaves < nr;
+      load4(xa, more ? nx : i);
+      __builtin_amdgcn_sched_barrier(0);
+      sum4(xb, i);
+      i = nx;
+      if (!more) break;
     }
   }
   for (; i < nr; i += kXtWaves) {

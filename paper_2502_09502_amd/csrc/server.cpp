@@ -71,6 +71,17 @@ constexpr size_t kQueueCap = 1u << 20;
 
 }  // namespace cgl
 
+namespace cgl {
+namespace {
+// An FP64-path node in progress on a stream of its own (one per problem at a time: it uses the
+// problem's plain-path buffers).
+struct PlainJob {
+  std::unique_ptr<Request> r;
+  hipStream_t stream = nullptr;
+};
+}  // namespace
+}  // namespace cgl
+
 struct cgl_server {
   cgl_ctx* ctx = nullptr;
   size_t budget = 0;  // 0: no limit
@@ -78,6 +89,7 @@ struct cgl_server {
   uint64_t next_ticket = 1;
   std::deque<std::unique_ptr<cgl::Request>> queue;
   std::vector<cgl::Resident> resident;
+  std::vector<cgl::PlainJob> plain_jobs;
   std::deque<cgl::Finished> done;
 };
 
@@ -241,28 +253,68 @@ void engine_turn(cgl_server& S, Resident& R) {
   if (R.running() > 0) W.launch_chunk(P);
 }
 
-void plain_round(cgl_server& S) {
-  for (auto it = S.queue.begin(); it != S.queue.end(); ++it) {
-    if ((*it)->node.precision == CGL_PREC_MIXED) continue;
-    std::unique_ptr<Request> r = std::move(*it);
-    S.queue.erase(it);
+// Queued FP64-path nodes start, one per problem at a time, in queue order.
+void plain_start(cgl_server& S) {
+  for (auto it = S.queue.begin(); it != S.queue.end();) {
+    Request& q = **it;
+    if (q.node.precision == CGL_PREC_MIXED || q.P->plain.busy) {
+      ++it;
+      continue;
+    }
+    PlainJob job;
+    job.r = std::move(*it);
+    it = S.queue.erase(it);
+    Problem& P = *job.r->P;
+    CGL_HIP(hipStreamCreateWithFlags(&job.stream, hipStreamNonBlocking));  // default priority
+    P.plain.busy = true;
+    plain_begin(P, job.r->node, job.r->host, job.stream);
+    plain_launch(P, job.stream);
+    S.plain_jobs.push_back(std::move(job));
+  }
+}
+
+// The plain jobs whose chunks have completed: finished (or cancelled) ones to the completion
+// list, the others launch their next chunk.
+void plain_serve(cgl_server& S, bool& any, bool& served) {
+  for (size_t i = 0; i < S.plain_jobs.size();) {
+    PlainJob& job = S.plain_jobs[i];
+    Problem& P = *job.r->P;
+    any = true;
+    const hipError_t q = hipEventQuery(P.plain.chunk_ev);
+    if (q == hipErrorNotReady) {
+      ++i;
+      continue;
+    }
+    CGL_HIP(q);
+    served = true;
+    const bool finished = plain_after_chunk(P);
+    if (!finished && !job.r->cancelled) {
+      plain_launch(P, job.stream);
+      ++i;
+      continue;
+    }
     cgl_result res{};
-    std::vector<double> beta((size_t)r->P->p);
-    solve_plain(*r->P, r->node, r->host, beta.data(), &res);
-    finish(S, std::move(r), res, std::move(beta));
-    return;  // one per poll
+    std::vector<double> beta((size_t)P.p);
+    plain_end(P, &res, beta.data(), job.stream);
+    if (job.r->cancelled) res.status = CGL_CANCELLED;
+    P.plain.busy = false;
+    (void)hipStreamDestroy(job.stream);
+    finish(S, std::move(job.r), res, std::move(beta));
+    S.plain_jobs.erase(S.plain_jobs.begin() + (ptrdiff_t)i);
   }
 }
 
 void run_round(cgl_server& S) {
-  // idle engines with work take a turn (their chunks then run while the host goes on)
+  // idle engines with work take a turn (their chunks then run while the host goes on), and
+  // queued FP64-path nodes start on streams of their own
   for (auto& R : S.resident)
     if (!R.P->mixed->in_flight && (R.running() > 0 || has_queued(S, R.P))) engine_turn(S, R);
-  // an FP64-path node on the context's stream, beside the engines' chunks
-  plain_round(S);
-  // engines whose chunks have completed take their turn; wait for the first one if none has
+  plain_start(S);
+  // engines and plain jobs whose chunks have completed are served; wait for the first one if
+  // none has
   for (;;) {
     bool any = false, served = false;
+    plain_serve(S, any, served);
     for (auto& R : S.resident) {
       MixedWork& W = *R.P->mixed;
       if (!W.in_flight) continue;
@@ -393,6 +445,11 @@ int cgl_server_cancel(cgl_server* srv, uint64_t ticket) {
         r->cancelled = true;  // retired with its best certified bound at the next round
         return CGL_OK;
       }
+  for (auto& job : srv->plain_jobs)
+    if (job.r->ticket == ticket) {
+      job.r->cancelled = true;  // stopped after its chunk in flight, with its best bound
+      return CGL_OK;
+    }
   set_error("unknown or finished ticket");
   return CGL_E_NOTFOUND;
   CGL_API_END
@@ -401,7 +458,7 @@ int cgl_server_cancel(cgl_server* srv, uint64_t ticket) {
 int cgl_server_stats(cgl_server* srv, int32_t* queued, int32_t* running, int32_t* done) {
   CGL_API_BEGIN
   if (!srv) invalid("NULL argument");
-  int run = 0;
+  int run = (int)srv->plain_jobs.size();
   for (const auto& R : srv->resident) run += R.running();
   if (queued) *queued = (int32_t)srv->queue.size();
   if (running) *running = run;
@@ -414,6 +471,12 @@ int cgl_server_destroy(cgl_server* srv) {
   CGL_API_BEGIN
   if (!srv) return CGL_OK;
   (void)hipSetDevice(srv->ctx->device);
+  for (auto& job : srv->plain_jobs) {
+    CGL_HIP(hipStreamSynchronize(job.stream));
+    job.r->P->plain.busy = false;
+    (void)hipStreamDestroy(job.stream);
+  }
+  srv->plain_jobs.clear();
   for (auto& R : srv->resident) {
     // free the slots held by unfinished requests so the problem's engine stays usable
     MixedWork* W = R.P->mixed;

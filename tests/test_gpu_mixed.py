@@ -358,3 +358,32 @@ def test_eigen_perspective_on_the_batched_engine(dtype):
     back = prob.solve_batch(_specs(prob, sets[:2]))
     for r, r0 in zip(back, persp[:2]):
         assert rel(r.primal, r0.primal) <= 1e-6
+
+
+def test_split_tuning_persists_across_contexts(tmp_path, monkeypatch):
+    """The split-K choices the autotuner times at engine setup go to the tuning cache file (one
+    line per product: arch, pass, rows, k-length, nodes, split) and a later context on the same
+    architecture loads them instead of timing again."""
+    path = tmp_path / "splits.txt"
+    monkeypatch.setenv("CGL_TUNE_CACHE", str(path))
+    d = synth.make_dataset(1500, 600, 5, loss="ls", dtype="bf16", config_id=83, k_true=5)
+    spec_sets = synth.node_sets(d.p, d.k, 2, 5, config_id=83)
+    c1 = _lib.Context(0)
+    p1 = _lib.Problem(c1, d.X_store, d.y, loss=d.loss, lam2=d.lam2, M=d.M, k=d.k)
+    r1 = p1.solve_batch(_specs(p1, spec_sets))
+    lines = path.read_text().splitlines()
+    assert len(lines) == 2, lines  # the X pass and the X^T pass each had several candidates
+    fields = [ln.split() for ln in lines]
+    assert all(len(f) == 6 and f[0].startswith("gfx") and int(f[5]) >= 1 for f in fields)
+    assert sorted(int(f[1]) for f in fields) == [0, 1]
+    p1.close()
+    c1.close()
+    c2 = _lib.Context(0)
+    p2 = _lib.Problem(c2, d.X_store, d.y, loss=d.loss, lam2=d.lam2, M=d.M, k=d.k)
+    r2 = p2.solve_batch(_specs(p2, spec_sets))
+    assert path.read_text().splitlines() == lines  # loaded, not timed again
+    for a, b in zip(r1, r2):
+        assert a.status == b.status == "converged"
+        assert rel(a.primal, b.primal) <= 1e-6
+    p2.close()
+    c2.close()

@@ -490,6 +490,8 @@ def main():
         return
     if args.workload in SINGLE_WORKLOADS:
         single_workload(args)
+        if args.copy_bytes > 0:
+            copy_calibration(args.copy_bytes)
         return
     if args.workload == "serve":
         serve(args)

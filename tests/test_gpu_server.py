@@ -183,3 +183,28 @@ def test_poll_stride_keeps_results_that_do_not_fit():
     assert np.all(betas[1, :50] == 0.0) and np.all(betas[1, 50:] == 7.0)
     assert srv.stats() == {"queued": 0, "running": 0, "done": 0}
     srv.close()
+
+
+def test_server_fp64_nodes_run_beside_engines_and_cancel():
+    """FP64-path requests run as chunked jobs beside the batched engines (one per problem at a
+    time); a running one can be cancelled, a direct FP64 solve of that problem is refused while
+    the job holds the problem's plain-path buffers, and the others match solves alone."""
+    a, pa, b, pb = _problems()
+    sets = synth.node_sets(a.p, a.k, 6, 8, config_id=6)
+    srv = _lib.Server(ctx(), 0, 256)
+    plain = [pa.node(Z0=z0, Z1=z1, tol=1e-6, max_iter=5000, precision="f64") for z0, z1 in sets]
+    mixed = [pb.node(Z0=z0, Z1=z1, tol=1e-6, max_iter=5000, precision="mixed") for z0, z1 in sets]
+    tp = [srv.submit(pa, s) for s in plain]
+    tm = [srv.submit(pb, s) for s in mixed]
+    srv.poll(0)  # the first FP64 node of pa runs, the mixed nodes of pb are admitted
+    assert srv.stats()["running"] >= 1
+    with pytest.raises(_lib.CglError):
+        pa.solve(tol=1e-6)  # pa's plain-path buffers are held by the server's job
+    srv.cancel(tp[0])
+    out = _drain(srv, len(tp) + len(tm))
+    srv.close()
+    assert out[tp[0]][0].status in ("cancelled", "converged")
+    for t, s in zip(tp[1:] + tm, plain[1:] + mixed):
+        prob = pa if t in tp else pb
+        _same(out[t][0], prob.solve_batch([s])[0])
+    pa.solve(tol=1e-6)  # free again

@@ -240,7 +240,7 @@ int cgl_problem_matvec(cgl_problem* prob, int32_t trans, const double* v, double
 /* The node prox on the device (Alg. 1 via the Moreau identity, node form): for each of count
  * rows w_i (host, count x p doubles), beta_i = prox_{g_node/rho}(w_i) with k' = k - |Z1_i|, and
  * gval_i = g_node(beta_i) (Alg. 2). nodes may be NULL (no fixed sets, only k used). beta_out:
- * count x p doubles; gval_out: NULL or count doubles. p <= 1048576 (above 32768 each vector is
+ * count x p doubles; gval_out: NULL or count doubles. p <= 1048576 (above 16384 each vector is
  * streamed from device memory by its workgroup instead of held per thread; the standalone
  * workload of Sec. 4.1 runs to p = 102400). Errors (CGL_E_INVAL): NULL ctx, W or beta_out;
  * count < 0; p < 1 or p > 1048576; rho <= 0, M <= 0 or k < 0; an invalid node; 256 < k' < |F|. */

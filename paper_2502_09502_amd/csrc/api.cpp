@@ -105,6 +105,8 @@ int64_t pad_cols(int64_t p) { return (p + 511) / 512 * 512; }
 
 // Longest vector of the standalone prox (cgl_prox_node_batch); problems stop at 32768.
 constexpr int64_t kProxMaxP = 1 << 20;
+// Longest vector the standalone prox holds per thread (16 values in LDS slices).
+constexpr int64_t kProxHeldP = 16 * 1024;
 
 // ------------------------------------------------------------------ node validation
 
@@ -860,10 +862,13 @@ int cgl_prox_node_batch(cgl_ctx* ctx, double rho, double M, int32_t k, const cgl
   CGL_HIP(hipMemcpyAsync(dS.ptr, st.data(), (size_t)count * sizeof(NodeDev),
                          hipMemcpyHostToDevice, s));
   if (ctx->profiling) CGL_HIP(hipEventRecord(ctx->event(0), s));
-  if (prox_elems(p) > 0)
+  // up to 16 values per thread in the workgroup's LDS slices; beyond that the register-held
+  // variants spill, and the kernel that streams each vector from memory is faster (256 against
+  // about 140 us for one vector at p = 25600)
+  if (p <= kProxHeldP)
     launch_prox(count, dW.as<double>(), p, nullptr, 0, dC.as<uint8_t>(), p, p, rho, M, 1.0,
                 dS.as<NodeDev>(), dB.as<double>(), 0, p, s);
-  else  // beyond one workgroup's per-thread values: the kernel that streams each vector
+  else
     launch_prox_paged(count, dW.as<double>(), p, dC.as<uint8_t>(), p, p, rho, M,
                       dS.as<NodeDev>(), dB.as<double>(), p, s);
   if (ctx->profiling) CGL_HIP(hipEventRecord(ctx->event(1), s));

@@ -205,6 +205,15 @@ void MixedWork::ensure(Problem& P) {
   md.L = P.L;
   md.rho = P.rho;
   md.shift = P.shift;
+  md.cert_gap = kCertGap;
+  md.stall_cycles = kStallCycles;
+  {  // tuning knobs of the certification requests (defaults: the fastest of a sweep on the
+     // 256-node least-squares workload)
+    const char* g = std::getenv("CGL_CERT_GAP");
+    if (g && std::atof(g) > 0.0) md.cert_gap = std::atof(g);
+    const char* c = std::getenv("CGL_STALL_CYCLES");
+    if (c && std::atoi(c) > 0) md.stall_cycles = std::atoi(c);
+  }
   md.slots = S;
   md.S_pad = S_pad;
   md.st = st.as<NodeDev>();

@@ -451,8 +451,8 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
       st->since_improve += 1;
     }
     st->since_recentre += 1;
-    if (mgap <= 0.5 * st->tol ||
-        (st->since_improve >= kStallCycles && st->since_recentre >= kStallCycles) ||
+    if (mgap <= md.cert_gap * st->tol ||
+        (st->since_improve >= md.stall_cycles && st->since_recentre >= md.stall_cycles) ||
         iter + 1 >= st->max_iter) {
       st->want_cert = 1;
     }

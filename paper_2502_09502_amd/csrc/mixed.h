@@ -8,7 +8,8 @@
 
 namespace cgl {
 
-constexpr int kStallCycles = 15;  // re-centre when the working gap has not halved for this long
+constexpr int kStallCycles = 6;   // re-centre when the working gap has not halved for this long
+constexpr double kCertGap = 1.0;  // ask for an FP64 round once the working gap is <= kCertGap * tol
 
 struct MixedDev {
   // problem
@@ -18,6 +19,8 @@ struct MixedDev {
   const double* y;      // n_pad (zero padded)
   int loss;
   double lam2, M, L, rho;
+  double cert_gap;      // a node asks for an FP64 round when its working gap is <= cert_gap * tol
+  int stall_cycles;     // ... or when that gap has not halved for this many cycles
   double shift;         // eigen-perspective shift s (App. D.2; least squares), 0 otherwise: the
                         // gradient gains -2 s gamma, the objective -s ||beta||^2, the regulariser
                         // weight is 2 (lambda2 + s) and the bound gains s ||point||^2

@@ -1,8 +1,9 @@
-"""The device prox beyond p = 32768 (the long-vector kernel that streams each vector from
+"""The device prox beyond p = 16384 (the long-vector kernel that streams each vector from
 memory), element by element against the oracle's stack PAVA (Alg. 1 via the Moreau identity) and
 g by Alg. 2, at the sizes of the standalone prox workload of Sec. 4.1 (p = 100 * 2^i up to
-102400, gamma ~ N(0, I), k = 10, M = 1, rho = 1) and around them: other k (both the candidate
-ranking and the radix fallback), fixed sets, ties and zeros."""
+102400, gamma ~ N(0, I), k = 10, M = 1, rho = 1), from just past the switch away from the
+register-held kernels at p = 16384, and around them: other k (both the candidate ranking and the
+radix fallback), fixed sets, ties and zeros."""
 import numpy as np
 import pytest
 
@@ -27,7 +28,7 @@ def _check(W, rho, M, k, sets=None, atol=1e-11):
         assert abs(g[i] - gref) <= 1e-10 * max(1.0, abs(gref)), (i, g[i], gref)
 
 
-@pytest.mark.parametrize("p", [32769, 51200, 102400])
+@pytest.mark.parametrize("p", [16385, 25600, 32769, 51200, 102400])
 def test_prox_fig1_setting_large_p(p):
     W = np.stack([np.random.default_rng([4, p, s]).standard_normal(p) for s in range(3)])
     _check(W, 1.0, 1.0, 10)

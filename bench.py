@@ -537,7 +537,7 @@ def main():
     # timed steps: the production path (graph-captured chunks), with only the host wall time of
     # the engine's phases recorded (batched engine)
     ctx.set_profiling(True, phases_only=True)
-    for w in range(10):
+    for w in range(12):
         ctx.kernel_stats(w, reset=True)
     t0 = time.perf_counter()
     results = []
@@ -551,12 +551,13 @@ def main():
     if mode == "batched":
         phases = {}
         for w, name in ((5, "iteration_chunks"), (6, "certification_rounds"),
-                        (7, "admission_retirement")):
+                        (7, "admission_retirement"), (10, "chunks_gpu"),
+                        (11, "certification_rounds_gpu")):
             ms, cnt = ctx.kernel_stats(w, reset=True)
             phases[name] = {"ms_per_step": round(ms / args.steps, 3), "count_per_step": cnt / args.steps}
     # one more step, untimed, with kernel events on the roofline's kernel (its launches then run
     # outside graphs): the kernel's live average launch time and the per-cycle kernel figures
-    for w in range(10):
+    for w in range(12):
         ctx.kernel_stats(w, reset=True)
     ctx.set_profiling(True)
     prob.solve_batch(step_specs, out=out)
@@ -571,8 +572,8 @@ def main():
                             "from": "the profiled step"}
         cycles = phases["xt_pass_kernel"]["count_per_step"]
         if cycles:
-            phases["iteration_chunks"]["us_per_cycle"] = round(
-                1e3 * phases["iteration_chunks"]["ms_per_step"] / cycles, 1)
+            for name in ("iteration_chunks", "chunks_gpu"):
+                phases[name]["us_per_cycle"] = round(1e3 * phases[name]["ms_per_step"] / cycles, 1)
         # the X pass reads only the operand's nonzero prefix of the support-first column order
         # (not timed: a timed launch starts a few microseconds later)
         frac, passes = ctx.kernel_stats(9)
@@ -589,15 +590,23 @@ def main():
     if mode == "batched" and args.plain_nodes > 0:
         pspecs = specs("f64")[: args.plain_nodes]
         lat = []
+        pres = []
         tp0 = time.perf_counter()
         for s in pspecs:
             ts = time.perf_counter()
-            prob.solve_batch([s])
+            pres += prob.solve_batch([s])
             lat.append(time.perf_counter() - ts)
         tp = time.perf_counter() - tp0
         plain = {"solves_per_s": len(pspecs) / tp, "nodes": len(pspecs),
                  "p50_ms": 1e3 * float(np.percentile(lat, 50)),
-                 "p99_ms": 1e3 * float(np.percentile(lat, 99))}
+                 "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                 "iterations": {"median": statistics.median([r.iters for r in pres]),
+                                "max": max(r.iters for r in pres)},
+                 "restarts": {"median": statistics.median([r.restarts for r in pres]),
+                              "max": max(r.restarts for r in pres)},
+                 "batched_same_nodes": {
+                     "iterations_median": statistics.median([r.iters for r in results[:len(pspecs)]]),
+                     "restarts_median": statistics.median([r.restarts for r in results[:len(pspecs)]])}}
 
     out = {
         "metric": "node relaxations solved/sec at 1e-6 gap, batched vs plain; p50/p99 latency",
@@ -617,6 +626,8 @@ def main():
         "all_certified": ok,
         "iterations": {"median": statistics.median(iters), "p99": float(np.percentile(iters, 99)),
                        "max": max(iters)},
+        "restarts": {"median": statistics.median([r.restarts for r in results]),
+                     "max": max(r.restarts for r in results)},
         "roofline": roof,
     }
     if phases is not None:

@@ -143,7 +143,9 @@ int cgl_ctx_destroy(cgl_ctx* ctx);
  *        5 = iteration chunks, 6 = certification rounds, 7 = admission and retirement;
  *        8 = the prox kernel of cgl_prox_node_batch (one launch per call);
  *        9 = the batched X pass's operand extent: total_ms holds the sum over passes of the
- *            fraction of the padded columns read (not a time), launches the passes.
+ *            fraction of the padded columns read (not a time), launches the passes;
+ *        10, 11 (on = 3 only) = GPU time of the batched engine's graph-captured chunks and of
+ *            its certification rounds (HIP events around each on the stream).
  * cgl_ctx_kernel_stats returns the totals since the last reset (reset = 1 clears them). */
 int cgl_ctx_set_profiling(cgl_ctx* ctx, int32_t on);
 int cgl_ctx_kernel_stats(cgl_ctx* ctx, int32_t which, int32_t reset, double* total_ms,

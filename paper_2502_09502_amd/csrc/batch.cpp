@@ -457,7 +457,10 @@ void MixedWork::launch_chunk(Problem& P) {
       CGL_HIP(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
       CGL_HIP(hipGraphDestroy(graph));
     }
+    // level 3: the GPU span of the chunk (launch gaps inside the graph included)
+    if (ctx->phase_timing) CGL_HIP(hipEventRecord(ctx->event(200), s));
     CGL_HIP(hipGraphLaunch(graph_exec, s));
+    if (ctx->phase_timing) CGL_HIP(hipEventRecord(ctx->event(201), s));
   }
   // the operand order is checked with the chunk's own synchronisation and changed (if at all)
   // before the next launches
@@ -499,12 +502,36 @@ void MixedWork::finish_chunk(Problem& P) {
       ctx->kt_n[2] += 1;
     }
   }
+  if (ctx->phase_timing && !ctx->profiling && mixed_graphs()) {
+    float a = 0.f;
+    CGL_HIP(hipEventElapsedTime(&a, ctx->event(200), ctx->event(201)));
+    ctx->kt_ms[10] += a;
+    ctx->kt_n[10] += 1;
+  }
   cycles += chunk;
+}
+
+// Waits for an event by polling it: the host takes up the chunk's outcome within microseconds
+// of the GPU reaching the event (a blocking wait returns later, and the GPU idles meanwhile).
+static void poll_event(hipEvent_t e) {
+  static const bool block = [] {
+    const char* v = std::getenv("CGL_BLOCKING_WAIT");
+    return v && std::atoi(v) > 0;
+  }();
+  if (block) {
+    CGL_HIP(hipEventSynchronize(e));
+    return;
+  }
+  for (;;) {
+    const hipError_t r = hipEventQuery(e);
+    if (r == hipSuccess) return;
+    if (r != hipErrorNotReady) CGL_HIP(r);
+  }
 }
 
 void MixedWork::run_chunk(Problem& P) {
   launch_chunk(P);
-  CGL_HIP(hipEventSynchronize(chunk_done));
+  poll_event(chunk_done);
   finish_chunk(P);
 }
 
@@ -545,6 +572,8 @@ int MixedWork::cert_round(Problem& P, bool overlap) {
   upload_list(P, want, kListCert);
   hipEvent_t e0 = ctx->profiling ? ctx->event(100) : nullptr;
   hipEvent_t e1 = ctx->profiling ? ctx->event(101) : nullptr;
+  const bool span = ctx->phase_timing && !ctx->profiling;  // level 3: the round's GPU span
+  if (span) CGL_HIP(hipEventRecord(ctx->event(202), s));
   // X beta in FP64 over the union of the iterates' supports (the other coordinates contribute
   // exact zeros), from the rows of the transposed design
   launch_cert_gather(md, list.as<int>(), nq, B64.as<double>(), sflag.as<uint8_t>(), s);
@@ -574,6 +603,8 @@ int MixedWork::cert_round(Problem& P, bool overlap) {
                     ldp, part64.as<double>(), part64_cap, s);
   launch_cert_finish(md, list.as<int>(), nq, B64.as<double>(), H64.as<double>(),
                      cpart.as<double>(), ncchunk, s);
+  if (span) CGL_HIP(hipEventRecord(ctx->event(203), s));
+  round_span = span;
   round_open = true;
   if (overlap) return kRoundOpen;
   CGL_HIP(hipMemcpyAsync(st_host, st.ptr, (size_t)S * sizeof(NodeDev), hipMemcpyDeviceToHost, s));
@@ -593,6 +624,13 @@ void MixedWork::close_round(Problem& P) {
     CGL_HIP(hipEventElapsedTime(&a, ctx->event(100), ctx->event(101)));
     ctx->kt_ms[4] += a;
     ctx->kt_n[4] += 1;
+  }
+  if (round_span) {
+    float a = 0.f;
+    CGL_HIP(hipEventElapsedTime(&a, ctx->event(202), ctx->event(203)));
+    ctx->kt_ms[11] += a;
+    ctx->kt_n[11] += 1;
+    round_span = false;
   }
   cert_rounds += 1;
 }
@@ -666,7 +704,9 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
     CGL_HIP(hipMemcpyAsync(bres.as<double>() + o, ws.data(), (size_t)P.p * 8,
                            hipMemcpyHostToDevice, s));
   }
-  // the admitted slots' class rows, one copy per run of consecutive slots
+  // the admitted slots' class rows and states, one copy per run of consecutive slots (the other
+  // slots' device states stay as they are: a certification round queued earlier may still be
+  // writing them)
   {
     std::vector<int> ss = slots;
     std::sort(ss.begin(), ss.end());
@@ -675,10 +715,11 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
       while (b < ss.size() && ss[b] == ss[b - 1] + 1) ++b;
       const size_t off = (size_t)ss[a] * ldp, len = (b - a) * (size_t)ldp;
       CGL_HIP(hipMemcpyAsync((uint8_t*)cls.ptr + off, cls_host + off, len, hipMemcpyHostToDevice, s));
+      CGL_HIP(hipMemcpyAsync(st.as<NodeDev>() + ss[a], st_host + ss[a], (b - a) * sizeof(NodeDev),
+                             hipMemcpyHostToDevice, s));
       a = b;
     }
   }
-  CGL_HIP(hipMemcpyAsync(st.ptr, st_host, (size_t)S * sizeof(NodeDev), hipMemcpyHostToDevice, s));
   CGL_HIP(hipStreamSynchronize(s));
   if (reorder && (int)adm.size() >= S / 4) {
     // many new supports: no prefix (no strays) until a check half an interval later lists them
@@ -747,7 +788,7 @@ void MixedWork::retire(Problem& P, const std::vector<int>& slots,
   }
 }
 
-// Upload the host image of the slot states (after retire/admit edits; the device is idle).
+// A slot list to the device (list), through the pinned region of its caller.
 void MixedWork::upload_list(Problem& P, const std::vector<int>& v, int region) {
   int* h = list_host + (size_t)region * S;
   std::copy(v.begin(), v.end(), h);
@@ -768,6 +809,8 @@ void MixedWork::flush_retired() {
   ret_pending.clear();
 }
 
+// Upload the host image of all slot states (after retire/admit edits; nothing of the engine is
+// in flight).
 void MixedWork::push_states(Problem& P) {
   CGL_HIP(hipMemcpyAsync(st.ptr, st_host, (size_t)S * sizeof(NodeDev), hipMemcpyHostToDevice,
                          stream));
@@ -828,11 +871,11 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
   phase(7, [&] { fill(); });
   phase(5, [&] { W.run_chunk(P); });
   while (finished < count) {
-    // a round left open runs ahead of the next chunk and shares its synchronisation; a closed
-    // round (no other node running, or none) is followed by the retirements first
-    int round = MixedWork::kRoundNone;
-    phase(6, [&] { round = W.cert_round(P, /*overlap=*/true); });
-    if (round == MixedWork::kRoundOpen) phase(5, [&] { W.run_chunk(P); });
+    // A round left open runs ahead of the next chunk and shares its synchronisation; the
+    // retirements of nodes certified by earlier rounds (and the admissions into their slots)
+    // are queued behind it, so the host's part of them overlaps the round's device work. A
+    // closed round (no other node running) has synchronised, and its nodes retire at once.
+    phase(6, [&] { (void)W.cert_round(P, /*overlap=*/true); });
     phase(7, [&] {
       std::vector<int> done;
       std::vector<cgl_result*> rs;
@@ -855,7 +898,7 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
     });
     // a run with nothing active and work pending would spin: guard
     if (finished < count && W.free_slots() == W.S && next >= count) break;
-    if (finished < count && round != MixedWork::kRoundOpen) phase(5, [&] { W.run_chunk(P); });
+    if (finished < count) phase(5, [&] { W.run_chunk(P); });
   }
   CGL_HIP(hipStreamSynchronize(s));
   W.flush_retired();

@@ -109,6 +109,7 @@ struct MixedWork {
   int cert_round(Problem& P, bool overlap = false);
   void close_round(Problem& P);
   bool round_open = false;
+  bool round_span = false;  // the open round's GPU span is being timed (profiling level 3)
   // X-pass operand order. The probe (queued at the end of a chunk) lists the coordinates where a
   // running slot's recent iterates, base point or operand are nonzero and stages the extent and
   // stray counts for the host; after the chunk's synchronisation, apply puts those coordinates

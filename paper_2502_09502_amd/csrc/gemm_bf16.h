@@ -55,7 +55,16 @@ struct GemmArgs {
   int64_t c_split_stride;
 };
 
+// A tile row segment, as a streaming (non-temporal) load when NT: the caches then do not keep
+// the design, whose rows are read once per pass.
+template <bool NT>
+__device__ __forceinline__ u32x4 load_a16(const uint16_t* p) {
+  if (NT) return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+  return *reinterpret_cast<const u32x4*>(p);
+}
+
 // Main loop; leaves this wave's GT_RT x 2 accumulator tiles (row block r, node block c) in acc.
+template <bool NT = false>
 __device__ __forceinline__ void gemm_bf16_mainloop(const GemmArgs& g, int64_t m0, int64_t n0,
                                                    int64_t k0, int64_t k1, uint16_t* As,
                                                    floatx16 (&acc)[GT_RT][2]) {
@@ -91,7 +100,7 @@ __device__ __forceinline__ void gemm_bf16_mainloop(const GemmArgs& g, int64_t m0
   for (int d = 0; d < 2; ++d) {
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-      ra[d][j] = *reinterpret_cast<const u32x4*>(ag + j * arow_stride + (int64_t)d * GT_K);
+      ra[d][j] = load_a16<NT>(ag + j * arow_stride + (int64_t)d * GT_K);
     const uint16_t* b = bg + (int64_t)d * fstep;
 #pragma unroll
     for (int kb = 0; kb < GT_KB; ++kb)
@@ -116,7 +125,7 @@ __device__ __forceinline__ void gemm_bf16_mainloop(const GemmArgs& g, int64_t m0
         const int64_t st = min((int64_t)(s + d + 2), last);
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-          ra[d][j] = *reinterpret_cast<const u32x4*>(ag + j * arow_stride + st * GT_K);
+          ra[d][j] = load_a16<NT>(ag + j * arow_stride + st * GT_K);
       }
       __builtin_amdgcn_sched_barrier(0);
       __syncthreads();
@@ -172,6 +181,12 @@ __device__ __forceinline__ void gemm_bf16_mainloop(const GemmArgs& g, int64_t m0
 // extent (X pass only): the operand extent counters (the pass reads the columns below the larger
 // of extent[0] and extent[1]); with bump, extent[2] and extent[3] accumulate the columns read
 // (units of 2 GT_K) and the passes.
+// The X^T pass streams all of X~^T (larger than the last-level cache) with non-temporal loads,
+// which leaves that cache to the X pass's support prefix of X~.
+#ifndef CGL_STREAM_XT
+#define CGL_STREAM_XT 1
+#endif
+constexpr bool kStreamXt = CGL_STREAM_XT != 0;
 template <int PASS>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int mtiles, int ks, int per_xcd,
                                                    int* bump, int* extent) {
@@ -201,7 +216,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int mtiles, int k
   const int64_t k0 = (int64_t)z * kc;
   const int64_t k1 = min(K, k0 + kc);
   floatx16 acc[GT_RT][2];
-  gemm_bf16_mainloop(g, m0, n0, k0, k1, As, acc);
+  gemm_bf16_mainloop<PASS == 1 && kStreamXt>(g, m0, n0, k0, k1, As, acc);
   float* C = g.C + (int64_t)z * g.c_split_stride;
   const int hi = lane >> 5;
 #pragma unroll

@@ -83,6 +83,27 @@ def test_batched_equals_alone_and_refill():
         _check(d, batched[i], *sets[i])
 
 
+def test_refill_with_warm_starts_and_open_rounds():
+    """More nodes than slots where the late nodes are warm-started: they are admitted into freed
+    slots while certification rounds of other nodes are still queued, are parked until a round
+    evaluates their start, and reach the oracle's certified optimum like cold nodes."""
+    d = synth.make_dataset(400, 150, 6, config_id=83)
+    prob = _problem(d)
+    sets = synth.node_sets(d.p, d.k, 290, 15, config_id=83)
+    rng = np.random.default_rng(83)
+    specs = []
+    for i, (z0, z1) in enumerate(sets):
+        w = None
+        if i >= 260:  # admitted only after earlier nodes retire
+            w = 0.5 * rng.standard_normal(d.p) if i % 2 else np.zeros(d.p)
+        specs.append(prob.node(Z0=z0, Z1=z1, tol=1e-6, max_iter=5000, precision="mixed",
+                               warm_start=w))
+    res = prob.solve_batch(specs)
+    assert all(r.status == "converged" and r.gap_rel <= 1e-6 for r in res)
+    for i in (1, 261, 262, 289):
+        _check(d, res[i], *sets[i])
+
+
 def test_mixed_edge_cases():
     d = synth.make_dataset(150, 40, 4, config_id=82)
     prob = _problem(d)

@@ -96,6 +96,7 @@ void MixedWork::ensure(Problem& P) {
   rchunk = kLossChunk;
   nrt = (int)((n_pad + rchunk - 1) / rchunk);
   lpart.alloc((size_t)S * nrt * 8);
+  npart.alloc((size_t)S * nrt * 8);
   fpart.alloc((size_t)S * nrt * 8);
   cycle.alloc(sizeof(int));
   CGL_HIP(hipMemsetAsync(cycle.ptr, 0xff, sizeof(int), s));  // -1: the first cycle is 0
@@ -213,6 +214,9 @@ void MixedWork::ensure(Problem& P) {
     if (g && std::atof(g) > 0.0) md.cert_gap = std::atof(g);
     const char* c = std::getenv("CGL_STALL_CYCLES");
     if (c && std::atoi(c) > 0) md.stall_cycles = std::atoi(c);
+    md.restart_slack = kRestartSlack;
+    const char* r = std::getenv("CGL_RESTART_SLACK");
+    if (r && std::atof(r) >= 0.0) md.restart_slack = std::atof(r);
   }
   md.slots = S;
   md.S_pad = S_pad;
@@ -240,6 +244,7 @@ void MixedWork::ensure(Problem& P) {
   md.ksplit = ksplit;
   md.xt_kchunk = xt_kchunk;
   md.lpart = lpart.as<double>();
+  md.npart = npart.as<double>();
   md.fpart = fpart.as<double>();
   md.nrt = nrt;
   md.rchunk = rchunk;
@@ -637,7 +642,7 @@ void MixedWork::close_round(Problem& P) {
 
 size_t MixedWork::device_bytes() const {
   const DevBuf* bufs[] = {&Xb, &Xbt, &ypad, &st, &cls, &bring, &beta0, &H0, &base0, &base1, &e0f,
-                          &bres, &bdual, &dop, &gop, &dU, &dUp, &dH, &lpart, &fpart, &cycle, &prevsel, &B64,
+                          &bres, &bdual, &dop, &gop, &dU, &dUp, &dH, &lpart, &npart, &fpart, &cycle, &prevsel, &B64,
                           &U64, &R64, &H64, &cpart, &list, &H0_cold, &base0_cold, &base1_cold,
                           &Xt, &part64, &sflag, &sidx, &scount, &Bu, &G, &pinv, &pinv_new,
                           &perm, &perm_new, &dop_tmp, &pfx, &sj, &sv, &Bret};

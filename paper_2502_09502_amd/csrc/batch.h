@@ -35,7 +35,7 @@ struct MixedWork {
   int64_t x_kchunk = 0;
   int64_t rchunk = 0, cchunk = 0;
   double f_cold = 0.0;
-  DevBuf Xb, Xbt, ypad, st, cls, bring, beta0, H0, base0, base1, e0f, bres, bdual, dop, gop, dU, dUp, dH, lpart,
+  DevBuf Xb, Xbt, ypad, st, cls, bring, beta0, H0, base0, base1, e0f, bres, bdual, dop, gop, dU, dUp, dH, lpart, npart,
       fpart, cycle, prevsel, B64, U64, R64, H64, cpart, list, H0_cold, base0_cold, base1_cold, Xt, part64,
       sflag, sidx, scount, Bu, G, Bret, pinv, pinv_new, perm, perm_new, dop_tmp, pfx, sj, sv;
   int64_t ldg = 0;  // least squares: G = X^T X in FP64 (p x ldg), when built

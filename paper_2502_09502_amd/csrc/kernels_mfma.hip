@@ -89,7 +89,8 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
   }
   // four consecutive rows per thread and step (16-byte loads and stores; n_pad and the chunk
   // bounds are multiples of 256)
-  double ls = 0.0;
+  double ls = 0.0, nz = 0.0;
+  const bool noise = md.restart_slack > 0.0;  // uniform: a launch argument
   const float* dup = md.dUp + (int64_t)slot * md.n_pad;
   for (int64_t i = i0 + 4 * (int64_t)threadIdx.x; i < i1; i += 4 * 256) {
     float4 du = *reinterpret_cast<const float4*>(dup + i);
@@ -124,17 +125,31 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
         if (i + c < md.n) {
           const double e = (double)ev[c] + (double)dv[c];  // u - y
           ls += e * e;
+          if (noise) {
+            const double t = 2.0 * e * (double)dv[c];
+            nz += t * t;
+          }
         }
       }
     } else {
       for (int c = 0; c < 4; ++c)
-        if (i + c < md.n)
-          ls += loss_val(md.loss, md.base0[(int64_t)slot * md.n_pad + i + c] + (double)dv[c],
-                         md.y[i + c]);
+        if (i + c < md.n) {
+          const double u = md.base0[(int64_t)slot * md.n_pad + i + c] + (double)dv[c];
+          ls += loss_val(md.loss, u, md.y[i + c]);
+          if (noise) {
+            const double t = loss_grad(md.loss, u, md.y[i + c]) * (double)dv[c];
+            nz += t * t;
+          }
+        }
     }
   }
   ls = block_reduce(ls, red, OpAdd(), 0.0);
   if (threadIdx.x == 0) md.lpart[(int64_t)slot * md.nrt + blockIdx.x] = ls;
+  if (noise) {  // the rounding scale of this chunk's loss terms: each dU_i carries a relative
+                // error of about 2^-9 (BF16 operand), which moves f by about f_i'(u) dU_i 2^-9
+    nz = block_reduce(nz, red, OpAdd(), 0.0);
+    if (threadIdx.x == 0) md.npart[(int64_t)slot * md.nrt + blockIdx.x] = nz;
+  }
 }
 
 // =====================================================================================
@@ -156,9 +171,15 @@ __global__ __launch_bounds__(256) void k_mixed_resid(MixedDev md) {
   const float* dun = md.dU + (int64_t)(cyc & 1) * md.dU_ring + (int64_t)slot * md.n_pad;
   const float* duo = md.dU + (int64_t)((cyc + 1) & 1) * md.dU_ring + (int64_t)slot * md.n_pad;
   if (threadIdx.x < 64) {
-    double a = 0.0;
+    double a = 0.0, nz = 0.0;
     for (int i = threadIdx.x; i < md.nrt; i += 64) a += md.lpart[(int64_t)slot * md.nrt + i];
     a = wave_sum(a);
+    if (md.restart_slack > 0.0) {
+      for (int i = threadIdx.x; i < md.nrt; i += 64) nz += md.npart[(int64_t)slot * md.nrt + i];
+      nz = wave_sum(nz);
+    }
+    // rounding margin of the working objective (zero: Alg. 3's plain comparison)
+    const double margin = md.restart_slack * 0x1p-9 * sqrt(nz);
     if (threadIdx.x == 0) {
       const double Lnew = a - md.shift * st->bsq_new + 2.0 * (md.lam2 + md.shift) * st->g_new;
       double phi = st->phi;
@@ -168,7 +189,7 @@ __global__ __launch_bounds__(256) void k_mixed_resid(MixedDev md) {
       } else if (st->rebase) {
         // L^t was evaluated against the previous base: the momentum runs on untested
         phi += 1.0;
-      } else if (Lnew >= st->L_prev) {
+      } else if (Lnew >= st->L_prev + margin) {
         phi = 1.0;
         restarts += 1;
       } else {

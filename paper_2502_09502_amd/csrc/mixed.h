@@ -10,6 +10,7 @@ namespace cgl {
 
 constexpr int kStallCycles = 6;   // re-centre when the working gap has not halved for this long
 constexpr double kCertGap = 1.0;  // ask for an FP64 round once the working gap is <= kCertGap * tol
+constexpr double kRestartSlack = 1.0;  // noise margin of the restart test (0: plain comparison)
 
 struct MixedDev {
   // problem
@@ -53,6 +54,8 @@ struct MixedDev {
   int ksplit;
   int64_t xt_kchunk;
   double* lpart;        // S x nrt loss partials
+  double* npart;        // S x nrt: sums of (f_i'(u) dU_i)^2, the scale of the loss's rounding
+  double restart_slack; // > 0: a restart needs L^{t+1} >= L^t + slack 2^-9 sqrt(sum npart)
   double* fpart;        // S x nrt F* partials (residual kernel)
   int nrt;
   int64_t rchunk;

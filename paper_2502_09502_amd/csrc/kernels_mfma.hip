@@ -284,7 +284,7 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
   const int iter = st->iter;
   const bool check = (iter % st->check_every) == 0;
   // H at gamma (FP64 base + BF16-product corrections) into the per-thread value slice
-  __shared__ double vbuf[ProxVals<E>::lds ? E * kProxThreads : 1];
+  __shared__ double vbuf[ProxVals<E>::nl * kProxThreads];
   ProxVals<E> pv;
   pv.sl = vbuf;
   uint64_t cb = 0;
@@ -634,7 +634,7 @@ __global__ __launch_bounds__(1024) void k_cert_finish(MixedDev md, const int* li
   const int cyc = *md.cycle + 1;  // the cycle the slot runs next (the counter holds the last one)
   const bool keep = keeps_momentum(st, cyc);
   const uint8_t* cl = md.cls + (int64_t)slot * md.ldp;
-  __shared__ double vbuf[ProxVals<E>::lds ? E * kProxThreads : 1];
+  __shared__ double vbuf[ProxVals<E>::nl * kProxThreads];
   ProxVals<E> hv;
   hv.sl = vbuf;
   uint64_t cb = 0;
@@ -1075,6 +1075,7 @@ void launch_mixed_resid(const MixedDev& md, hipStream_t s) {
     case 10: { constexpr int EE = 10; CALL; break; } \
     case 12: { constexpr int EE = 12; CALL; break; } \
     case 16: { constexpr int EE = 16; CALL; break; } \
+    case 20: { constexpr int EE = 20; CALL; break; } \
     case 24: { constexpr int EE = 24; CALL; break; } \
     case 32: { constexpr int EE = 32; CALL; break; } \
     default: break;              \

@@ -328,7 +328,7 @@ __global__ __launch_bounds__(1024) void k_prox(const double* __restrict__ w, int
   const int iter = st->iter;
   const double* wn = w + (int64_t)node * w_ld;
   const uint8_t* cls_n = cls_all + (int64_t)node * cls_ld;
-  __shared__ double vbuf[ProxVals<E>::lds ? E * kProxThreads : 1];
+  __shared__ double vbuf[ProxVals<E>::nl * kProxThreads];
   ProxVals<E> pv;
   pv.sl = vbuf;
   uint64_t cb = 0;
@@ -515,10 +515,10 @@ void launch_grad_step(const double* part, int nchunks, int64_t p_pad, const Node
 
 int prox_elems(int64_t p) {
   // elements per thread: powers of two and the steps of 1.5 between the larger ones, so that at
-  // most a third of a thread's element slots go unused for p above 4096 (and 10, which fits
-  // p = 10000 with 2% of the slots unused instead of 19%)
+  // most a third of a thread's element slots go unused for p above 4096 (and 10 and 20, which fit
+  // p = 10000 and p = 20000 with 2% of the slots unused)
   const int64_t e = (p + kProxThreads - 1) / kProxThreads;
-  for (int c : {1, 2, 4, 6, 8, 10, 12, 16, 24, 32})
+  for (int c : {1, 2, 4, 6, 8, 10, 12, 16, 20, 24, 32})
     if (e <= c) return c;
   return -1;
 }
@@ -543,6 +543,7 @@ void launch_prox(int nodes, const double* w, int64_t w_ld, const double* h, int6
     CGL_PROX_CASE(10)
     CGL_PROX_CASE(12)
     CGL_PROX_CASE(16)
+    CGL_PROX_CASE(20)
     CGL_PROX_CASE(24)
     CGL_PROX_CASE(32)
     default:
@@ -633,7 +634,7 @@ __global__ __launch_bounds__(1024) void k_g_gstar(const double* __restrict__ bet
   const int kp = st->kp, nfree = st->nfree;
   const uint8_t* cl = cls_all + (int64_t)node * cls_ld;
   // |beta| first (Alg. 2), then |h| (the conjugate) in the per-thread value slice
-  __shared__ double vbuf[ProxVals<E>::lds ? E * kProxThreads : 1];
+  __shared__ double vbuf[ProxVals<E>::nl * kProxThreads];
   ProxVals<E> pv;
   pv.sl = vbuf;
   uint64_t cb = 0;
@@ -723,6 +724,7 @@ void launch_g_gstar(int nodes, const double* beta, int64_t b_ld, const double* h
     CGL_G_CASE(10)
     CGL_G_CASE(12)
     CGL_G_CASE(16)
+    CGL_G_CASE(20)
     CGL_G_CASE(24)
     CGL_G_CASE(32)
     default:

@@ -136,7 +136,7 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
 // thread's element s (index s * kProxThreads + tid), act bit s whether it takes part; keys are
 // recomputed from the caller's registers on every scan instead of being held in another array.
 template <int E, typename KeyF>
-__device__ void block_topk(KeyF key, uint32_t act, int K, ProxSmem& sm) {
+__device__ __forceinline__ void block_topk(KeyF key, uint32_t act, int K, ProxSmem& sm) {
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
   uint32_t avail = act;
@@ -270,7 +270,7 @@ struct Select {
 
 // need-th largest among active keys (1 <= need <= number of active keys). Byte-wise radix.
 template <int E, typename KeyF>
-__device__ Select radix_select_desc(KeyF key, uint32_t act, int need, ProxSmem& sm) {
+__device__ __forceinline__ Select radix_select_desc(KeyF key, uint32_t act, int need, ProxSmem& sm) {
   uint64_t o = 0, a = ~(uint64_t)0;
 #pragma unroll
   for (int s = 0; s < E; ++s)
@@ -397,7 +397,7 @@ __device__ double psi_root(const double* hu, const double* hb, int kh, double vl
 
 // v* over the tail (see the file comment). hu[0..kh): sorted head values. v0: a hint.
 template <int E, typename UF>
-__device__ double tail_root(UF u, uint32_t tail, const double* hu, const double* hb, int kh,
+__device__ __forceinline__ double tail_root(UF u, uint32_t tail, const double* hu, const double* hb, int kh,
                            double v0, double rho, double M, ProxSmem& sm) {
   double v = v0 > 0.0 ? v0 : 0.0;
   double m_prev = -1.0;
@@ -465,7 +465,7 @@ __device__ __forceinline__ uint32_t cls_mask(uint64_t cb, int c) {
 // cb: packed class codes (CLS_*); kp = k - |Z1| (>= 0); nfree = |F|; vhint: previous v* (0 if
 // none). The result is handed to out(s, beta_s) once, element by element, at the end.
 template <int E, typename UF, typename OutF>
-__device__ ProxOut node_prox(UF U, uint32_t neg, uint64_t cb, int kp, int nfree, double rho,
+__device__ __forceinline__ ProxOut node_prox(UF U, uint32_t neg, uint64_t cb, int kp, int nfree, double rho,
                              double M, double vhint, OutF out, ProxSmem& sm,
                              const double* uv = nullptr, int* prev = nullptr) {
   const uint32_t fm = cls_mask<E>(cb, CLS_FREE);
@@ -582,7 +582,7 @@ __device__ ProxOut node_prox(UF U, uint32_t neg, uint64_t cb, int kp, int nfree,
 // H_M is increasing in |a| and the division is monotone, so the top kp of H_M(a_F) are found
 // on A directly and only the selected values are divided.
 template <int E, typename AF>
-__device__ double gstar_node(AF A, double div, uint64_t cb, int kp, int nfree, double M,
+__device__ __forceinline__ double gstar_node(AF A, double div, uint64_t cb, int kp, int nfree, double M,
                              ProxSmem& sm, const double* av = nullptr, int* prev = nullptr) {
   const uint32_t fm = cls_mask<E>(cb, CLS_FREE);
   double z1 = 0.0;
@@ -620,21 +620,24 @@ __device__ double gstar_node(AF A, double div, uint64_t cb, int kp, int nfree, d
 }
 
 // Per-thread working values of the prox kernels: element s of thread t at s * kProxThreads + t
-// of an LDS array (private to the thread: no barrier needed) when E <= kLdsElems, else in
-// registers. Keeps register pressure low enough for 1024-thread workgroups.
+// of an LDS array (private to the thread: no barrier needed) for s < kLdsElems, in registers
+// beyond (E > kLdsElems: the first kLdsElems in LDS, the rest in registers). Keeps register
+// pressure low enough for 1024-thread workgroups.
 constexpr int kLdsElems = 16;
 template <int E>
 struct ProxVals {
-  static constexpr bool lds = E <= kLdsElems;
-  double* sl;           // LDS slice base (lds)
-  double reg[lds ? 1 : E];
+  static constexpr bool lds = E <= kLdsElems;              // every value in the LDS slice
+  static constexpr int nl = E < kLdsElems ? E : kLdsElems;  // values in the LDS slice
+  static constexpr int nr = E - nl;                          // values in registers
+  double* sl;                                                // LDS slice base (nl * kProxThreads)
+  double reg[nr > 0 ? nr : 1];
   __device__ __forceinline__ void set(int s, double v) {
-    if constexpr (lds) sl[s * kProxThreads + threadIdx.x] = v;
-    else reg[s] = v;
+    if (s < nl) sl[s * kProxThreads + threadIdx.x] = v;
+    else reg[s - nl] = v;
   }
   __device__ __forceinline__ double get(int s) const {
-    if constexpr (lds) return sl[s * kProxThreads + threadIdx.x];
-    else return reg[s];
+    if (s < nl) return sl[s * kProxThreads + threadIdx.x];
+    return reg[s - nl];
   }
 };
 

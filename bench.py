@@ -494,6 +494,11 @@ def main():
             copy_calibration(args.copy_bytes)
         return
     if args.workload == "serve":
+        # one hardware queue per resident engine's stream (six engines, the context's stream and
+        # the retirement copies), read by the HIP runtime when it starts (no HIP call has been
+        # made yet): with the default four, a small design's kernels wait behind a large
+        # design's in a shared queue
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
         serve(args)
         if args.copy_bytes > 0:
             copy_calibration(args.copy_bytes)

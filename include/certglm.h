@@ -273,7 +273,11 @@ int cgl_prox_batch_noalloc(cgl_ctx* ctx, double rho, double M, int32_t k, const 
  * slots while slots and the HBM budget allow, advanced together (continuous batching: finished
  * slots are refilled between iteration chunks), and returned through poll.
  *   hbm_budget_bytes: upper bound on the device memory the server's slot state may use
- *                     (0 = no limit beyond max_slots); max_slots: slots per problem. */
+ *                     (0 = no limit beyond max_slots); max_slots: slots per problem.
+ * Each resident problem's engine runs on a HIP stream of its own. The HIP runtime maps a
+ * process's streams onto GPU_MAX_HW_QUEUES hardware queues (4 by default), and kernels that
+ * share a queue run in order: with more resident problems than that, set the variable to at
+ * least the number of resident problems plus two before the process's first HIP call. */
 int cgl_server_create(cgl_ctx* ctx, size_t hbm_budget_bytes, int32_t max_slots,
                       cgl_server** out);
 /* Queue a node of prob (copied; never blocks). ticket receives its id. CGL_E_BUSY when the

@@ -174,8 +174,14 @@ def serve(args):
     probs = []
     for p in sizes:
         X32, y_ls, y_log = synth.serving_dataset(p)
+        pair = []
         for loss, y in (("ls", y_ls), ("logistic", y_log)):
-            probs.append((p, loss, _lib.Problem(ctx, X32, y, loss=loss, lam2=1e-3, M=2.0, k=10)))
+            pair.append((p, loss, _lib.Problem(ctx, X32, y, loss=loss, lam2=1e-3, M=2.0, k=10)))
+        if not args.no_share:
+            # the logistic relaxation shares the least-squares problem's engine: one pass over
+            # the design per iteration advances the nodes of both
+            pair[0][2].share_design(pair[1][2])
+        probs += pair
         del X32
     print(f"# serving setup {time.perf_counter() - t_setup:.1f}s", file=sys.stderr, flush=True)
     N = args.requests
@@ -237,7 +243,8 @@ def serve(args):
         "dtype": "bf16-mfma/fp32-acc + fp64 bound",
         "data": "synthetic",
         "config": {"workload": SERVE_WORKLOAD, "requests": N, "rate_per_s": args.rate,
-                   "sizes": sizes, "engine": "server"},
+                   "sizes": sizes, "engine": "server",
+                   "engines": "one per problem" if args.no_share else "one per dataset"},
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
                        "p99": round(float(np.percentile(lat_ms, 99)), 3),
                        "max": round(float(lat_ms.max()), 3)},
@@ -476,6 +483,8 @@ def main():
     ap.add_argument("--requests", type=int, default=600, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: mean arrivals per second")
     ap.add_argument("--serve-sizes", default="1000,5000,20000", help="serve: dataset p values")
+    ap.add_argument("--no-share", action="store_true",
+                    help="serve: an engine per problem (the two losses of a dataset apart)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after the run, one device copy of this many bytes (counter calibration)")
     args = ap.parse_args()

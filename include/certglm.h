@@ -172,7 +172,20 @@ int cgl_ctx_kernel_stats(cgl_ctx* ctx, int32_t which, int32_t reset, double* tot
 int cgl_problem_create(cgl_ctx* ctx, const void* X, int32_t x_dtype, int32_t x_mem, int64_t n,
                        int64_t p, int64_t ldx, const double* y, int32_t loss, double lambda2,
                        double M, int32_t k, double L, cgl_problem** out);
+/* Destroying an owner of a shared design (below) leaves its sharers standalone; destroying a
+ * sharer drops it from its owner's engine. Neither may have nodes on a server then. */
 int cgl_problem_destroy(cgl_problem* prob);
+/* Two problems on the same design X (problem (1) with other labels, loss or constants, e.g. a
+ * least-squares and a logistic relaxation of one dataset): from now on the owner's batched
+ * engine also serves the sharer's mixed-precision nodes, so that one pass over the BF16 design
+ * per iteration advances the nodes of both (cgl_solve_batch and the server route the sharer's
+ * nodes there; its FP64-path solves are its own). Each node keeps its own problem's labels,
+ * loss, lambda2, M, k, L and eigen shift. Call before the first mixed-precision solve of either
+ * problem. Errors: CGL_E_INVAL (NULL argument; the same problem twice; different contexts; n, p
+ * or the stored precision differ; the stored designs differ in any bit, compared on the device;
+ * either already shares a design as a sharer, or the sharer has sharers; an engine of either
+ * exists; more than 4 problems on one design). */
+int cgl_problem_share_design(cgl_problem* owner, cgl_problem* sharer);
 /* The Lipschitz constant in use. */
 int cgl_problem_lipschitz(const cgl_problem* prob, double* L);
 /* Eigen-perspective relaxation for least squares (App. D.2): with Q = X^T X - shift I and

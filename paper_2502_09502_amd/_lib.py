@@ -27,7 +27,7 @@ EXPORTS = [
     "cgl_node_validate", "cgl_solve_node", "cgl_solve_batch", "cgl_solve_batch_dual",
     "cgl_certify", "cgl_problem_matvec",
     "cgl_prox_node_batch", "cgl_prox_batch_noalloc", "cgl_problem_set_eigen",
-    "cgl_problem_eigen_shift", "cgl_server_create", "cgl_server_submit", "cgl_server_poll",
+    "cgl_problem_eigen_shift", "cgl_problem_share_design", "cgl_server_create", "cgl_server_submit", "cgl_server_poll",
     "cgl_server_cancel", "cgl_server_stats", "cgl_server_destroy",
 ]
 
@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH):
     lib.cgl_prox_batch_noalloc.argtypes = [P, dbl, dbl, i32, P, i32, i64, P, P]
     lib.cgl_problem_set_eigen.argtypes = [P, dbl]
     lib.cgl_problem_eigen_shift.argtypes = [P, pd]
+    lib.cgl_problem_share_design.argtypes = [P, P]
     if hasattr(lib, "cgl_server_create"):
         lib.cgl_server_create.argtypes = [P, C.c_size_t, i32, C.POINTER(P)]
         lib.cgl_server_submit.argtypes = [P, P, C.POINTER(CglNode), C.POINTER(C.c_uint64)]
@@ -247,6 +248,10 @@ class Problem:
         v = C.c_double()
         check(self.lib.cgl_problem_eigen_shift(self.h, C.byref(v)))
         return v.value
+
+    def share_design(self, other: "Problem") -> None:
+        """Serve other's mixed-precision nodes from this problem's batched engine (same X)."""
+        check(self.lib.cgl_problem_share_design(self.h, other.h))
 
     def node(self, **kw) -> NodeSpec:
         return NodeSpec(self.p, **kw)

@@ -646,11 +646,49 @@ int cgl_problem_create(cgl_ctx* ctx, const void* X, int32_t x_dtype, int32_t x_m
   CGL_API_END
 }
 
+int cgl_problem_share_design(cgl_problem* owner, cgl_problem* sharer) {
+  CGL_API_BEGIN
+  if (!owner || !sharer) invalid("NULL argument");
+  Problem& O = *reinterpret_cast<Problem*>(owner);
+  Problem& Q = *reinterpret_cast<Problem*>(sharer);
+  if (&O == &Q) invalid("a problem cannot share its own design");
+  if (O.ctx != Q.ctx) invalid("the problems belong to different contexts");
+  if (O.n != Q.n || O.p != Q.p || O.xtype != Q.xtype)
+    invalid("the problems differ in n, p or the stored precision of X");
+  if (O.design_owner || Q.design_owner || !Q.sharers.empty())
+    invalid("a problem already shares a design (one owner, sharers of that owner only)");
+  if (O.sharers.size() + 1 >= (size_t)kMaxMembers)
+    invalid("too many problems on one design (at most " + std::to_string(kMaxMembers) + ")");
+  if (O.mixed || Q.mixed)
+    invalid("a batched engine of either problem exists already: share before the first "
+            "mixed-precision solve");
+  CGL_HIP(hipSetDevice(O.ctx->device));
+  DevBuf diff;
+  diff.alloc(sizeof(int));
+  int ndiff = 0;
+  const int64_t bytes = O.n * O.ldx * (O.xtype == XT_F64 ? 8 : (O.xtype == XT_F32 ? 4 : 2));
+  CGL_HIP(hipMemsetAsync(diff.ptr, 0, sizeof(int), O.ctx->stream));
+  launch_count_diff(O.X.ptr, Q.X.ptr, bytes / 4, diff.as<int>(), O.ctx->stream);
+  CGL_HIP(hipMemcpyAsync(&ndiff, diff.ptr, sizeof(int), hipMemcpyDeviceToHost, O.ctx->stream));
+  CGL_HIP(hipStreamSynchronize(O.ctx->stream));
+  if (ndiff != 0) invalid("the problems' designs differ");
+  O.sharers.push_back(&Q);
+  Q.design_owner = &O;
+  return CGL_OK;
+  CGL_API_END
+}
+
 int cgl_problem_destroy(cgl_problem* prob) {
   CGL_API_BEGIN
   if (!prob) return CGL_OK;
   Problem* P = reinterpret_cast<Problem*>(prob);
   (void)hipSetDevice(P->ctx->device);
+  if (Problem* O = P->design_owner) {
+    // the owner's engine keeps its copies of P's labels; it stops naming P
+    O->sharers.erase(std::remove(O->sharers.begin(), O->sharers.end(), P), O->sharers.end());
+    if (O->mixed) O->mixed->forget_member(P);
+  }
+  for (Problem* Q : P->sharers) Q->design_owner = nullptr;  // standalone from now on
   delete P;
   return CGL_OK;
   CGL_API_END
@@ -689,8 +727,9 @@ int cgl_problem_set_eigen(cgl_problem* prob, double shift) {
   Problem& P = *reinterpret_cast<Problem*>(prob);
   if (P.loss != LOSS_LS) invalid("the eigen-perspective relaxation is for least squares");
   if (!(shift >= 0.0) || !std::isfinite(shift)) invalid("shift must be >= 0");
-  if ((P.mixed && (P.mixed->in_flight || P.mixed->free_slots() != P.mixed->S)) || P.plain.busy)
-    invalid("a server runs nodes of the problem");
+  const Problem& E = P.engine_problem();
+  if ((E.mixed && (E.mixed->in_flight || E.mixed->free_slots() != E.mixed->S)) || P.plain.busy)
+    invalid("a server runs nodes of the problem or of one sharing its design");
   CGL_HIP(hipSetDevice(P.ctx->device));
   if (P.lam_max <= 0.0) P.lam_max = power_lambda_max(P);
   if (shift >= P.lam_max) invalid("shift must be below lambda_max(X^T X)");

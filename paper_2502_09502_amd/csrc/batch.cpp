@@ -56,6 +56,11 @@ void MixedWork::ensure(Problem& P) {
     if (e && std::atoi(e) > 0) *dst = std::atoi(e);
   }
   chunk = std::min(chunk, 16);  // its timing events (4 per cycle) stay below those of the FP64 rounds
+  // the problems the engine serves: its own and those declared to share its design
+  members.assign(1, &P);
+  for (Problem* Q : P.sharers) members.push_back(Q);
+  bool any_ls = false, any_other = false;
+  for (Problem* Q : members) (Q->loss == LOSS_LS ? any_ls : any_other) = true;
   S = kSlots;
   S_pad = (int)round_up(S, 256);
   n_pad = round_up(P.n, GT_M);  // rows of X~: a multiple of the GEMM tile and of its k-chunk grain
@@ -65,9 +70,14 @@ void MixedWork::ensure(Problem& P) {
   Xbt.alloc((size_t)ldp * n_pad * 2);
   launch_make_bf16(P.xtype, P.X.ptr, P.ldx, P.n, P.p, n_pad, ldp, Xb.as<uint16_t>(),
                    Xbt.as<uint16_t>(), s);
-  ypad.alloc((size_t)n_pad * 8);
-  CGL_HIP(hipMemsetAsync(ypad.ptr, 0, (size_t)n_pad * 8, s));
-  CGL_HIP(hipMemcpyAsync(ypad.ptr, P.y.ptr, (size_t)P.n * 8, hipMemcpyDeviceToDevice, s));
+  mbufs.clear();
+  for (Problem* Q : members) {
+    mbufs.emplace_back(new MemberBufs());
+    DevBuf& yp = mbufs.back()->y;
+    yp.alloc((size_t)n_pad * 8);
+    CGL_HIP(hipMemsetAsync(yp.ptr, 0, (size_t)n_pad * 8, s));
+    CGL_HIP(hipMemcpyAsync(yp.ptr, Q->y.ptr, (size_t)P.n * 8, hipMemcpyDeviceToDevice, s));
+  }
   // slots
   const size_t Sp = (size_t)S * ldp, Sn = (size_t)S * n_pad;
   st.alloc(st_bytes());
@@ -75,9 +85,9 @@ void MixedWork::ensure(Problem& P) {
   bring.alloc(3 * Sp * 8);
   beta0.alloc(Sp * 8);
   H0.alloc(Sp * 8);
-  base0.alloc(P.loss == LOSS_LS ? 8 : Sn * 8);
-  base1.alloc(P.loss == LOSS_LS ? 8 : Sn * 8);
-  e0f.alloc(P.loss == LOSS_LS ? Sn * 4 : 8);
+  base0.alloc(any_other ? Sn * 8 : 8);
+  base1.alloc(any_other ? Sn * 8 : 8);
+  e0f.alloc(any_ls ? Sn * 4 : 8);
   bres.alloc(Sp * 8);
   bdual.alloc(Sp * 8);
   dop.alloc((size_t)S_pad * ldp * 2);
@@ -132,37 +142,36 @@ void MixedWork::ensure(Problem& P) {
   ncchunk = (int)((n_pad + cchunk - 1) / cchunk);
   cpart.alloc((size_t)S * ncchunk * 16);
   list.alloc((size_t)S * sizeof(int));
-  // cold-start base: u_0 = 0, r_0 = grad f(0) = a + b y (per loss), H_0 = X^T r_0 in FP64
-  {
+  // cold-start base of each problem: u_0 = 0, r_0 = grad f(0) = a + b y (per loss), H_0 = X^T r_0
+  // in FP64
+  for (size_t m = 0; m < members.size(); ++m) {
+    const Problem& Q = *members[m];
+    MemberBufs& B = *mbufs[m];
     const PlainGeom g = plain_geometry(P.xtype, P.n, P.ldx);
     std::vector<double> yv((size_t)P.n), r0((size_t)P.n);
-    CGL_HIP(hipMemcpy(yv.data(), P.y.ptr, (size_t)P.n * 8, hipMemcpyDeviceToHost));
-    const double ga = loss_grad0_a(P.loss), gb = loss_grad0_b(P.loss);
+    CGL_HIP(hipMemcpy(yv.data(), Q.y.ptr, (size_t)P.n * 8, hipMemcpyDeviceToHost));
+    const double ga = loss_grad0_a(Q.loss), gb = loss_grad0_b(Q.loss);
     for (int64_t i = 0; i < P.n; ++i) r0[(size_t)i] = ga + gb * yv[(size_t)i];
     DevBuf part, dr0;
     part.alloc((size_t)g.nchunks * P.ldx * 8);
     dr0.alloc((size_t)P.n * 8);
     CGL_HIP(hipMemcpy(dr0.ptr, r0.data(), (size_t)P.n * 8, hipMemcpyHostToDevice));
-    H0_cold.alloc((size_t)ldp * 8);
-    CGL_HIP(hipMemsetAsync(H0_cold.ptr, 0, (size_t)ldp * 8, s));
+    B.H0c.alloc((size_t)ldp * 8);
+    CGL_HIP(hipMemsetAsync(B.H0c.ptr, 0, (size_t)ldp * 8, s));
     launch_xt(P.xtype, P.X.ptr, P.ldx, P.n, P.ldx, g, dr0.as<double>(), 0, nullptr, nullptr, 0,
               1, part.as<double>(), nullptr, s);
     launch_grad_step(part.as<double>(), g.nchunks, P.ldx, nullptr, nullptr, 0, 0.0,
-                     H0_cold.as<double>(), nullptr, s);
+                     B.H0c.as<double>(), nullptr, s);
     CGL_HIP(hipStreamSynchronize(s));
     std::vector<double> b0((size_t)n_pad, 0.0), b1((size_t)n_pad, 0.0);
     for (int64_t i = 0; i < P.n; ++i) {
-      if (P.loss == LOSS_LS) b0[(size_t)i] = -yv[(size_t)i];  // e_0 = 0 - y
+      if (Q.loss == LOSS_LS) b0[(size_t)i] = -yv[(size_t)i];  // e_0 = 0 - y
       else b1[(size_t)i] = r0[(size_t)i];                      // r_0, with u_0 = 0
     }
-    base0_cold.alloc((size_t)n_pad * 8);
-    base1_cold.alloc((size_t)n_pad * 8);
-    CGL_HIP(hipMemcpy(base0_cold.ptr, b0.data(), (size_t)n_pad * 8, hipMemcpyHostToDevice));
-    CGL_HIP(hipMemcpy(base1_cold.ptr, b1.data(), (size_t)n_pad * 8, hipMemcpyHostToDevice));
-    double f0 = 0.0;
-    for (int64_t i = 0; i < P.n; ++i)
-      f0 += loss_at0(P.loss, yv[(size_t)i]);
-    f_cold = f0;
+    B.b0c.alloc((size_t)n_pad * 8);
+    B.b1c.alloc((size_t)n_pad * 8);
+    CGL_HIP(hipMemcpy(B.b0c.ptr, b0.data(), (size_t)n_pad * 8, hipMemcpyHostToDevice));
+    CGL_HIP(hipMemcpy(B.b1c.ptr, b1.data(), (size_t)n_pad * 8, hipMemcpyHostToDevice));
   }
   // Least squares with n >= p: G = X^T X in FP64 (2 n p^2 FLOP, once per engine), so that a
   // certification round gets X^T grad f(X beta) = 2 G beta - 2 X^T y from the rows of G on the
@@ -170,7 +179,7 @@ void MixedWork::ensure(Problem& P) {
   // off.
   {
     const char* ng = std::getenv("CGL_NO_GRAM");
-    if (P.loss == LOSS_LS && P.n >= P.p && P.p <= kGramMaxP && !(ng && std::atoi(ng) > 0)) {
+    if (any_ls && P.n >= P.p && P.p <= kGramMaxP && !(ng && std::atoi(ng) > 0)) {
       ldg = round_up(P.p, 256);
       G.alloc((size_t)P.p * ldg * 8);
       CGL_HIP(hipMemsetAsync(G.ptr, 0, G.bytes, s));
@@ -199,13 +208,23 @@ void MixedWork::ensure(Problem& P) {
   md.p = P.p;
   md.n_pad = n_pad;
   md.ldp = ldp;
-  md.y = ypad.as<double>();
-  md.loss = P.loss;
-  md.lam2 = P.lam2;
-  md.M = P.M;
-  md.L = P.L;
-  md.rho = P.rho;
-  md.shift = P.shift;
+  memtab.alloc(kMaxMembers * sizeof(MemberDev));
+  for (size_t m = 0; m < members.size(); ++m) {
+    MemberDev& d = mem_host[m];
+    const Problem& Q = *members[m];
+    d.y = mbufs[m]->y.as<double>();
+    d.H0c = mbufs[m]->H0c.as<double>();
+    d.b0c = mbufs[m]->b0c.as<double>();
+    d.b1c = mbufs[m]->b1c.as<double>();
+    d.loss = Q.loss;
+    d.lam2 = Q.lam2;
+    d.M = Q.M;
+    d.L = Q.L;
+    d.rho = Q.rho;
+    d.shift = Q.shift;
+  }
+  CGL_HIP(hipMemcpyAsync(memtab.ptr, mem_host, sizeof(mem_host), hipMemcpyHostToDevice, s));
+  md.mem = memtab.as<MemberDev>();
   md.cert_gap = kCertGap;
   md.stall_cycles = kStallCycles;
   {  // tuning knobs of the certification requests (defaults: the fastest of a sweep on the
@@ -295,15 +314,35 @@ void MixedWork::ensure(Problem& P) {
 }
 
 void MixedWork::set_relaxation(Problem& P) {
-  if (md.L == P.L && md.rho == P.rho && md.shift == P.shift) return;
-  md.L = P.L;
-  md.rho = P.rho;
-  md.shift = P.shift;
-  // the kernels of a captured chunk hold the old values
-  if (graph_exec) {
-    CGL_HIP(hipGraphExecDestroy(graph_exec));
-    graph_exec = nullptr;
+  (void)P;
+  bool changed = false;
+  for (size_t m = 0; m < members.size(); ++m) {
+    if (!members[m]) continue;
+    MemberDev& d = mem_host[m];
+    const Problem& Q = *members[m];
+    if (d.L == Q.L && d.rho == Q.rho && d.shift == Q.shift) continue;
+    d.L = Q.L;
+    d.rho = Q.rho;
+    d.shift = Q.shift;
+    changed = true;
   }
+  if (!changed) return;
+  // the engine is idle: the table is read by launches queued after this copy (the host image
+  // stays unchanged until the copy has run: the next change needs another idle engine, after a
+  // synchronisation)
+  CGL_HIP(hipMemcpyAsync(memtab.ptr, mem_host, sizeof(mem_host), hipMemcpyHostToDevice, stream));
+  CGL_HIP(hipStreamSynchronize(stream));
+}
+
+int MixedWork::member_of(const Problem* Q) const {
+  for (size_t m = 0; m < members.size(); ++m)
+    if (members[m] == Q) return (int)m;
+  return -1;
+}
+
+void MixedWork::forget_member(const Problem* Q) {
+  for (auto& m : members)
+    if (m == Q) m = nullptr;  // the table entry stays (a slot may still name it until retired)
 }
 
 std::vector<int> MixedWork::split_candidates(int64_t m_tiles, int64_t K) {
@@ -594,12 +633,13 @@ int MixedWork::cert_round(Problem& P, bool overlap) {
                        nq, U64.as<double>(), n_pad, part64.as<double>(), part64_cap, s);
   if (e1) CGL_HIP(hipEventRecord(e1, s));
   // X^T grad f(X beta): least squares from the Gram rows on the same support (p K against n p
-  // products), else the FP64 product with all of X^T
-  const bool gram = G.ptr != nullptr;
+  // products), else (a round with nodes of other losses too) the FP64 product with all of X^T
+  bool gram = G.ptr != nullptr;
+  for (int sl : want) gram = gram && mem_host[st_host[sl].member].loss == LOSS_LS;
   if (gram) {
     launch_gemm_f64_rows(XT_F64, G.ptr, ldg, sidx.as<int>(), P.p, P.p, kdev, Bu.as<double>(), ldp,
                          nq, H64.as<double>(), ldp, part64.as<double>(), part64_cap, s);
-    launch_gram_finish(H64.as<double>(), ldp, P.p, nq, H0_cold.as<double>(), s);
+    launch_gram_finish(H64.as<double>(), ldp, P.p, nq, md, list.as<int>(), s);
   }
   launch_cert_resid(md, list.as<int>(), nq, U64.as<double>(), R64.as<double>(),
                     cpart.as<double>(), ncchunk, cchunk, s);
@@ -641,13 +681,14 @@ void MixedWork::close_round(Problem& P) {
 }
 
 size_t MixedWork::device_bytes() const {
-  const DevBuf* bufs[] = {&Xb, &Xbt, &ypad, &st, &cls, &bring, &beta0, &H0, &base0, &base1, &e0f,
+  const DevBuf* bufs[] = {&Xb, &Xbt, &memtab, &st, &cls, &bring, &beta0, &H0, &base0, &base1, &e0f,
                           &bres, &bdual, &dop, &gop, &dU, &dUp, &dH, &lpart, &npart, &fpart, &cycle, &prevsel, &B64,
-                          &U64, &R64, &H64, &cpart, &list, &H0_cold, &base0_cold, &base1_cold,
+                          &U64, &R64, &H64, &cpart, &list,
                           &Xt, &part64, &sflag, &sidx, &scount, &Bu, &G, &pinv, &pinv_new,
                           &perm, &perm_new, &dop_tmp, &pfx, &sj, &sv, &Bret};
   size_t b = 0;
   for (const DevBuf* d : bufs) b += d->bytes;
+  for (const auto& m : mbufs) b += m->y.bytes + m->H0c.bytes + m->b0c.bytes + m->b1c.bytes;
   return b;
 }
 
@@ -666,6 +707,7 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
     slots.push_back(sl);
     slot_owner[(size_t)sl] = a.owner;
     NodeDev d = make_node_dev(a.node, a.host);
+    d.member = a.member;
     d.active = 1;
     d.primed = 0;
     d.P_best = HUGE_VAL;
@@ -690,8 +732,23 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
     admitted_at[sl] = cycles;
   }
   upload_list(P, slots, kListAdmit);
-  launch_admit(md, list.as<int>(), (int)slots.size(), H0_cold.as<double>(),
-               base0_cold.as<double>(), base1_cold.as<double>(), s);
+  // the admitted slots' class rows and states, one copy per run of consecutive slots (the other
+  // slots' device states stay as they are: a certification round queued earlier may still be
+  // writing them); the cold-start kernel then reads each slot's problem from its state
+  {
+    std::vector<int> ss = slots;
+    std::sort(ss.begin(), ss.end());
+    for (size_t a = 0; a < ss.size();) {
+      size_t b = a + 1;
+      while (b < ss.size() && ss[b] == ss[b - 1] + 1) ++b;
+      const size_t off = (size_t)ss[a] * ldp, len = (b - a) * (size_t)ldp;
+      CGL_HIP(hipMemcpyAsync((uint8_t*)cls.ptr + off, cls_host + off, len, hipMemcpyHostToDevice, s));
+      CGL_HIP(hipMemcpyAsync(st.as<NodeDev>() + ss[a], st_host + ss[a], (b - a) * sizeof(NodeDev),
+                             hipMemcpyHostToDevice, s));
+      a = b;
+    }
+  }
+  launch_admit(md, list.as<int>(), (int)slots.size(), s);
   // warm starts (fixed-zero coordinates set to 0) into the iterate ring, the base and the best
   std::vector<std::vector<double>> starts;
   for (const Admission& a : adm) {
@@ -708,22 +765,6 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
                            hipMemcpyHostToDevice, s));
     CGL_HIP(hipMemcpyAsync(bres.as<double>() + o, ws.data(), (size_t)P.p * 8,
                            hipMemcpyHostToDevice, s));
-  }
-  // the admitted slots' class rows and states, one copy per run of consecutive slots (the other
-  // slots' device states stay as they are: a certification round queued earlier may still be
-  // writing them)
-  {
-    std::vector<int> ss = slots;
-    std::sort(ss.begin(), ss.end());
-    for (size_t a = 0; a < ss.size();) {
-      size_t b = a + 1;
-      while (b < ss.size() && ss[b] == ss[b - 1] + 1) ++b;
-      const size_t off = (size_t)ss[a] * ldp, len = (b - a) * (size_t)ldp;
-      CGL_HIP(hipMemcpyAsync((uint8_t*)cls.ptr + off, cls_host + off, len, hipMemcpyHostToDevice, s));
-      CGL_HIP(hipMemcpyAsync(st.as<NodeDev>() + ss[a], st_host + ss[a], (b - a) * sizeof(NodeDev),
-                             hipMemcpyHostToDevice, s));
-      a = b;
-    }
   }
   CGL_HIP(hipStreamSynchronize(s));
   if (reorder && (int)adm.size() >= S / 4) {
@@ -821,16 +862,21 @@ void MixedWork::push_states(Problem& P) {
                          stream));
 }
 
-void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_out,
+void solve_mixed(Problem& Pm, const cgl_node* nodes, int32_t count, double* beta_out,
                  cgl_result* res, const int32_t* rows, double* dual_out) {
   // node i reports into the caller's row rows[i] (res and beta_out), or row i
   auto row = [&](int32_t i) -> int64_t { return rows ? rows[i] : i; };
+  // the nodes are Pm's; the engine is that of the problem owning Pm's design (Pm itself unless
+  // Pm shares another problem's design)
+  Problem& P = Pm.engine_problem();
   if (!P.mixed) P.mixed = new MixedWork();
   MixedWork& W = *P.mixed;
   W.ensure(P);
+  const int member = W.member_of(&Pm);
+  if (member < 0) invalid("the problem's design was shared after its owner's engine was built");
   if (W.free_slots() != W.S)
     invalid("the problem's batched engine is in use by a server; solve through the server");
-  if (P.shift != 0.0 && P.loss != LOSS_LS)
+  if (Pm.shift != 0.0 && Pm.loss != LOSS_LS)
     invalid("the eigen-perspective relaxation is for least squares");
   if (W.in_flight) invalid("the problem's batched engine is in use by a server");
   W.set_relaxation(P);
@@ -841,7 +887,7 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
   std::vector<NodeHost> hosts;
   hosts.reserve((size_t)count);
   for (int32_t i = 0; i < count; ++i) {
-    hosts.push_back(make_node_host(nodes[i], P.p, P.k));
+    hosts.push_back(make_node_host(nodes[i], P.p, Pm.k));
   }
   int32_t next = 0, finished = 0;
   // infeasible nodes never take a slot
@@ -859,7 +905,7 @@ void solve_mixed(Problem& P, const cgl_node* nodes, int32_t count, double* beta_
       if (W.slot_owner[(size_t)sl] >= 0) continue;
       while (next < count && handled[(size_t)next]) ++next;
       if (next >= count) break;
-      adm.push_back(Admission{sl, next, nodes[next], hosts[(size_t)next]});
+      adm.push_back(Admission{sl, next, nodes[next], hosts[(size_t)next], member});
       ++next;
     }
     W.admit(P, adm);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
 #include <vector>
 
 #include "engine.h"
@@ -23,6 +24,12 @@ struct Admission {
   int owner;  // caller's index (solve) or request id (server)
   cgl_node node;
   NodeHost host;
+  int member = 0;  // index of the node's problem among the engine's problems
+};
+
+// Device buffers of one problem served by an engine (labels and cold-start base).
+struct MemberBufs {
+  DevBuf y, H0c, b0c, b1c;
 };
 
 struct MixedWork {
@@ -34,9 +41,16 @@ struct MixedWork {
   int nrt = 0, ncchunk = 0, ksx = 1;
   int64_t x_kchunk = 0;
   int64_t rchunk = 0, cchunk = 0;
-  double f_cold = 0.0;
-  DevBuf Xb, Xbt, ypad, st, cls, bring, beta0, H0, base0, base1, e0f, bres, bdual, dop, gop, dU, dUp, dH, lpart, npart,
-      fpart, cycle, prevsel, B64, U64, R64, H64, cpart, list, H0_cold, base0_cold, base1_cold, Xt, part64,
+  // the problems served (members[0] is the engine's own; the others share its design), their
+  // buffers and the device table the kernels read (a slot's state names its problem)
+  std::vector<Problem*> members;
+  std::vector<std::unique_ptr<MemberBufs>> mbufs;
+  MemberDev mem_host[kMaxMembers] = {};
+  DevBuf memtab;
+  int member_of(const Problem* Q) const;  // index in members, -1 if not served
+  void forget_member(const Problem* Q);    // a sharer is destroyed: no more nodes of it come
+  DevBuf Xb, Xbt, st, cls, bring, beta0, H0, base0, base1, e0f, bres, bdual, dop, gop, dU, dUp, dH, lpart, npart,
+      fpart, cycle, prevsel, B64, U64, R64, H64, cpart, list, Xt, part64,
       sflag, sidx, scount, Bu, G, Bret, pinv, pinv_new, perm, perm_new, dop_tmp, pfx, sj, sv;
   int64_t ldg = 0;  // least squares: G = X^T X in FP64 (p x ldg), when built
   size_t part64_cap = 0;

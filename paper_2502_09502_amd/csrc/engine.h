@@ -108,6 +108,11 @@ struct Problem {
   double lam_max = 0.0;        // lambda_max(X^T X) estimate when the library computed L
   MixedWork* mixed = nullptr;  // created on first mixed solve
   size_t mixed_bytes = 0;      // its device footprint, once known
+  // Problems on the same design (cgl_problem_share_design): an owner's batched engine serves
+  // its sharers' mixed-precision nodes too; a sharer names its owner and has no engine.
+  std::vector<Problem*> sharers;
+  Problem* design_owner = nullptr;
+  Problem& engine_problem() { return design_owner ? *design_owner : *this; }
   ~Problem();
 };
 

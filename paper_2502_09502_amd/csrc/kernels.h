@@ -61,5 +61,7 @@ void launch_g_gstar(int nodes, const double* beta, int64_t b_ld, const double* h
 // *bad += number of non-finite values among the count stored elements of X (BF16: exponent all
 // ones); *bad must start at zero.
 void launch_count_nonfinite(int xtype, const void* X, int64_t count, int* bad, hipStream_t s);
+// diff += number of 32-bit words where two device buffers differ (words 32-bit words each).
+void launch_count_diff(const void* a, const void* b, int64_t words, int* diff, hipStream_t s);
 
 }  // namespace cgl

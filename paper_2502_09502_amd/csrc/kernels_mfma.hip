@@ -59,6 +59,9 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
   const int slot = blockIdx.y;
   const NodeDev* st = md.st + slot;
   if (!slot_running(st)) return;
+  const MemberDev& mb = md.mem[st->member];
+  const int loss = mb.loss;
+  const double* yv = mb.y;
   const int cyc = *md.cycle;
   const bool rebase = st->rebase != 0;
   float* dun = md.dU + (int64_t)(cyc & 1) * md.dU_ring + (int64_t)slot * md.n_pad;
@@ -118,7 +121,7 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
     }
     *reinterpret_cast<float4*>(dun + i) = du;
     const float dv[4] = {du.x, du.y, du.z, du.w};
-    if (md.loss == LOSS_LS) {
+    if (loss == LOSS_LS) {
       const float4 e4 = *reinterpret_cast<const float4*>(md.e0f + (int64_t)slot * md.n_pad + i);
       const float ev[4] = {e4.x, e4.y, e4.z, e4.w};
       for (int c = 0; c < 4; ++c) {
@@ -135,9 +138,9 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
       for (int c = 0; c < 4; ++c)
         if (i + c < md.n) {
           const double u = md.base0[(int64_t)slot * md.n_pad + i + c] + (double)dv[c];
-          ls += loss_val(md.loss, u, md.y[i + c]);
+          ls += loss_val(loss, u, yv[i + c]);
           if (noise) {
-            const double t = loss_grad(md.loss, u, md.y[i + c]) * (double)dv[c];
+            const double t = loss_grad(loss, u, yv[i + c]) * (double)dv[c];
             nz += t * t;
           }
         }
@@ -167,6 +170,8 @@ __global__ __launch_bounds__(256) void k_mixed_resid(MixedDev md) {
   const int slot = blockIdx.y;
   NodeDev* st = md.st + slot;
   if (!slot_running(st)) return;
+  const MemberDev& mb = md.mem[st->member];
+  const int loss = mb.loss;
   const int cyc = *md.cycle;
   const float* dun = md.dU + (int64_t)(cyc & 1) * md.dU_ring + (int64_t)slot * md.n_pad;
   const float* duo = md.dU + (int64_t)((cyc + 1) & 1) * md.dU_ring + (int64_t)slot * md.n_pad;
@@ -181,7 +186,7 @@ __global__ __launch_bounds__(256) void k_mixed_resid(MixedDev md) {
     // rounding margin of the working objective (zero: Alg. 3's plain comparison)
     const double margin = md.restart_slack * 0x1p-9 * sqrt(nz);
     if (threadIdx.x == 0) {
-      const double Lnew = a - md.shift * st->bsq_new + 2.0 * (md.lam2 + md.shift) * st->g_new;
+      const double Lnew = a - mb.shift * st->bsq_new + 2.0 * (mb.lam2 + mb.shift) * st->g_new;
       double phi = st->phi;
       int primed = st->primed, restarts = st->restarts;
       if (!primed) {
@@ -217,7 +222,7 @@ __global__ __launch_bounds__(256) void k_mixed_resid(MixedDev md) {
     const float4 o4 = *reinterpret_cast<const float4*>(duo + i);
     const float nv[4] = {n4.x, n4.y, n4.z, n4.w}, ov[4] = {o4.x, o4.y, o4.z, o4.w};
     float ev[4] = {0.f, 0.f, 0.f, 0.f};
-    if (md.loss == LOSS_LS) {
+    if (loss == LOSS_LS) {
       const float4 e4 = *reinterpret_cast<const float4*>(md.e0f + (int64_t)slot * md.n_pad + i);
       ev[0] = e4.x;
       ev[1] = e4.y;
@@ -228,16 +233,16 @@ __global__ __launch_bounds__(256) void k_mixed_resid(MixedDev md) {
     for (int k = 0; k < 4; ++k) {
       if (i + k >= md.n) continue;
       const double dg = (double)nv[k] + c * ((double)nv[k] - (double)ov[k]);
-      const double y = md.y[i + k];
-      if (md.loss == LOSS_LS) {
+      const double y = mb.y[i + k];
+      if (loss == LOSS_LS) {
         const double e = (double)ev[k] + dg;  // u_gamma - y
         const double r = 2.0 * e;
         fs += 0.25 * r * r + y * r;  // F*(-zeta), zeta = -r: ||zeta||^2/4 - y.zeta
         gv[k] = float_to_bf16((float)(2.0 * dg));
       } else {  // base0 holds u_0, base1 holds r_0 = grad f(u_0)
         const double u = md.base0[(int64_t)slot * md.n_pad + i + k] + dg;
-        const double r = loss_grad(md.loss, u, y);
-        fs += fstar_term(md.loss, u, y);
+        const double r = loss_grad(loss, u, y);
+        fs += fstar_term(loss, u, y);
         gv[k] = float_to_bf16((float)(r - md.base1[(int64_t)slot * md.n_pad + i + k]));
       }
     }
@@ -261,6 +266,8 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
   const int slot = blockIdx.x;
   NodeDev* st = md.st + slot;
   if (!slot_running(st)) return;
+  const MemberDev& mb = md.mem[st->member];
+  const double mM = mb.M, mrho = mb.rho;
   const int cyc = *md.cycle;
   const int64_t p = md.p;
   const double* bt1 = md.bring + (int64_t)(cyc % 3) * md.bring_stride + (int64_t)slot * md.ldp;
@@ -280,7 +287,7 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
     st->rebase = 0;  // read by the loss and residual kernels of this cycle only
   }
   const double c = st->c;
-  const double invL = 1.0 / md.L;
+  const double invL = 1.0 / mb.L;
   const int iter = st->iter;
   const bool check = (iter % st->check_every) == 0;
   // H at gamma (FP64 base + BF16-product corrections) into the per-thread value slice
@@ -330,8 +337,8 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
   }
   // eigen-perspective shift: the gradient at gamma is X^T grad f(X gamma) - 2 s gamma, and the
   // bound gains s ||gamma||^2 (uniform branch: the shift is a launch argument)
-  const double shift = md.shift;
-  const double two_le = 2.0 * (md.lam2 + shift);
+  const double shift = mb.shift;
+  const double two_le = 2.0 * (mb.lam2 + shift);
   double gsq = 0.0;
   if (shift != 0.0) {
 #pragma unroll
@@ -352,7 +359,7 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
   double gs = 0.0;
   if (check)
     gs = gstar_node<E>([&](int s) { return fabs(pv.get(s)); }, two_le, cb, st->kp,
-                       st->nfree, md.M, sm, slice, md.prevtop + (int64_t)slot * 65);
+                       st->nfree, mM, sm, slice, md.prevtop + (int64_t)slot * 65);
   // gradient step w = gamma - H / L; the slice then holds u = rho |w|, the signs a mask
   uint32_t neg = 0;
 #pragma unroll
@@ -365,7 +372,7 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
       w = gam - pv.get(s) * invL;
     }
     neg |= (w < 0.0 ? 1u : 0u) << s;
-    pv.set(s, md.rho * fabs(w));
+    pv.set(s, mrho * fabs(w));
   }
   const int64_t nbk = md.S_pad >> 5;
   // operand extent (LDS: nothing extra stays live through the prox)
@@ -374,7 +381,7 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
   __syncthreads();
   double bsq = 0.0;
   const ProxOut po = node_prox<E>(
-      [&](int s) { return pv.get(s); }, neg, cb, st->kp, st->nfree, md.rho, md.M, st->vstar,
+      [&](int s) { return pv.get(s); }, neg, cb, st->kp, st->nfree, mrho, mM, st->vstar,
       [&](int s, double b) {
         const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
         bsq += b * b;
@@ -572,29 +579,31 @@ __global__ __launch_bounds__(256) void k_cert_resid(MixedDev md, const int* list
   const int q = blockIdx.y;
   if (q >= nq) return;
   const int slot = list[q];
+  const MemberDev& mb = md.mem[md.st[slot].member];
+  const int loss = mb.loss;
   const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(md.n_pad, i0 + chunk);
   double ls = 0.0, fs = 0.0;
   for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
     double r = 0.0, b0 = 0.0, b1 = 0.0;
     if (i < md.n) {
       const double u = U64[(int64_t)q * md.n_pad + i];
-      const double y = md.y[i];
-      if (md.loss == LOSS_LS) {
+      const double y = mb.y[i];
+      if (loss == LOSS_LS) {
         const double e = u - y;
         r = 2.0 * e;
         ls += e * e;
         fs += 0.25 * r * r + y * r;
         b0 = e;
       } else {
-        r = loss_grad(md.loss, u, y);
-        ls += loss_val(md.loss, u, y);
-        fs += fstar_term(md.loss, u, y);
+        r = loss_grad(loss, u, y);
+        ls += loss_val(loss, u, y);
+        fs += fstar_term(loss, u, y);
         b0 = u;
         b1 = r;
       }
     }
     R64[(int64_t)q * md.n_pad + i] = r;
-    if (md.loss == LOSS_LS) {
+    if (loss == LOSS_LS) {
       md.e0f[(int64_t)slot * md.n_pad + i] = (float)b0;
     } else {
       md.base0[(int64_t)slot * md.n_pad + i] = b0;
@@ -640,8 +649,9 @@ __global__ __launch_bounds__(1024) void k_cert_finish(MixedDev md, const int* li
   uint64_t cb = 0;
   // eigen-perspective shift s: the gradient at beta is X^T grad f(X beta) - 2 s beta, the
   // objective loses s ||beta||^2 and the bound gains it (App. D.2); 0 for the perspective bound
-  const double shift = md.shift;
-  const double two_le = 2.0 * (md.lam2 + shift);
+  const MemberDev& mb = md.mem[st->member];
+  const double shift = mb.shift;
+  const double two_le = 2.0 * (mb.lam2 + shift);
   double bsq = 0.0;
 #pragma unroll
   for (int s = 0; s < E; ++s) {
@@ -657,7 +667,7 @@ __global__ __launch_bounds__(1024) void k_cert_finish(MixedDev md, const int* li
     }
   }
   const double gs = gstar_node<E>([&](int s) { return hv.get(s); }, two_le, cb, st->kp,
-                                  st->nfree, md.M, sm);
+                                  st->nfree, mb.M, sm);
   double acc[3] = {0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < nchunk; i += blockDim.x) {
     acc[0] += part[((int64_t)q * nchunk + i) * 2];
@@ -729,14 +739,17 @@ __global__ __launch_bounds__(1024) void k_cert_finish(MixedDev md, const int* li
   }
 }
 
-// Admission from the cold start beta = 0 (the base quantities are the same for every node:
-// u_0 = 0, r_0 = grad f(0), H_0 = X^T r_0).
-__global__ __launch_bounds__(256) void k_admit(MixedDev md, const int* list, int nq,
-                                               const double* H0_cold, const double* base0_cold,
-                                               const double* base1_cold) {
+// Admission from the cold start beta = 0 (the base quantities are the same for every node of
+// a problem: u_0 = 0, r_0 = grad f(0), H_0 = X^T r_0). The slot's state (with its problem) has
+// been written before this kernel.
+__global__ __launch_bounds__(256) void k_admit(MixedDev md, const int* list, int nq) {
   const int q = blockIdx.y;
   if (q >= nq) return;
   const int slot = list[q];
+  const MemberDev& mb = md.mem[md.st[slot].member];
+  const double* H0_cold = mb.H0c;
+  const double* base0_cold = mb.b0c;
+  const double* base1_cold = mb.b1c;
   const int64_t stride = (int64_t)gridDim.x * 256;
   if (blockIdx.x == 0 && threadIdx.x == 0) {  // no selection history for a new node
     md.prevhead[(int64_t)slot * 65] = 0;
@@ -754,7 +767,7 @@ __global__ __launch_bounds__(256) void k_admit(MixedDev md, const int* list, int
   }
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < md.n_pad; i += stride) {
     const int64_t o = (int64_t)slot * md.n_pad + i;
-    if (md.loss == LOSS_LS) {
+    if (mb.loss == LOSS_LS) {
       md.e0f[o] = (float)base0_cold[i];
     } else {
       md.base0[o] = base0_cold[i];
@@ -766,10 +779,8 @@ __global__ __launch_bounds__(256) void k_admit(MixedDev md, const int* list, int
   }
 }
 
-void launch_admit(const MixedDev& md, const int* list, int nq, const double* H0_cold,
-                  const double* base0_cold, const double* base1_cold, hipStream_t s) {
-  hipLaunchKernelGGL(k_admit, dim3(16, (unsigned)nq), dim3(256), 0, s, md, list, nq, H0_cold,
-                     base0_cold, base1_cold);
+void launch_admit(const MixedDev& md, const int* list, int nq, hipStream_t s) {
+  hipLaunchKernelGGL(k_admit, dim3(16, (unsigned)nq), dim3(256), 0, s, md, list, nq);
 }
 
 // dst (nq x p, contiguous) = rows list[q] of src (leading dimension ld).
@@ -950,17 +961,19 @@ void launch_widen(int xtype, const void* src, int64_t ld, int64_t rows, int64_t 
 }
 
 // Least squares: X^T grad f(X beta) = 2 X^T X beta - 2 X^T y. H[q][j] holds (X^T X beta_q)_j on
-// entry and the gradient on exit; h0 = X^T grad f(0) = -2 X^T y.
+// entry and the gradient on exit; h0 = X^T grad f(0) = -2 X^T y of slot list[q]'s problem.
 __global__ __launch_bounds__(256) void k_gram_finish(double* H, int64_t ld, int64_t p,
-                                                     const double* h0) {
+                                                     MixedDev md, const int* list) {
   const int q = blockIdx.y;
+  const double* h0 = md.mem[md.st[list[q]].member].H0c;
   for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < p; j += (int64_t)gridDim.x * 256)
     H[(int64_t)q * ld + j] = 2.0 * H[(int64_t)q * ld + j] + h0[j];
 }
 
-void launch_gram_finish(double* H, int64_t ld, int64_t p, int nq, const double* h0, hipStream_t s) {
+void launch_gram_finish(double* H, int64_t ld, int64_t p, int nq, const MixedDev& md,
+                        const int* list, hipStream_t s) {
   if (nq <= 0) return;
-  hipLaunchKernelGGL(k_gram_finish, dim3(8, (unsigned)nq), dim3(256), 0, s, H, ld, p, h0);
+  hipLaunchKernelGGL(k_gram_finish, dim3(8, (unsigned)nq), dim3(256), 0, s, H, ld, p, md, list);
 }
 
 // Zero a slot's operand rows (retired or empty slots must not contribute to the products).

@@ -774,4 +774,28 @@ void launch_count_nonfinite(int xtype, const void* X, int64_t count, int* bad, h
                        (const uint16_t*)X, count, bad);
 }
 
+
+// Count of differing 32-bit words of two device buffers (words < count); the counter starts at
+// zero; each workgroup adds its count once.
+__global__ __launch_bounds__(256) void k_count_diff(const uint32_t* __restrict__ a,
+                                                    const uint32_t* __restrict__ b, int64_t count,
+                                                    int* diff) {
+  __shared__ int sd;
+  if (threadIdx.x == 0) sd = 0;
+  __syncthreads();
+  int c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256)
+    c += a[i] != b[i] ? 1 : 0;
+  if (c) atomicAdd(&sd, c);
+  __syncthreads();
+  if (threadIdx.x == 0 && sd) atomicAdd(diff, sd);
+}
+
+void launch_count_diff(const void* a, const void* b, int64_t words, int* diff, hipStream_t s) {
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (words + 255) / 256));
+  hipLaunchKernelGGL(k_count_diff, dim3(grid), dim3(256), 0, s, (const uint32_t*)a,
+                     (const uint32_t*)b, words, diff);
+}
+
 }  // namespace cgl

@@ -12,19 +12,29 @@ constexpr int kStallCycles = 6;   // re-centre when the working gap has not halv
 constexpr double kCertGap = 1.0;  // ask for an FP64 round once the working gap is <= kCertGap * tol
 constexpr double kRestartSlack = 1.0;  // noise margin of the restart test (0: plain comparison)
 
+// One problem served by an engine: the problems of an engine share the design X and differ in
+// the labels, the loss and the constants. A slot's state names its problem (NodeDev::member).
+constexpr int kMaxMembers = 4;
+struct MemberDev {
+  const double* y;    // n_pad labels (zero padded)
+  const double* H0c;  // ldp: X^T grad f(0), the base gradient of a cold start
+  const double* b0c;  // n_pad: least squares e_0 = -y; other losses u_0 = 0
+  const double* b1c;  // n_pad: other losses r_0 = grad f(0)
+  int loss;
+  double lam2, M, L, rho;
+  double shift;       // eigen-perspective shift s (App. D.2; least squares), 0 otherwise: the
+                      // gradient gains -2 s gamma, the objective -s ||beta||^2, the regulariser
+                      // weight is 2 (lambda2 + s) and the bound gains s ||point||^2
+};
+
 struct MixedDev {
   // problem
   const uint16_t* Xb;   // n_pad x ldp, BF16 copy of X (zero padded)
   const uint16_t* Xbt;  // ldp x n_pad, its transpose
   int64_t n, p, n_pad, ldp;
-  const double* y;      // n_pad (zero padded)
-  int loss;
-  double lam2, M, L, rho;
+  const MemberDev* mem; // kMaxMembers entries (device)
   double cert_gap;      // a node asks for an FP64 round when its working gap is <= cert_gap * tol
   int stall_cycles;     // ... or when that gap has not halved for this many cycles
-  double shift;         // eigen-perspective shift s (App. D.2; least squares), 0 otherwise: the
-                        // gradient gains -2 s gamma, the objective -s ||beta||^2, the regulariser
-                        // weight is 2 (lambda2 + s) and the bound gains s ||point||^2
   // slots
   int slots;            // S
   int S_pad;            // operand rows, multiple of 256
@@ -108,8 +118,10 @@ void launch_gemm_f64_rows(int xtype, const void* At, int64_t ldat, const int* id
 // dst[r][c] = src[r][c] (the design's stored precision) widened to FP64, r < rows, c < cols.
 void launch_widen(int xtype, const void* src, int64_t ld, int64_t rows, int64_t cols, double* dst,
                   int64_t ldd, hipStream_t s);
-// Least squares: H[q][j] = 2 H[q][j] + h0[j] for j < p (H = X^T X beta on entry, h0 = -2 X^T y).
-void launch_gram_finish(double* H, int64_t ld, int64_t p, int nq, const double* h0, hipStream_t s);
+// Least squares: H[q][j] = 2 H[q][j] + h0[j] for j < p (H = X^T X beta on entry, h0 = -2 X^T y of
+// the problem of slot list[q]).
+void launch_gram_finish(double* H, int64_t ld, int64_t p, int nq, const MixedDev& md, const int* list,
+                        hipStream_t s);
 // Xt (p x n_pad) = X^T in the stored precision, zero in columns n .. n_pad.
 void launch_transpose(int xtype, const void* X, int64_t ldx, int64_t n, int64_t p, int64_t n_pad,
                       void* Xt, hipStream_t s);
@@ -145,7 +157,6 @@ void launch_perm_design(const uint16_t* Xbt, int64_t n_pad, const int* perm, int
 // dst (nq x p, contiguous) = rows list[q] of src (leading dimension ld).
 void launch_gather_rows(const double* src, int64_t ld, const int* list, int nq, int64_t p,
                         double* dst, hipStream_t s);
-void launch_admit(const MixedDev& md, const int* list, int nq, const double* H0_cold,
-                  const double* base0_cold, const double* base1_cold, hipStream_t s);
+void launch_admit(const MixedDev& md, const int* list, int nq, hipStream_t s);
 
 }  // namespace cgl

@@ -130,9 +130,10 @@ void release_stream(Resident& R) {
   }
 }
 
+// Queued mixed-precision nodes for P's engine (nodes of P or of a problem sharing its design).
 bool has_queued(const cgl_server& S, const Problem* P) {
   for (const auto& r : S.queue)
-    if (r->P == P && r->node.precision == CGL_PREC_MIXED) return true;
+    if (&r->P->engine_problem() == P && r->node.precision == CGL_PREC_MIXED) return true;
   return false;
 }
 
@@ -180,9 +181,10 @@ void bring_in(cgl_server& S) {
   std::vector<Problem*> seen;
   for (const auto& q : S.queue) {
     if (q->node.precision != CGL_PREC_MIXED) continue;
-    if (std::find(seen.begin(), seen.end(), q->P) != seen.end()) continue;
-    seen.push_back(q->P);
-    make_resident(S, q->P);
+    Problem* E = &q->P->engine_problem();
+    if (std::find(seen.begin(), seen.end(), E) != seen.end()) continue;
+    seen.push_back(E);
+    make_resident(S, E);
   }
 }
 
@@ -192,7 +194,8 @@ void admit_for(cgl_server& S, Resident& R) {
   std::vector<Admission> adm;
   for (auto it = S.queue.begin(); it != S.queue.end();) {
     Request& q = **it;
-    if (q.P != R.P || q.node.precision != CGL_PREC_MIXED) {
+    const int member = W.member_of(q.P);
+    if (member < 0 || q.node.precision != CGL_PREC_MIXED) {  // another engine's node
       ++it;
       continue;
     }
@@ -201,7 +204,7 @@ void admit_for(cgl_server& S, Resident& R) {
     for (int sl = 0; sl < W.S; ++sl)
       if (W.slot_owner[(size_t)sl] < 0 && !R.slot_req[(size_t)sl]) { slot = sl; break; }
     if (slot < 0) break;
-    adm.push_back(Admission{slot, slot, q.node, q.host});
+    adm.push_back(Admission{slot, slot, q.node, q.host, member});
     R.slot_req[(size_t)slot] = std::move(*it);
     it = S.queue.erase(it);
   }

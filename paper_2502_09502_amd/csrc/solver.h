@@ -55,6 +55,7 @@ struct NodeDev {
   double rs_L;
   int rs_primed;
   int rs_restarts;
+  int member;        // mixed path: the problem of the engine's member table the node belongs to
 };
 
 constexpr int kRunning = -1;

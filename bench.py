@@ -480,7 +480,9 @@ def main():
     ap.add_argument("--prox-batch", type=int, default=256, help="prox: vectors per launch")
     ap.add_argument("--prox-max-i", type=int, default=10,
                     help="prox: sizes p = 100 * 2^i for i = 0..this (Fig. 1 runs to i = 10)")
-    ap.add_argument("--requests", type=int, default=600, help="serve: number of requests")
+    ap.add_argument("--requests", type=int, default=3000,
+                    help="serve: number of requests (3000 at 2000/s: 1.5 s of arrivals, long "
+                         "enough for the engines to reach their steady occupancy)")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: mean arrivals per second")
     ap.add_argument("--serve-sizes", default="1000,5000,20000", help="serve: dataset p values")
     ap.add_argument("--no-share", action="store_true",

@@ -50,12 +50,18 @@ void MixedWork::ensure(Problem& P) {
   // batching of the certification rounds (tuning knobs; the defaults suit the 256-slot engine)
   for (auto [name, dst] : {std::pair<const char*, int*>{"CGL_CERT_BATCH", &cert_batch},
                            std::pair<const char*, int*>{"CGL_CERT_WAIT", &cert_wait},
-                           std::pair<const char*, int*>{"CGL_CHUNK", &chunk},
                            std::pair<const char*, int*>{"CGL_REORDER_EVERY", &reorder_every}}) {
     const char* e = std::getenv(name);
     if (e && std::atoi(e) > 0) *dst = std::atoi(e);
   }
-  chunk = std::min(chunk, 16);  // its timing events (4 per cycle) stay below those of the FP64 rounds
+  {
+    const char* e = std::getenv("CGL_CHUNK");
+    if (e && std::atoi(e) > 0) serve_chunk = solve_chunk = std::atoi(e);
+  }
+  // the timing events of a chunk (4 per cycle) stay below those of the FP64 rounds
+  serve_chunk = std::min(serve_chunk, 16);
+  solve_chunk = std::min(solve_chunk, 16);
+  chunk = serve_chunk;
   // the problems the engine serves: its own and those declared to share its design
   members.assign(1, &P);
   for (Problem* Q : P.sharers) members.push_back(Q);
@@ -332,6 +338,15 @@ void MixedWork::set_relaxation(Problem& P) {
   // synchronisation)
   CGL_HIP(hipMemcpyAsync(memtab.ptr, mem_host, sizeof(mem_host), hipMemcpyHostToDevice, stream));
   CGL_HIP(hipStreamSynchronize(stream));
+}
+
+void MixedWork::set_chunk(int c) {
+  if (c == chunk) return;
+  chunk = c;
+  if (graph_exec) {
+    CGL_HIP(hipGraphExecDestroy(graph_exec));
+    graph_exec = nullptr;
+  }
 }
 
 int MixedWork::member_of(const Problem* Q) const {
@@ -880,6 +895,7 @@ void solve_mixed(Problem& Pm, const cgl_node* nodes, int32_t count, double* beta
     invalid("the eigen-perspective relaxation is for least squares");
   if (W.in_flight) invalid("the problem's batched engine is in use by a server");
   W.set_relaxation(P);
+  W.set_chunk(W.solve_chunk);
   W.stream = P.ctx->stream;  // a server may have run it on a stream of its own
   hipStream_t s = W.stream;
   // a solve that failed part-way may have left staged iterates for buffers that are gone

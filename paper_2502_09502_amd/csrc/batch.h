@@ -13,7 +13,8 @@
 namespace cgl {
 
 constexpr int kSlots = 256;  // node slots per problem
-constexpr int kChunk = 4;    // iterations per graph launch between host checks
+constexpr int kChunk = 4;       // iterations per graph launch between host checks: the server
+constexpr int kSolveChunk = 8;  // ... a batched solve (cgl_solve_batch), where throughput counts
 constexpr int kCertBatch = 16;  // certification requests that trigger a round at once
 constexpr int kCertWait = 1;    // chunks the oldest request may wait for others
 constexpr int kReorderEvery = 8;  // cycles between checks of the X-pass operand order
@@ -89,7 +90,10 @@ struct MixedWork {
   int64_t cert_rounds = 0;
   int cert_batch = kCertBatch;  // CGL_CERT_BATCH overrides
   int cert_wait = kCertWait;    // CGL_CERT_WAIT overrides
-  int chunk = kChunk;           // CGL_CHUNK overrides (cycles per launch between host checks)
+  int chunk = kChunk;           // cycles per launch between host checks (the one in use)
+  int serve_chunk = kChunk;     // the server's and a batched solve's; CGL_CHUNK overrides both
+  int solve_chunk = kSolveChunk;
+  void set_chunk(int c);        // a captured chunk of another length is dropped
   int reorder_every = kReorderEvery;  // CGL_REORDER_EVERY overrides
   hipGraphExec_t graph_exec = nullptr;  // one chunk of cycles
   MixedDev md{};

@@ -247,6 +247,7 @@ void engine_turn(cgl_server& S, Resident& R) {
   W.stream = R.stream;
   if (W.in_flight) W.finish_chunk(P);
   W.set_relaxation(P);  // the shift changes only while the engine holds no node
+  W.set_chunk(W.serve_chunk);
   if (W.cert_round(P, /*overlap=*/true) == MixedWork::kRoundOpen) {
     W.launch_chunk(P);  // queued behind the round; retirement after it
     return;

@@ -468,6 +468,11 @@ def main():
     ap.add_argument("--nodes", type=int, default=256)
     ap.add_argument("--plain-nodes", type=int, default=16,
                     help="nodes of the plain FP64 per-node comparator")
+    ap.add_argument("--stream-batches", type=int, default=4,
+                    help="batched: batches of --nodes nodes streamed through the engine's slots in "
+                         "one call after the timed steps (0: skip)")
+    ap.add_argument("--check-every", type=int, default=1,
+                    help="batched: dual-monitor period of the nodes (iterations)")
     ap.add_argument("--mode", choices=["auto", "batched", "plain"], default="auto")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-nodes-per-core", type=int, default=2,
@@ -526,7 +531,8 @@ def main():
     print(f"# setup {time.perf_counter() - t_setup:.1f}s  L={L:.6g}", file=sys.stderr, flush=True)
 
     def specs(prec):
-        return [prob.node(Z0=z0, Z1=z1, tol=1e-6, precision=prec) for z0, z1 in sets]
+        return [prob.node(Z0=z0, Z1=z1, tol=1e-6, precision=prec, check_every=args.check_every)
+                for z0, z1 in sets]
 
     mode = args.mode
     engine_setup_ms = None
@@ -553,7 +559,7 @@ def main():
     # timed steps: the production path (graph-captured chunks), with only the host wall time of
     # the engine's phases recorded (batched engine)
     ctx.set_profiling(True, phases_only=True)
-    for w in range(12):
+    for w in range(16):
         ctx.kernel_stats(w, reset=True)
     t0 = time.perf_counter()
     results = []
@@ -571,6 +577,7 @@ def main():
                         (11, "certification_rounds_gpu")):
             ms, cnt = ctx.kernel_stats(w, reset=True)
             phases[name] = {"ms_per_step": round(ms / args.steps, 3), "count_per_step": cnt / args.steps}
+        phases["reorders_per_step"] = ctx.kernel_stats(12, reset=True)[1] / args.steps
     # one more step, untimed, with kernel events on the roofline's kernel (its launches then run
     # outside graphs): the kernel's live average launch time and the per-cycle kernel figures
     for w in range(12):
@@ -600,6 +607,45 @@ def main():
     iters = [r.iters for r in results]
     print(f"# {mode}: {value:.2f} solves/s, all certified: {ok}, iterations median "
           f"{statistics.median(iters)} max {max(iters)}", file=sys.stderr, flush=True)
+
+    # continuous batching, as a branch-and-bound driver feeds the engine: several batches of
+    # nodes of the same kind in one call, each node admitted into a slot as soon as one frees, so
+    # the tail of one batch overlaps the next (a warm-up call first, then the measured one)
+    stream = None
+    if mode == "batched" and args.stream_batches > 0:
+        csets = synth.node_sets(d.p, d.k, args.stream_batches * len(step_specs), 20, seed=3,
+                                config_id=4)
+        cspecs = [prob.node(Z0=z0, Z1=z1, tol=1e-6, precision="mixed") for z0, z1 in csets]
+        cout = np.empty((len(cspecs), d.p))
+        cout.fill(0.0)
+        prob.solve_batch(cspecs[: len(step_specs)], out=cout[: len(step_specs)])
+        ctx.set_profiling(True, phases_only=True)
+        for w in range(16):
+            ctx.kernel_stats(w, reset=True)
+        tc0 = time.perf_counter()
+        cres = prob.solve_batch(cspecs, out=cout)
+        tc = time.perf_counter() - tc0
+        ctx.set_profiling(False)
+        cphases = {}
+        for w, name in ((5, "iteration_chunks"), (6, "certification_rounds"),
+                        (7, "admission_retirement"), (10, "chunks_gpu"),
+                        (11, "certification_rounds_gpu")):
+            ms, cnt = ctx.kernel_stats(w, reset=True)
+            cphases[name] = {"ms": round(ms, 3), "count": cnt}
+        frac, passes = ctx.kernel_stats(9, reset=True)
+        if passes:
+            cphases["x_pass_kernel"] = {"count": passes, "mean_columns_read": round(frac / passes, 4)}
+        cphases["reorders"] = ctx.kernel_stats(12, reset=True)[1]
+        cphases["admissions"] = ctx.kernel_stats(13, reset=True)[1]
+        cit = [r.iters for r in cres]
+        stream = {"solves_per_s": round(len(cspecs) / tc, 1), "nodes": len(cspecs),
+                  "batches": args.stream_batches, "ms": round(1e3 * tc, 2),
+                  "all_certified": all(r.status == "converged" and r.gap_rel <= 1e-6 for r in cres),
+                  "iterations": {"median": statistics.median(cit), "max": max(cit)},
+                  "phases": cphases,
+                  "note": "one call; nodes fill slots as they free (not the headline value)"}
+        print(f"# stream of {len(cspecs)} nodes: {stream['solves_per_s']} solves/s", file=sys.stderr,
+              flush=True)
 
     # plain FP64 per-node comparator on the first nodes (each solve is its own latency)
     plain = None
@@ -653,6 +699,8 @@ def main():
     if mode == "plain":
         out["latency_ms"] = {"note": "per-node solve time on the plain path, sequential",
                              "p50": round(1e3 * elapsed / args.steps / len(step_specs), 3)}
+    if stream is not None:
+        out["continuous_batching"] = stream
     if plain is not None:
         out["plain_fp64_per_node"] = plain
         out["speedup_vs_plain"] = round(value / plain["solves_per_s"], 2)

@@ -145,7 +145,10 @@ int cgl_ctx_destroy(cgl_ctx* ctx);
  *        9 = the batched X pass's operand extent: total_ms holds the sum over passes of the
  *            fraction of the padded columns read (not a time), launches the passes;
  *        10, 11 (on = 3 only) = GPU time of the batched engine's graph-captured chunks and of
- *            its certification rounds (HIP events around each on the stream).
+ *            its certification rounds (HIP events around each on the stream);
+ *        12 = rewrites of the batched engine's support-first column order (launches = count,
+ *            total_ms = 0); 13 = nodes admitted into the batched engine's slots (launches =
+ *            count, total_ms = 0).
  * cgl_ctx_kernel_stats returns the totals since the last reset (reset = 1 clears them). */
 int cgl_ctx_set_profiling(cgl_ctx* ctx, int32_t on);
 int cgl_ctx_kernel_stats(cgl_ctx* ctx, int32_t which, int32_t reset, double* total_ms,

@@ -493,6 +493,7 @@ void MixedWork::reorder_apply(Problem& P) {
   *order_host = (int)after;
   CGL_HIP(hipMemcpyAsync(pfx.ptr, order_host, sizeof(int), hipMemcpyHostToDevice, s));
   reorders += 1;
+  if (P.ctx->profiling || P.ctx->phase_timing) P.ctx->kt_n[12] += 1;
 }
 
 void MixedWork::launch_chunk(Problem& P) {
@@ -545,10 +546,12 @@ void MixedWork::finish_chunk(Problem& P) {
     reorder_checked = cycles + chunk;
     reorder_apply(P);
   }
-  if (ctx->profiling) {
+  if (ctx->profiling || ctx->phase_timing) {
     // mean X-pass operand extent: total = sum of the extents as fractions of ldp, count = passes
     ctx->kt_ms[9] += (double)es[0] * (2 * GT_K) / (double)ldp;
     ctx->kt_n[9] += es[1];
+  }
+  if (ctx->profiling) {
     for (int i = 0; i < chunk; ++i) {
       float a = 0.f, b = 0.f;
       if (ctx->profile_x) {
@@ -764,6 +767,7 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
     }
   }
   launch_admit(md, list.as<int>(), (int)slots.size(), s);
+  if (P.ctx->profiling || P.ctx->phase_timing) P.ctx->kt_n[13] += (int64_t)slots.size();
   // warm starts (fixed-zero coordinates set to 0) into the iterate ring, the base and the best
   std::vector<std::vector<double>> starts;
   for (const Admission& a : adm) {

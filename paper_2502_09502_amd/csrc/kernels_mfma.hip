@@ -290,6 +290,19 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
   const double invL = 1.0 / mb.L;
   const int iter = st->iter;
   const bool check = (iter % st->check_every) == 0;
+  // read ahead (their latency is spent on the loads of H): the winners of this slot's last two
+  // selections (where the registers allow), and the F* partials of the residual kernel (summed
+  // per wave below)
+  constexpr bool kAhead = E <= 12;
+  int* const rtop = md.prevtop + (int64_t)slot * 65;
+  int* const rhead = md.prevhead + (int64_t)slot * 65;
+  WarmPrev wtop{rtop, -1, 0}, whead{rhead, -1, 0};
+  if (kAhead) {
+    wtop = warm_prev(rtop);
+    whead = warm_prev(rhead);
+  }
+  double fpre = 0.0;
+  for (int i = threadIdx.x; i < md.nrt; i += blockDim.x) fpre += md.fpart[(int64_t)slot * md.nrt + i];
   // H at gamma (FP64 base + BF16-product corrections) into the per-thread value slice
   __shared__ double vbuf[ProxVals<E>::nl * kProxThreads];
   ProxVals<E> pv;
@@ -335,6 +348,8 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
       if (j < p) pv.set(s, pv.get(s) + (double)dq[j]);
     }
   }
+  fpre = wave_sum(fpre);
+  if ((threadIdx.x & 63) == 0) sm.fsw[threadIdx.x >> 6] = fpre;  // read after later barriers
   // eigen-perspective shift: the gradient at gamma is X^T grad f(X gamma) - 2 s gamma, and the
   // bound gains s ||gamma||^2 (uniform branch: the shift is a launch argument)
   const double shift = mb.shift;
@@ -359,7 +374,7 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
   double gs = 0.0;
   if (check)
     gs = gstar_node<E>([&](int s) { return fabs(pv.get(s)); }, two_le, cb, st->kp,
-                       st->nfree, mM, sm, slice, md.prevtop + (int64_t)slot * 65);
+                       st->nfree, mM, sm, slice, kAhead ? wtop : warm_prev(rtop));
   // gradient step w = gamma - H / L; the slice then holds u = rho |w|, the signs a mask
   uint32_t neg = 0;
 #pragma unroll
@@ -379,21 +394,44 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
   __shared__ int ext_s;
   if (threadIdx.x == 0) ext_s = 0;
   __syncthreads();
+  // the prox hands each beta_j back into the value slice (its u is not read again)
   double bsq = 0.0;
   const ProxOut po = node_prox<E>(
       [&](int s) { return pv.get(s); }, neg, cb, st->kp, st->nfree, mrho, mM, st->vstar,
       [&](int s, double b) {
-        const int64_t j = (int64_t)s * kProxThreads + threadIdx.x;
         bsq += b * b;
-        if (j < p) {
-          bout[j] = b;
-          const int pos = md.pinv[j];
-          const uint16_t d = float_to_bf16((float)(b - b0[j]));
-          md.dop[frag_index(slot, pos, nbk)] = d;
-          if ((d & 0x7fffu) != 0) atomicMax(&ext_s, pos + 1);
-        }
+        pv.set(s, b);
       },
-      sm, slice, md.prevhead + (int64_t)slot * 65);
+      sm, slice, kAhead ? whead : warm_prev(rhead));
+  // the new iterate and its operand entries, in groups whose loads of beta_0 and of the column
+  // positions are all issued before the group's stores (groups of 4 where registers are short)
+  constexpr int G = E <= 12 ? E : 4;
+#pragma unroll
+  for (int s0 = 0; s0 < E; s0 += G) {
+    double b0v[G];
+    int posv[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int64_t j = (int64_t)(s0 + g) * kProxThreads + threadIdx.x;
+      b0v[g] = 0.0;
+      posv[g] = 0;
+      if (s0 + g < E && j < p) {
+        b0v[g] = b0[j];
+        posv[g] = md.pinv[j];
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int64_t j = (int64_t)(s0 + g) * kProxThreads + threadIdx.x;
+      if (s0 + g < E && j < p) {
+        const double b = pv.get(s0 + g);
+        bout[j] = b;
+        const uint16_t d = float_to_bf16((float)(b - b0v[g]));
+        md.dop[frag_index(slot, posv[g], nbk)] = d;
+        if ((d & 0x7fffu) != 0) atomicMax(&ext_s, posv[g] + 1);
+      }
+    }
+  }
   __syncthreads();
   // Entries past the support prefix leave the operand as strays, in position order, when there
   // are at most kStrayCap of them; otherwise they all stay and the extent covers them (their
@@ -453,9 +491,8 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
   if (threadIdx.x == 0) md.sn[slot] = ns;
   double fs = 0.0;
   if (check) {
-    for (int i = threadIdx.x; i < md.nrt; i += blockDim.x)
-      fs += md.fpart[(int64_t)slot * md.nrt + i];
-    fs = bsum(fs, sm);
+#pragma unroll
+    for (int w = 0; w < kProxWaves; ++w) fs += sm.fsw[w];
   }
   if (shift != 0.0) bsq = bsum(bsq, sm);
   if (threadIdx.x == 0) {

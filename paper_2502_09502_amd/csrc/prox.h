@@ -53,6 +53,7 @@ struct ProxSmem {
   int hidx[kMaxHead + 1];
   double tmp[kMaxHead];
   double redd[kProxWaves * 4];
+  double fsw[kProxWaves];  // per-wave partial sums a caller keeps across the prox
   uint64_t redu[kProxWaves];
   int redi[kProxWaves];
   int head_fill;
@@ -195,22 +196,40 @@ __device__ __forceinline__ void block_topk(KeyF key, uint32_t act, int K, ProxSm
   __syncthreads();
 }
 
+// A node's record of the winners of its last selection (rec[0] = K, rec[1..K] = element
+// indices; 65 ints), read ahead of the selection so that the load's latency is spent elsewhere:
+// k0 = rec[0] and, for the first 64 threads, idx = rec[1 + threadIdx.x].
+struct WarmPrev {
+  int* rec;
+  int k0;
+  int idx;
+};
+__device__ __forceinline__ WarmPrev warm_prev(int* rec) {
+  WarmPrev w{rec, -1, 0};
+  if (rec != nullptr) {
+    w.k0 = rec[0];
+    if (threadIdx.x < 64) w.idx = rec[1 + threadIdx.x];
+  }
+  return w;
+}
+
 // Warm-started selection of the K largest (the same order as block_topk: value desc, index asc)
-// from the K winners of the previous call on this node (prev[0] = K, prev[1..K] = indices). Their
-// current values give a threshold tau = min over them, and at least K elements have a value
-// >= tau, so the K largest all lie in {value >= tau}; those candidates (at most kWarmCap) are
-// ranked exactly. uv[j]: the value of element j (ABS: its magnitude) for every j < E *
-// kProxThreads (an LDS array indexed by element). Returns false, having written nothing in
-// sm.hu / sm.hidx, when there is no usable history or too many candidates; the caller then runs
-// block_topk. On success the winners are stored back into prev for the next call.
+// from the K winners of the previous call on this node (wp). Their current values give a
+// threshold tau = min over them, and at least K elements have a value >= tau, so the K largest
+// all lie in {value >= tau}; those candidates (at most kWarmCap) are ranked exactly. uv[j]: the
+// value of element j (ABS: its magnitude) for every j < E * kProxThreads (an LDS array indexed
+// by element). Returns false, having written nothing in sm.hu / sm.hidx, when there is no usable
+// history or too many candidates; the caller then runs block_topk. On success the winners are
+// stored back into the record for the next call.
 constexpr int kWarmCap = 256;
 template <int E, bool ABS>
-__device__ __noinline__ bool block_topk_warm(const double* uv, uint32_t act, int K, int* prev, ProxSmem& sm) {
-  if (prev == nullptr || prev[0] != K) return false;  // uniform: every thread reads the same word
+__device__ __noinline__ bool block_topk_warm(const double* uv, uint32_t act, int K, WarmPrev wp,
+                                             ProxSmem& sm) {
+  if (wp.rec == nullptr || wp.k0 != K) return false;  // uniform
   const int tid = threadIdx.x;
   auto val = [&](int j) { return ABS ? fabs(uv[j]) : uv[j]; };
   if (tid < 64) {
-    double t = tid < K ? val(prev[1 + tid]) : HUGE_VAL;
+    double t = tid < K ? val(wp.idx) : HUGE_VAL;
     t = wave_reduce(t, HUGE_VAL, OpMin());
     if (tid == 0) {
       sm.b_dbl[0] = t;
@@ -249,7 +268,7 @@ __device__ __noinline__ bool block_topk_warm(const double* uv, uint32_t act, int
     }
   }
   __syncthreads();
-  if (tid < K) prev[1 + tid] = sm.hidx[tid];
+  if (tid < K) wp.rec[1 + tid] = sm.hidx[tid];
   return true;
 }
 
@@ -467,7 +486,7 @@ __device__ __forceinline__ uint32_t cls_mask(uint64_t cb, int c) {
 template <int E, typename UF, typename OutF>
 __device__ __forceinline__ ProxOut node_prox(UF U, uint32_t neg, uint64_t cb, int kp, int nfree, double rho,
                              double M, double vhint, OutF out, ProxSmem& sm,
-                             const double* uv = nullptr, int* prev = nullptr) {
+                             const double* uv = nullptr, WarmPrev prev = WarmPrev{nullptr, -1, 0}) {
   const uint32_t fm = cls_mask<E>(cb, CLS_FREE);
   auto sgn = [&](int s, double mag) { return ((neg >> s) & 1u) ? -mag : mag; };
   // Z1 coordinates: ridge-and-clip rho w / (1 + rho) clipped to [-M, M]
@@ -497,7 +516,7 @@ __device__ __forceinline__ ProxOut node_prox(UF U, uint32_t neg, uint64_t cb, in
     // uv: the u values indexed by element (for the warm start); prev: the last call's winners
     if (uv == nullptr || !block_topk_warm<E, false>(uv, fm, kp + 1, prev, sm)) {
       block_topk<E>(U, fm, kp + 1, sm);
-      topk_remember(prev, kp + 1, sm);
+      topk_remember(prev.rec, kp + 1, sm);
     }
     const double tv = sm.hu[kp - 1];
     const int ti = sm.hidx[kp - 1];
@@ -583,7 +602,8 @@ __device__ __forceinline__ ProxOut node_prox(UF U, uint32_t neg, uint64_t cb, in
 // on A directly and only the selected values are divided.
 template <int E, typename AF>
 __device__ __forceinline__ double gstar_node(AF A, double div, uint64_t cb, int kp, int nfree, double M,
-                             ProxSmem& sm, const double* av = nullptr, int* prev = nullptr) {
+                             ProxSmem& sm, const double* av = nullptr,
+                             WarmPrev prev = WarmPrev{nullptr, -1, 0}) {
   const uint32_t fm = cls_mask<E>(cb, CLS_FREE);
   double z1 = 0.0;
 #pragma unroll
@@ -599,7 +619,7 @@ __device__ __forceinline__ double gstar_node(AF A, double div, uint64_t cb, int 
       // av: signed values indexed by element (A = |av|) for the warm start
       if (av == nullptr || !block_topk_warm<E, true>(av, fm, kp, prev, sm)) {
         block_topk<E>(A, fm, kp, sm);
-        topk_remember(prev, kp, sm);
+        topk_remember(prev.rec, kp, sm);
       }
       if (threadIdx.x == 0)
         for (int r = 0; r < kp; ++r) top += huber(sm.hu[r] / div, M);

@@ -50,7 +50,8 @@ void MixedWork::ensure(Problem& P) {
   // batching of the certification rounds (tuning knobs; the defaults suit the 256-slot engine)
   for (auto [name, dst] : {std::pair<const char*, int*>{"CGL_CERT_BATCH", &cert_batch},
                            std::pair<const char*, int*>{"CGL_CERT_WAIT", &cert_wait},
-                           std::pair<const char*, int*>{"CGL_REORDER_EVERY", &reorder_every}}) {
+                           std::pair<const char*, int*>{"CGL_REORDER_EVERY", &reorder_every},
+                           std::pair<const char*, int*>{"CGL_REORDER_SHRINK", &reorder_shrink}}) {
     const char* e = std::getenv(name);
     if (e && std::atoi(e) > 0) *dst = std::atoi(e);
   }
@@ -477,7 +478,7 @@ void MixedWork::reorder_apply(Problem& P) {
   for (int i = 0; i < S; ++i) strays += h[kCtlStrays + i];
   // a stray costs its slot a column of X~ every cycle (one row of X~^T read by the loss kernel);
   // a reorder rewrites X~ once (about 0.25 ms)
-  const bool shorter = after <= now - std::max<int64_t>(2 * grain, now / 8);
+  const bool shorter = after <= now - std::max<int64_t>(2 * grain, now / reorder_shrink);
   if (!shorter && strays <= S) return;  // the current order still serves
   CGL_HIP(hipMemcpyAsync(dop_tmp.ptr, dop.ptr, dop.bytes, hipMemcpyDeviceToDevice, s));
   CGL_HIP(hipMemsetAsync(md.keff, 0, 2 * sizeof(int), s));  // the extent counters only

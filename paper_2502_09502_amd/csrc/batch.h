@@ -18,6 +18,8 @@ constexpr int kSolveChunk = 8;  // ... a batched solve (cgl_solve_batch), where 
 constexpr int kCertBatch = 16;  // certification requests that trigger a round at once
 constexpr int kCertWait = 1;    // chunks the oldest request may wait for others
 constexpr int kReorderEvery = 8;  // cycles between checks of the X-pass operand order
+// a reorder is made when the union is at least 1 / kReorderShrink of the extent shorter
+constexpr int kReorderShrink = 8;
 constexpr int64_t kGramMaxP = 16384;  // least squares: largest p with an FP64 Gram matrix (2.1 GB)
 
 struct Admission {
@@ -95,6 +97,7 @@ struct MixedWork {
   int solve_chunk = kSolveChunk;
   void set_chunk(int c);        // a captured chunk of another length is dropped
   int reorder_every = kReorderEvery;  // CGL_REORDER_EVERY overrides
+  int reorder_shrink = kReorderShrink;  // CGL_REORDER_SHRINK overrides
   hipGraphExec_t graph_exec = nullptr;  // one chunk of cycles
   MixedDev md{};
 

@@ -56,9 +56,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_bf16_c4_traffic.md")
 TRAFFIC_SOURCES = ("paper_2502_09502_amd/csrc/gemm_bf16.h",)  # the product kernels and their main loop
 
 
-def measured_traffic(key: str):
+def tiling_desc(code):
+    """A product's tiling from the engine's code (split-K, plus 100 for the 128-row tile)."""
+    code = int(code)
+    if code <= 0:
+        return None
+    return f"{128 if code >= 100 else 256} rows x 256 nodes per workgroup, split-K {code % 100}"
+
+
+def measured_traffic(key: str, tiling=None):
     """HBM bytes per launch from the committed counter summary, or None when the kernel sources
-    changed since the counters were taken (or there is no summary)."""
+    changed since the counters were taken, when the counters were taken on another tiling of the
+    product than the one in use (tiling: its code), or when there is no summary."""
     import hashlib
     try:
         h = hashlib.sha256()
@@ -72,6 +81,9 @@ def measured_traffic(key: str):
                     k, v = line.split(":", 1)
                     vals[k.strip()] = v.strip()
         if vals.get("source_sha256_16") != h.hexdigest()[:16]:
+            return None
+        tkey = key.replace("traffic_bytes_", "tiling_")
+        if tiling is not None and tkey in vals and int(vals[tkey]) != int(tiling):
             return None
         return float(vals[key])
     except (OSError, KeyError, ValueError):
@@ -91,8 +103,11 @@ def roofline(ctx, n, p, sx, nodes, which):
            "kernel": KERNEL_NAMES[which], "avg_launch_us": round(avg_s * 1e6, 2),
            "launches": cnt, "bytes_per_launch": nbytes}
     if which in (2, 3):
+        code_x, code_xt = ctx.kernel_stats(14)  # the tilings the engine's autotuner chose
+        code = int(code_xt if which == 2 else code_x)
+        out["tiling"] = tiling_desc(code)
         out["traffic"] = measured_traffic("traffic_bytes_xt_pass" if which == 2 else
-                                          "traffic_bytes_x_pass")
+                                          "traffic_bytes_x_pass", tiling=code)
         tflops = 2.0 * n * p * nodes / avg_s / 1e12
         out["mfma_context"] = {"achieved_tflops": round(tflops, 1),
                                "peak_tflops": MFMA_BF16_PEAK_TFLOPS,

@@ -555,6 +555,11 @@ int cgl_ctx_kernel_stats(cgl_ctx* ctx, int32_t which, int32_t reset, double* tot
   CGL_API_BEGIN
   if (!ctx) invalid("ctx is NULL");
   if (which < 0 || which >= 16) invalid("which out of range");
+  if (which == 14) {  // the tilings in use (not counters: reset does not apply)
+    if (total_ms) *total_ms = (double)ctx->tiling[0];
+    if (launches) *launches = ctx->tiling[1];
+    return CGL_OK;
+  }
   if (total_ms) *total_ms = ctx->kt_ms[which];
   if (launches) *launches = ctx->kt_n[which];
   if (reset) {

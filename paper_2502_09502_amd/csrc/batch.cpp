@@ -104,12 +104,17 @@ void MixedWork::ensure(Problem& P) {
   // four rounds of 256 workgroups (one workgroup of the product fits on a compute unit); the
   // partial buffers are sized for the largest candidate and the choice is made by timing
   // (tune_splits) once the buffers exist
-  split_cands_x = split_candidates(n_pad / GT_M, ldp);
-  split_cands_xt = split_candidates(ldp / GT_M, n_pad);
+  split_cands_x = tiling_candidates(n_pad, ldp);
+  split_cands_xt = tiling_candidates(ldp, n_pad);
   set_split_x(split_cands_x.front());
   set_split_xt(split_cands_xt.front());
-  dUp.alloc((size_t)split_cands_x.back() * S_pad * n_pad * 4);
-  dH.alloc((size_t)split_cands_xt.back() * S_pad * ldp * 4);
+  {
+    int kx = 1, kt = 1;
+    for (int c : split_cands_x) kx = std::max(kx, code_ks(c));
+    for (int c : split_cands_xt) kt = std::max(kt, code_ks(c));
+    dUp.alloc((size_t)kx * S_pad * n_pad * 4);
+    dH.alloc((size_t)kt * S_pad * ldp * 4);
+  }
   rchunk = kLossChunk;
   nrt = (int)((n_pad + rchunk - 1) / rchunk);
   lpart.alloc((size_t)S * nrt * 8);
@@ -373,53 +378,78 @@ std::vector<int> MixedWork::split_candidates(int64_t m_tiles, int64_t K) {
   return c;
 }
 
-void MixedWork::set_split_x(int ks) {
+// Every split candidate of the 256-row tiling, then those of the 128-row tiling (M rows, a
+// multiple of 256, and a k-length of K).
+std::vector<int> MixedWork::tiling_candidates(int64_t M, int64_t K) {
+  std::vector<int> c = split_candidates(M / GT_M, K);
+  for (int ks : split_candidates(M / (GT_M / 2), K)) c.push_back(ks + kTile128);
+  return c;
+}
+
+void MixedWork::set_split_x(int code) {
+  const int ks = std::max(1, code_ks(code));
   x_kchunk = round_up((ldp + ks - 1) / ks, 128);
   ksx = (int)((ldp + x_kchunk - 1) / x_kchunk);
   md.ksx = ksx;
   md.x_kchunk = x_kchunk;
+  md.x_rt = code_rt(code);
 }
 
-void MixedWork::set_split_xt(int ks) {
+void MixedWork::set_split_xt(int code) {
+  const int ks = std::max(1, code_ks(code));
   xt_kchunk = round_up((n_pad + ks - 1) / ks, 128);
   ksplit = (int)((n_pad + xt_kchunk - 1) / xt_kchunk);
   md.ksplit = ksplit;
   md.xt_kchunk = xt_kchunk;
+  md.xt_rt = code_rt(code);
 }
 
-// Autotuner of the split-K of both products: every candidate is launched on the engine's own
-// buffers (the operands are still zero, the partials are scratch) and timed with HIP events.
+// Autotuner of the tiling of both products (row tile and split-K): every candidate is launched
+// on the engine's own buffers (the operands are still zero, the partials are scratch) and timed
+// with HIP events.
 // Its cost is that time plus the reading of its partial sums by the next kernel (one FP32 slab
 // of nodes x rows per chunk, charged at 4 TB/s, about what the consumers achieve); the cheapest
-// wins, a larger split only when it is 2% cheaper. Results are kept on the context per (pass,
-// rows, k-length, nodes) and in the tuning cache file of the device's architecture, which later
-// contexts load (CGL_TUNE_CACHE); CGL_AUTOTUNE=0 keeps the first candidate that fills the chip in
-// one round.
+// wins, a later candidate (a larger split, or the 128-row tile) only when it is 2% cheaper.
+// Results (the tiling's code) are kept on the context per (pass, rows, k-length, nodes) and in
+// the tuning cache file of the device's architecture, which later contexts load
+// (CGL_TUNE_CACHE); CGL_AUTOTUNE=0 keeps the 256-row tiling's largest split that fills the chip
+// in one round.
 void MixedWork::tune_splits(Problem& P) {
   cgl_ctx* ctx = P.ctx;
   hipStream_t s = stream;
   const char* env = std::getenv("CGL_AUTOTUNE");
   const bool tune = !(env && env[0] == '0');
+  // test hook: CGL_FORCE_TILE = 256 or 128 keeps only that row tiling (not saved to the cache)
+  const char* ft = std::getenv("CGL_FORCE_TILE");
+  const int force = ft ? std::atoi(ft) : 0;
   for (int pass = 0; pass < 2; ++pass) {
-    const std::vector<int>& cand = pass == 0 ? split_cands_x : split_cands_xt;
+    std::vector<int> cand = pass == 0 ? split_cands_x : split_cands_xt;
+    if (force == 256 || force == 128) {
+      std::vector<int> keep;
+      for (int c : cand)
+        if ((c >= kTile128) == (force == 128)) keep.push_back(c);
+      if (!keep.empty()) cand = keep;
+    }
     const int64_t m_tiles = pass == 0 ? n_pad / GT_M : ldp / GT_M;
     const std::array<int64_t, 4> key = {pass, pass == 0 ? n_pad : ldp, pass == 0 ? ldp : n_pad,
                                         (int64_t)S_pad};
     auto set = [&](int ks) { pass == 0 ? set_split_x(ks) : set_split_xt(ks); };
     auto launch = [&]() { pass == 0 ? launch_gemm_x(md, s) : launch_gemm_xt(md, s); };
     auto hit = ctx->tuned_split.find(key);
-    if (hit != ctx->tuned_split.end()) {
+    if (hit != ctx->tuned_split.end() && force == 0) {
       set(hit->second);
+      ctx->tiling[pass] = hit->second;
       continue;
     }
-    int choice = cand.back();
-    for (int ks : cand)  // without timing: the largest split that runs in one round
-      if (m_tiles * ks <= 256) choice = ks;
+    int choice = cand.front();
+    for (int c : cand)  // without timing: the 256-row tiling's largest split that runs in one round
+      if (c < kTile128 && m_tiles * c <= 256) choice = c;
     if (tune && cand.size() > 1) {
       const double slab_ms = (double)S_pad * (pass == 0 ? n_pad : ldp) * 4.0 / 4e12 * 1e3;
       double best = HUGE_VAL;
-      for (int ks : cand) {
-        set(ks);
+      for (int code : cand) {
+        const int ks = code_ks(code);
+        set(code);
         launch();  // warm-up
         CGL_HIP(hipEventRecord(ctx->event(0), s));
         for (int r = 0; r < 3; ++r) launch();
@@ -430,11 +460,13 @@ void MixedWork::tune_splits(Problem& P) {
         const double cost = ms / 3.0 + ks * slab_ms;
         if (cost < best * 0.98) {
           best = cost;
-          choice = ks;
+          choice = code;
         }
       }
     }
     set(choice);
+    ctx->tiling[pass] = choice;
+    if (force != 0) continue;
     ctx->tuned_split[key] = choice;
     if (tune && cand.size() > 1) ctx->save_tuning(key, choice);
   }

@@ -101,10 +101,16 @@ struct MixedWork {
   hipGraphExec_t graph_exec = nullptr;  // one chunk of cycles
   MixedDev md{};
 
+  // Tilings of the two products, as codes: the split-K, plus kTile128 for the 128-row tile
+  // (else 256 rows). The autotuner picks one code per product shape.
+  static constexpr int kTile128 = 100;
+  static int code_rt(int code) { return code >= kTile128 ? 4 : 8; }
+  static int code_ks(int code) { return code % kTile128; }
   std::vector<int> split_cands_x, split_cands_xt;
   static std::vector<int> split_candidates(int64_t m_tiles, int64_t K);
-  void set_split_x(int ks);
-  void set_split_xt(int ks);
+  static std::vector<int> tiling_candidates(int64_t M, int64_t K);
+  void set_split_x(int code);
+  void set_split_xt(int code);
   void tune_splits(Problem& P);
   void ensure(Problem& P);
   // Take the problem's step size and eigen-perspective shift (they change with

@@ -28,6 +28,7 @@ struct cgl_ctx {
   // split-K choices of the batched products found by timing, by (pass, M, K, nodes); loaded
   // from and appended to the tuning cache file (tune_cache_path) for this device's architecture
   std::map<std::array<int64_t, 4>, int> tuned_split;
+  int tiling[2] = {0, 0};  // tiling codes of the last batched engine set up (X pass, X^T pass)
   std::string arch;  // gcnArchName up to the first ':' (e.g. "gfx950")
   void load_tuning();
   void save_tuning(const std::array<int64_t, 4>& key, int choice) const;

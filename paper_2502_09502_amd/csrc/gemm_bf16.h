@@ -3,15 +3,19 @@
 //   A: M x K bf16 row-major (the design X~ or its transpose; streamed from HBM once),
 //   B: the per-node operands (small, L2 resident), stored in MFMA fragment order (below),
 //   C: FP32, node-major (ldc); split-K partials at c_split_stride.
-// M is a multiple of GT_M, K a multiple of 2 GT_K per chunk, nodes a multiple of GT_N.
+// M is a multiple of the row tile (32 RT), K a multiple of 2 GT_K per chunk, nodes a multiple of
+// GT_N.
 //
-// Workgroup: 256 rows of A x 256 nodes, 4 waves, one wave per SIMD; wave w owns nodes
-// [64 w, 64 w + 64) as 8 x 2 v_mfma_f32_32x32x16_bf16 tiles (rows x nodes), 256 accumulators
-// per lane. A row tile this tall halves the L2 traffic of B (every row tile reads all of B once)
-// against a 128-row tile. The A tile (256 x 64) is shared through a two-slot LDS ring (rows of
-// 144 bytes: 9 units of 16 bytes, so that 16 lanes reading 16 consecutive rows hit 16 distinct
-// bank groups); each wave's B fragments go straight from global memory into registers (each B
-// element is used by exactly one wave of the workgroup).
+// Workgroup: 32 RT rows of A x 256 nodes, 4 waves; wave w owns nodes [64 w, 64 w + 64) as
+// RT x 2 v_mfma_f32_32x32x16_bf16 tiles (rows x nodes), 32 RT accumulators per lane. Two row
+// tilings, chosen per product shape by the engine's autotuner: RT = 8 (256 rows, one wave per
+// SIMD; a row tile this tall halves the L2 traffic of B, since every row tile reads all of B
+// once) and RT = 4 (128 rows: twice the workgroups, for designs with few rows; two workgroups
+// per CU would leave too few registers for the prefetch buffers). The A tile (32 RT x 64) is
+// shared through a two-slot LDS ring (rows of 144 bytes: 9 units of 16 bytes, so that 16 lanes
+// reading 16 consecutive rows hit 16 distinct bank groups); each wave's B fragments go straight
+// from global memory into registers (each B element is used by exactly one wave of the
+// workgroup).
 //
 // Fragment order of B: the 32 x 16 (nodes x k) fragment that one MFMA consumes is stored as
 // 64 lanes x 8 bf16, lane = node % 32 + 32 ((k / 8) % 2), so a wave loads it with one fully
@@ -31,10 +35,10 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int GT_M = 256;
+constexpr int GT_M = 256;  // the taller row tile (padding unit of the engine's row counts)
 constexpr int GT_N = 256;
 constexpr int GT_K = 64;
-constexpr int GT_RT = GT_M / 32;  // row tiles per wave
+constexpr int GT_RT = GT_M / 32;  // row tiles of 32 per wave in the taller tiling
 constexpr int GT_KB = GT_K / 16;  // k-blocks of 16 per k-step
 constexpr int GT_LD = GT_K + 8;   // LDS row pitch in bf16 (144 bytes)
 
@@ -63,23 +67,23 @@ __device__ __forceinline__ u32x4 load_a16(const uint16_t* p) {
   return *reinterpret_cast<const u32x4*>(p);
 }
 
-// Main loop; leaves this wave's GT_RT x 2 accumulator tiles (row block r, node block c) in acc.
-template <bool NT = false>
+// Main loop; leaves this wave's RT x 2 accumulator tiles (row block r, node block c) in acc.
+template <int RT, bool NT = false>
 __device__ __forceinline__ void gemm_bf16_mainloop(const GemmArgs& g, int64_t m0, int64_t n0,
                                                    int64_t k0, int64_t k1, uint16_t* As,
-                                                   floatx16 (&acc)[GT_RT][2]) {
+                                                   floatx16 (&acc)[RT][2]) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wid = tid >> 6;
 #pragma unroll
-  for (int r = 0; r < GT_RT; ++r)
+  for (int r = 0; r < RT; ++r)
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[r][c][e] = 0.f;
   const int nsteps = (int)((k1 - k0) / GT_K);
   if (nsteps <= 0) return;
-  // A loader: thread t moves rows t / 8 + 32 j (j < 8), 16 bytes at k offset (t % 8) * 8
+  // A loader: thread t moves rows t / 8 + 32 j (j < RT), 16 bytes at k offset (t % 8) * 8
   const int arow = tid >> 3;
   const int ak = (tid & 7) * 8;
   const uint16_t* ag = g.A + (m0 + arow) * g.lda + k0 + ak;
@@ -94,12 +98,12 @@ __device__ __forceinline__ void gemm_bf16_mainloop(const GemmArgs& g, int64_t m0
   // nsteps is even (the caller pads K chunks to 2 GT_K), so the body unrolled over the two LDS
   // slots has no conditionals; prefetches past the end re-read the last step (a valid address;
   // the values are not used).
-  u32x4 ra[2][8];
+  u32x4 ra[2][RT];
   bf16x8 rb[2][GT_KB][2];
 #pragma unroll
   for (int d = 0; d < 2; ++d) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
+    for (int j = 0; j < RT; ++j)
       ra[d][j] = load_a16<NT>(ag + j * arow_stride + (int64_t)d * GT_K);
     const uint16_t* b = bg + (int64_t)d * fstep;
 #pragma unroll
@@ -116,34 +120,34 @@ __device__ __forceinline__ void gemm_bf16_mainloop(const GemmArgs& g, int64_t m0
       // keep the program order of the groups: the scheduler must not hoist later prefetches
       // above this step's waits
       __builtin_amdgcn_sched_barrier(0);
-      uint16_t* slot = As + d * (GT_M * GT_LD);
+      uint16_t* slot = As + d * (32 * RT * GT_LD);
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
+      for (int j = 0; j < RT; ++j)
         *reinterpret_cast<u32x4*>(slot + (arow + 32 * j) * GT_LD + ak) = ra[d][j];
       __builtin_amdgcn_sched_barrier(0);
       {
         const int64_t st = min((int64_t)(s + d + 2), last);
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
+        for (int j = 0; j < RT; ++j)
           ra[d][j] = load_a16<NT>(ag + j * arow_stride + st * GT_K);
       }
       __builtin_amdgcn_sched_barrier(0);
       __syncthreads();
-      bf16x8 af[2][GT_RT];
+      bf16x8 af[2][RT];
 #pragma unroll
-      for (int r = 0; r < GT_RT; ++r)
+      for (int r = 0; r < RT; ++r)
         af[0][r] = *reinterpret_cast<const bf16x8*>(slot + (r * 32 + fr) * GT_LD + fk);
 #pragma unroll
       for (int kb = 0; kb < GT_KB; ++kb) {
         if (kb + 1 < GT_KB) {
 #pragma unroll
-          for (int r = 0; r < GT_RT; ++r)
+          for (int r = 0; r < RT; ++r)
             af[(kb + 1) & 1][r] = *reinterpret_cast<const bf16x8*>(
                 slot + (r * 32 + fr) * GT_LD + (kb + 1) * 16 + fk);
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int r = 0; r < GT_RT; ++r)
+        for (int r = 0; r < RT; ++r)
 #pragma unroll
           for (int c = 0; c < 2; ++c)
             acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[kb & 1][r], rb[d][kb][c],
@@ -169,7 +173,7 @@ __device__ __forceinline__ void gemm_bf16_mainloop(const GemmArgs& g, int64_t m0
 // Element e of lane l in tile c: row i = (e % 4) + 4 (l / 32) + 8 (e / 4), node j = l % 32.
 // =====================================================================================
 // PASS only names the instantiation (0: X~ (beta - beta_0), 1: X~^T (grad - r_0)) so that
-// profiles report the two products separately.
+// profiles report the two products separately; RT: row tiles of 32 per wave (8 or 4, above).
 //
 // 1D grid, XCD-aware: workgroups are dispatched round-robin over the 8 XCDs by linear id, so the
 // (row tile, k-chunk) pairs, ordered k-chunk-major, are cut into 8 contiguous ranges and range x
@@ -187,16 +191,17 @@ __device__ __forceinline__ void gemm_bf16_mainloop(const GemmArgs& g, int64_t m0
 #define CGL_STREAM_XT 1
 #endif
 constexpr bool kStreamXt = CGL_STREAM_XT != 0;
-template <int PASS>
+template <int PASS, int RT>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int mtiles, int ks, int per_xcd,
                                                    int* bump, int* extent) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[2 * GT_M * GT_LD];
+  static_assert(RT == 8 || RT == 4, "row tilings of 256 and 128 rows");
+  __shared__ __attribute__((aligned(16))) uint16_t As[2 * 32 * RT * GT_LD];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
   const int pair = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (pair >= mtiles * ks) return;  // padding of the last range (no barrier reached yet)
   const int z = pair / mtiles;
-  const int64_t m0 = (int64_t)(pair % mtiles) * GT_M;
+  const int64_t m0 = (int64_t)(pair % mtiles) * (32 * RT);
   const int64_t n0 = (int64_t)blockIdx.y * GT_N;
   int64_t K = g.K, kc = g.kchunk;
   if (extent != nullptr) {
@@ -215,15 +220,15 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int mtiles, int k
   }
   const int64_t k0 = (int64_t)z * kc;
   const int64_t k1 = min(K, k0 + kc);
-  floatx16 acc[GT_RT][2];
-  gemm_bf16_mainloop<PASS == 1 && kStreamXt>(g, m0, n0, k0, k1, As, acc);
+  floatx16 acc[RT][2];
+  gemm_bf16_mainloop<RT, PASS == 1 && kStreamXt>(g, m0, n0, k0, k1, As, acc);
   float* C = g.C + (int64_t)z * g.c_split_stride;
   const int hi = lane >> 5;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const int64_t node = n0 + wid * 64 + c * 32 + (lane & 31);
 #pragma unroll
-    for (int r = 0; r < GT_RT; ++r)
+    for (int r = 0; r < RT; ++r)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int64_t m = m0 + r * 32 + 4 * hi + 8 * q;

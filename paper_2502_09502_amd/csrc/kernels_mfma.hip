@@ -1061,6 +1061,28 @@ void launch_make_bf16(int xtype, const void* X, int64_t ldx, int64_t n, int64_t 
     hipLaunchKernelGGL(k_make_bf16<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)X, ldx, n, p, n_pad, ldp, Xb, Xbt);
 }
 
+// One product launch in the row tiling rt (8: 256 rows, 4: 128 rows per workgroup); with e0,
+// the launch itself records its start and end (no separate event packets).
+template <int PASS>
+static void launch_bf16(int rt, dim3 grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                        const GemmArgs& g, int mt, int ks, int per, int* bump, int* extent) {
+  if (rt == 4) {
+    if (e0 != nullptr)
+      hipExtLaunchKernelGGL((k_gemm_bf16<PASS, 4>), grid, dim3(256), 0, s, e0, e1, 0, g, mt, ks,
+                            per, bump, extent);
+    else
+      hipLaunchKernelGGL((k_gemm_bf16<PASS, 4>), grid, dim3(256), 0, s, g, mt, ks, per, bump,
+                         extent);
+  } else {
+    if (e0 != nullptr)
+      hipExtLaunchKernelGGL((k_gemm_bf16<PASS, 8>), grid, dim3(256), 0, s, e0, e1, 0, g, mt, ks,
+                            per, bump, extent);
+    else
+      hipLaunchKernelGGL((k_gemm_bf16<PASS, 8>), grid, dim3(256), 0, s, g, mt, ks, per, bump,
+                         extent);
+  }
+}
+
 void launch_gemm_x(const MixedDev& md, hipStream_t s, bool advance, hipEvent_t e0, hipEvent_t e1) {
   GemmArgs g;
   g.A = md.Xb;
@@ -1073,14 +1095,10 @@ void launch_gemm_x(const MixedDev& md, hipStream_t s, bool advance, hipEvent_t e
   g.C = md.dUp;
   g.ldc = md.n_pad;
   g.c_split_stride = md.dUp_split;
-  const int mt = (int)(md.n_pad / GT_M), per = (mt * md.ksx + 7) / 8;
+  const int mt = (int)(md.n_pad / (32 * md.x_rt)), per = (mt * md.ksx + 7) / 8;
   dim3 grid((unsigned)(8 * per), (unsigned)(md.S_pad / GT_N));
   int* bump = advance ? md.cycle : nullptr;
-  if (e0 != nullptr)  // the launch itself records its start and end (no separate event packets)
-    hipExtLaunchKernelGGL(k_gemm_bf16<0>, grid, dim3(256), 0, s, e0, e1, 0, g, mt, md.ksx, per,
-                          bump, md.keff);
-  else
-    hipLaunchKernelGGL(k_gemm_bf16<0>, grid, dim3(256), 0, s, g, mt, md.ksx, per, bump, md.keff);
+  launch_bf16<0>(md.x_rt, grid, s, e0, e1, g, mt, md.ksx, per, bump, md.keff);
 }
 
 void launch_gemm_xt(const MixedDev& md, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
@@ -1095,14 +1113,9 @@ void launch_gemm_xt(const MixedDev& md, hipStream_t s, hipEvent_t e0, hipEvent_t
   g.C = md.dH;
   g.ldc = md.ldp;
   g.c_split_stride = md.dH_split;
-  const int mt = (int)(md.ldp / GT_M), per = (mt * md.ksplit + 7) / 8;
+  const int mt = (int)(md.ldp / (32 * md.xt_rt)), per = (mt * md.ksplit + 7) / 8;
   dim3 grid((unsigned)(8 * per), (unsigned)(md.S_pad / GT_N));
-  int* none = nullptr;
-  if (e0 != nullptr)
-    hipExtLaunchKernelGGL(k_gemm_bf16<1>, grid, dim3(256), 0, s, e0, e1, 0, g, mt, md.ksplit, per,
-                          none, none);
-  else
-    hipLaunchKernelGGL(k_gemm_bf16<1>, grid, dim3(256), 0, s, g, mt, md.ksplit, per, none, none);
+  launch_bf16<1>(md.xt_rt, grid, s, e0, e1, g, mt, md.ksplit, per, nullptr, nullptr);
 }
 
 void launch_mixed_loss(const MixedDev& md, hipStream_t s) {

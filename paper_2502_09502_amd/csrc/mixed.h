@@ -59,10 +59,12 @@ struct MixedDev {
   int64_t dUp_split;
   int ksx;
   int64_t x_kchunk;
+  int x_rt;             // row tiles of 32 per wave of the X pass's product (8 or 4)
   float* dH;            // ksplit x S_pad x ldp split-K partials of the X^T pass
   int64_t dH_split;
   int ksplit;
   int64_t xt_kchunk;
+  int xt_rt;            // the same for the X^T pass
   double* lpart;        // S x nrt loss partials
   double* npart;        // S x nrt: sums of (f_i'(u) dU_i)^2, the scale of the loss's rounding
   double restart_slack; // > 0: a restart needs L^{t+1} >= L^t + slack 2^-9 sqrt(sum npart)

@@ -195,6 +195,28 @@ def test_operand_reorder_matches_natural_order(loss, monkeypatch):
         assert rb.lower_bound <= ra.primal + 1e-12 * abs(ra.primal)
 
 
+@pytest.mark.parametrize("loss", ["ls", "logistic"])
+def test_row_tilings_agree(loss, monkeypatch, tmp_path):
+    """The two row tilings of the BF16 products (256 and 128 rows per workgroup; the autotuner
+    picks one per product shape) give the same certified results within the tolerance, and both
+    match the oracle. The BF16 design makes the products' inputs identical in both runs; only
+    the FP32 summation order differs."""
+    monkeypatch.setenv("CGL_TUNE_CACHE", str(tmp_path / "splits.txt"))
+    d = synth.make_dataset(700, 300, 6, loss=loss, dtype="bf16", config_id=90)
+    sets = synth.node_sets(d.p, d.k, 8, 15, config_id=90)
+    out = []
+    for tile in ("256", "128"):
+        monkeypatch.setenv("CGL_FORCE_TILE", tile)
+        prob = _problem(d)
+        out.append(prob.solve_batch(_specs(prob, sets)))
+    for (z0, z1), ra, rb in zip(sets, *out):
+        _check(d, ra, z0, z1)
+        _check(d, rb, z0, z1)
+        assert rel(ra.primal, rb.primal) <= 2e-6
+        assert ra.lower_bound <= rb.primal + 1e-12 * abs(rb.primal)
+        assert rb.lower_bound <= ra.primal + 1e-12 * abs(ra.primal)
+
+
 def test_support_prefix_strays_and_overflow(monkeypatch):
     """A support prefix capped far below the union (128 of 300 coordinates) sends every later
     entrant out of the operand as a stray (added to the X-pass product from X~^T) and, past the
@@ -382,9 +404,9 @@ def test_eigen_perspective_on_the_batched_engine(dtype):
 
 
 def test_split_tuning_persists_across_contexts(tmp_path, monkeypatch):
-    """The split-K choices the autotuner times at engine setup go to the tuning cache file (one
-    line per product: arch, pass, rows, k-length, nodes, split) and a later context on the same
-    architecture loads them instead of timing again."""
+    """The tilings the autotuner times at engine setup go to the tuning cache file (one line per
+    product: arch, pass, rows, k-length, nodes, tiling code = split-K, plus 100 for the 128-row
+    tile) and a later context on the same architecture loads them instead of timing again."""
     path = tmp_path / "splits.txt"
     monkeypatch.setenv("CGL_TUNE_CACHE", str(path))
     d = synth.make_dataset(1500, 600, 5, loss="ls", dtype="bf16", config_id=83, k_true=5)

@@ -57,11 +57,12 @@ TRAFFIC_SOURCES = ("paper_2502_09502_amd/csrc/gemm_bf16.h",)  # the product kern
 
 
 def tiling_desc(code):
-    """A product's tiling from the engine's code (split-K, plus 100 for the 128-row tile)."""
+    """A product's tiling from the engine's code (split-K, plus 100 for the 128-row tile and 200
+    for the 64-row tile)."""
     code = int(code)
     if code <= 0:
         return None
-    return f"{128 if code >= 100 else 256} rows x 256 nodes per workgroup, split-K {code % 100}"
+    return f"{256 >> min(code // 100, 2)} rows x 256 nodes per workgroup, split-K {code % 100}"
 
 
 def measured_traffic(key: str, tiling=None):

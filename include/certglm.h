@@ -151,8 +151,8 @@ int cgl_ctx_destroy(cgl_ctx* ctx);
  *            count, total_ms = 0);
  *        14 = the tilings of the products of the last batched engine set up on this context,
  *            whatever the profiling level (total_ms = the X pass's code, launches = the X^T
- *            pass's; code = split-K, plus 100 for the 128-row tile, else 256 rows; 0 before any
- *            engine); reset does not apply to it.
+ *            pass's; code = split-K, plus 100 for the 128-row tile or 200 for the 64-row tile,
+ *            else 256 rows; 0 before any engine); reset does not apply to it.
  * cgl_ctx_kernel_stats returns the totals since the last reset (reset = 1 clears them). */
 int cgl_ctx_set_profiling(cgl_ctx* ctx, int32_t on);
 int cgl_ctx_kernel_stats(cgl_ctx* ctx, int32_t which, int32_t reset, double* total_ms,

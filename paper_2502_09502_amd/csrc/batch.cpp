@@ -378,11 +378,12 @@ std::vector<int> MixedWork::split_candidates(int64_t m_tiles, int64_t K) {
   return c;
 }
 
-// Every split candidate of the 256-row tiling, then those of the 128-row tiling (M rows, a
-// multiple of 256, and a k-length of K).
+// Every split candidate of the 256-row tiling, then those of the 128-row and the 64-row tilings
+// (M rows, a multiple of 256, and a k-length of K).
 std::vector<int> MixedWork::tiling_candidates(int64_t M, int64_t K) {
   std::vector<int> c = split_candidates(M / GT_M, K);
-  for (int ks : split_candidates(M / (GT_M / 2), K)) c.push_back(ks + kTile128);
+  for (int t = 1; t <= 2; ++t)
+    for (int ks : split_candidates(M / (GT_M >> t), K)) c.push_back(ks + t * kTile128);
   return c;
 }
 
@@ -419,15 +420,16 @@ void MixedWork::tune_splits(Problem& P) {
   hipStream_t s = stream;
   const char* env = std::getenv("CGL_AUTOTUNE");
   const bool tune = !(env && env[0] == '0');
-  // test hook: CGL_FORCE_TILE = 256 or 128 keeps only that row tiling (not saved to the cache)
+  // test hook: CGL_FORCE_TILE = 256, 128 or 64 keeps only that row tiling (not saved to the
+  // cache)
   const char* ft = std::getenv("CGL_FORCE_TILE");
   const int force = ft ? std::atoi(ft) : 0;
   for (int pass = 0; pass < 2; ++pass) {
     std::vector<int> cand = pass == 0 ? split_cands_x : split_cands_xt;
-    if (force == 256 || force == 128) {
+    if (force == 256 || force == 128 || force == 64) {
       std::vector<int> keep;
       for (int c : cand)
-        if ((c >= kTile128) == (force == 128)) keep.push_back(c);
+        if (32 * code_rt(c) == force) keep.push_back(c);
       if (!keep.empty()) cand = keep;
     }
     const int64_t m_tiles = pass == 0 ? n_pad / GT_M : ldp / GT_M;

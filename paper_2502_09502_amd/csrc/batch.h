@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <memory>
 #include <vector>
 
@@ -101,10 +102,11 @@ struct MixedWork {
   hipGraphExec_t graph_exec = nullptr;  // one chunk of cycles
   MixedDev md{};
 
-  // Tilings of the two products, as codes: the split-K, plus kTile128 for the 128-row tile
-  // (else 256 rows). The autotuner picks one code per product shape.
+  // Tilings of the two products, as codes: the split-K, plus kTile128 for the 128-row tile and
+  // 2 kTile128 for the 64-row tile (else 256 rows). The autotuner picks one code per product
+  // shape.
   static constexpr int kTile128 = 100;
-  static int code_rt(int code) { return code >= kTile128 ? 4 : 8; }
+  static int code_rt(int code) { return 8 >> std::min(code / kTile128, 2); }
   static int code_ks(int code) { return code % kTile128; }
   std::vector<int> split_cands_x, split_cands_xt;
   static std::vector<int> split_candidates(int64_t m_tiles, int64_t K);

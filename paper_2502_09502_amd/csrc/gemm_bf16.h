@@ -7,11 +7,13 @@
 // GT_N.
 //
 // Workgroup: 32 RT rows of A x 256 nodes, 4 waves; wave w owns nodes [64 w, 64 w + 64) as
-// RT x 2 v_mfma_f32_32x32x16_bf16 tiles (rows x nodes), 32 RT accumulators per lane. Two row
+// RT x 2 v_mfma_f32_32x32x16_bf16 tiles (rows x nodes), 32 RT accumulators per lane. Three row
 // tilings, chosen per product shape by the engine's autotuner: RT = 8 (256 rows, one wave per
-// SIMD; a row tile this tall halves the L2 traffic of B, since every row tile reads all of B
-// once) and RT = 4 (128 rows: twice the workgroups, for designs with few rows; two workgroups
-// per CU would leave too few registers for the prefetch buffers). The A tile (32 RT x 64) is
+// SIMD; the tallest tile reads the least of B from L2, since every row tile reads all of B
+// once), RT = 4 (128 rows) and RT = 2 (64 rows): more workgroups for the same rows, so fewer
+// k-chunks and fewer partial sums fill the chip, for four times the L2 reads of B at RT = 2
+// (two workgroups per CU at RT = 4 would leave too few registers for the prefetch buffers).
+// The A tile (32 RT x 64) is
 // shared through a two-slot LDS ring (rows of 144 bytes: 9 units of 16 bytes, so that 16 lanes
 // reading 16 consecutive rows hit 16 distinct bank groups); each wave's B fragments go straight
 // from global memory into registers (each B element is used by exactly one wave of the
@@ -173,7 +175,7 @@ __device__ __forceinline__ void gemm_bf16_mainloop(const GemmArgs& g, int64_t m0
 // Element e of lane l in tile c: row i = (e % 4) + 4 (l / 32) + 8 (e / 4), node j = l % 32.
 // =====================================================================================
 // PASS only names the instantiation (0: X~ (beta - beta_0), 1: X~^T (grad - r_0)) so that
-// profiles report the two products separately; RT: row tiles of 32 per wave (8 or 4, above).
+// profiles report the two products separately; RT: row tiles of 32 per wave (8, 4 or 2, above).
 //
 // 1D grid, XCD-aware: workgroups are dispatched round-robin over the 8 XCDs by linear id, so the
 // (row tile, k-chunk) pairs, ordered k-chunk-major, are cut into 8 contiguous ranges and range x
@@ -194,7 +196,7 @@ constexpr bool kStreamXt = CGL_STREAM_XT != 0;
 template <int PASS, int RT>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int mtiles, int ks, int per_xcd,
                                                    int* bump, int* extent) {
-  static_assert(RT == 8 || RT == 4, "row tilings of 256 and 128 rows");
+  static_assert(RT == 8 || RT == 4 || RT == 2, "row tilings of 256, 128 and 64 rows");
   __shared__ __attribute__((aligned(16))) uint16_t As[2 * 32 * RT * GT_LD];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;

@@ -1061,12 +1061,19 @@ void launch_make_bf16(int xtype, const void* X, int64_t ldx, int64_t n, int64_t 
     hipLaunchKernelGGL(k_make_bf16<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)X, ldx, n, p, n_pad, ldp, Xb, Xbt);
 }
 
-// One product launch in the row tiling rt (8: 256 rows, 4: 128 rows per workgroup); with e0,
-// the launch itself records its start and end (no separate event packets).
+// One product launch in the row tiling rt (8: 256 rows, 4: 128 rows, 2: 64 rows per
+// workgroup); with e0, the launch itself records its start and end (no separate event packets).
 template <int PASS>
 static void launch_bf16(int rt, dim3 grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
                         const GemmArgs& g, int mt, int ks, int per, int* bump, int* extent) {
-  if (rt == 4) {
+  if (rt == 2) {
+    if (e0 != nullptr)
+      hipExtLaunchKernelGGL((k_gemm_bf16<PASS, 2>), grid, dim3(256), 0, s, e0, e1, 0, g, mt, ks,
+                            per, bump, extent);
+    else
+      hipLaunchKernelGGL((k_gemm_bf16<PASS, 2>), grid, dim3(256), 0, s, g, mt, ks, per, bump,
+                         extent);
+  } else if (rt == 4) {
     if (e0 != nullptr)
       hipExtLaunchKernelGGL((k_gemm_bf16<PASS, 4>), grid, dim3(256), 0, s, e0, e1, 0, g, mt, ks,
                             per, bump, extent);

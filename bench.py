@@ -34,7 +34,8 @@ WORKLOAD = ("256 least-squares node relaxations sharing X: n=20000, p=10000, BF1
             "(Toeplitz rho=0.5, standardised), k=10, M=2, lambda2=1e-3, |Z0|~U[0,20], "
             "|Z1|~U[0,10], FP64-certified rel. gap 1e-6")
 KERNEL_NAMES = {0: "k_xt (plain X^T pass)", 1: "k_xb (plain X pass)",
-                2: "k_gemm_bf16<1> (batched X^T pass)", 3: "k_gemm_bf16<0> (batched X pass)",
+                2: "k_gemm_bf16<1, RT> (batched X^T pass)",
+                3: "k_gemm_bf16<0, RT> (batched X pass)",
                 4: "k_gemm_f64 (FP64 certification X pass)"}
 
 

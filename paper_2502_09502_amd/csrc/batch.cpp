@@ -666,6 +666,15 @@ int MixedWork::cert_round(Problem& P, bool overlap) {
   hipStream_t s = stream;
   cgl_ctx* ctx = P.ctx;
   for (int sl : want) want_since[sl] = -1;
+  // least-squares nodes first: with a Gram matrix they take its rows (the first nls of the list)
+  // and only the others the FP64 product with all of X^T
+  int nls = 0;
+  if (G.ptr != nullptr) {
+    std::stable_partition(want.begin(), want.end(), [&](int sl) {
+      return mem_host[st_host[sl].member].loss == LOSS_LS;
+    });
+    for (int sl : want) nls += mem_host[st_host[sl].member].loss == LOSS_LS ? 1 : 0;
+  }
   upload_list(P, want, kListCert);
   hipEvent_t e0 = ctx->profiling ? ctx->event(100) : nullptr;
   hipEvent_t e1 = ctx->profiling ? ctx->event(101) : nullptr;
@@ -685,20 +694,19 @@ int MixedWork::cert_round(Problem& P, bool overlap) {
   launch_gemm_f64_rows(P.xtype, xt, n_pad, sidx.as<int>(), P.n, P.p, kdev, Bu.as<double>(), ldp,
                        nq, U64.as<double>(), n_pad, part64.as<double>(), part64_cap, s);
   if (e1) CGL_HIP(hipEventRecord(e1, s));
-  // X^T grad f(X beta): least squares from the Gram rows on the same support (p K against n p
-  // products), else (a round with nodes of other losses too) the FP64 product with all of X^T
-  bool gram = G.ptr != nullptr;
-  for (int sl : want) gram = gram && mem_host[st_host[sl].member].loss == LOSS_LS;
-  if (gram) {
+  // X^T grad f(X beta): the least-squares nodes from the Gram rows on the same support (p K
+  // against n p products), the others by the FP64 product with all of X^T
+  if (nls > 0) {
     launch_gemm_f64_rows(XT_F64, G.ptr, ldg, sidx.as<int>(), P.p, P.p, kdev, Bu.as<double>(), ldp,
-                         nq, H64.as<double>(), ldp, part64.as<double>(), part64_cap, s);
-    launch_gram_finish(H64.as<double>(), ldp, P.p, nq, md, list.as<int>(), s);
+                         nls, H64.as<double>(), ldp, part64.as<double>(), part64_cap, s);
+    launch_gram_finish(H64.as<double>(), ldp, P.p, nls, md, list.as<int>(), s);
   }
   launch_cert_resid(md, list.as<int>(), nq, U64.as<double>(), R64.as<double>(),
                     cpart.as<double>(), ncchunk, cchunk, s);
-  if (!gram)
-    launch_gemm_f64(P.xtype, xt, n_pad, P.p, P.n, R64.as<double>(), n_pad, nq, H64.as<double>(),
-                    ldp, part64.as<double>(), part64_cap, s);
+  if (nls < nq)
+    launch_gemm_f64(P.xtype, xt, n_pad, P.p, P.n, R64.as<double>() + (int64_t)nls * n_pad, n_pad,
+                    nq - nls, H64.as<double>() + (int64_t)nls * ldp, ldp, part64.as<double>(),
+                    part64_cap, s);
   launch_cert_finish(md, list.as<int>(), nq, B64.as<double>(), H64.as<double>(),
                      cpart.as<double>(), ncchunk, s);
   if (span) CGL_HIP(hipEventRecord(ctx->event(203), s));

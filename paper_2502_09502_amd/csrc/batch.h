@@ -21,7 +21,7 @@ constexpr int kCertWait = 1;    // chunks the oldest request may wait for others
 constexpr int kReorderEvery = 8;  // cycles between checks of the X-pass operand order
 // a reorder is made when the union is at least 1 / kReorderShrink of the extent shorter
 constexpr int kReorderShrink = 8;
-constexpr int64_t kGramMaxP = 16384;  // least squares: largest p with an FP64 Gram matrix (2.1 GB)
+constexpr int64_t kGramMaxP = 20480;  // least squares: largest p with an FP64 Gram matrix (3.4 GB)
 
 struct Admission {
   int slot;

@@ -480,8 +480,8 @@ def copy_calibration(nbytes: int) -> None:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--nodes", type=int, default=256)
     ap.add_argument("--plain-nodes", type=int, default=16,
                     help="nodes of the plain FP64 per-node comparator")

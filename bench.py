@@ -595,6 +595,15 @@ def main():
             ms, cnt = ctx.kernel_stats(w, reset=True)
             phases[name] = {"ms_per_step": round(ms / args.steps, 3), "count_per_step": cnt / args.steps}
         phases["reorders_per_step"] = ctx.kernel_stats(12, reset=True)[1] / args.steps
+        # cycles of the timed steps (one X pass each) and the share of the columns they read:
+        # the X pass reads only the operand's nonzero prefix of the support-first column order
+        frac, passes = ctx.kernel_stats(9, reset=True)
+        if passes:
+            cycles = passes / args.steps
+            phases["x_pass_kernel"] = {"count_per_step": cycles,
+                                       "mean_columns_read": round(frac / passes, 4)}
+            for name in ("iteration_chunks", "chunks_gpu"):
+                phases[name]["us_per_cycle"] = round(1e3 * phases[name]["ms_per_step"] / cycles, 1)
     # one more step, untimed, with kernel events on the roofline's kernel (its launches then run
     # outside graphs): the kernel's live average launch time and the per-cycle kernel figures
     for w in range(12):
@@ -610,16 +619,6 @@ def main():
             ms, cnt = ctx.kernel_stats(w)
             phases[name] = {"ms_per_step": round(ms, 3), "count_per_step": cnt,
                             "from": "the profiled step"}
-        cycles = phases["xt_pass_kernel"]["count_per_step"]
-        if cycles:
-            for name in ("iteration_chunks", "chunks_gpu"):
-                phases[name]["us_per_cycle"] = round(1e3 * phases[name]["ms_per_step"] / cycles, 1)
-        # the X pass reads only the operand's nonzero prefix of the support-first column order
-        # (not timed: a timed launch starts a few microseconds later)
-        frac, passes = ctx.kernel_stats(9)
-        if passes:
-            phases["x_pass_kernel"] = {"count_per_step": passes,
-                                       "mean_columns_read": round(frac / passes, 4)}
     ok = all(r.status == "converged" and r.gap_rel <= 1e-6 for r in results)
     iters = [r.iters for r in results]
     print(f"# {mode}: {value:.2f} solves/s, all certified: {ok}, iterations median "

@@ -10,7 +10,7 @@ namespace cgl {
 
 constexpr int kStallCycles = 6;   // re-centre when the working gap has not halved for this long
 constexpr double kCertGap = 1.0;  // ask for an FP64 round once the working gap is <= kCertGap * tol
-constexpr double kRestartSlack = 1.0;  // noise margin of the restart test (0: plain comparison)
+constexpr double kRestartSlack = 1.5;  // noise margin of the restart test (0: plain comparison)
 
 // One problem served by an engine: the problems of an engine share the design X and differ in
 // the labels, the loss and the constants. A slot's state names its problem (NodeDev::member).

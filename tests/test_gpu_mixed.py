@@ -209,6 +209,11 @@ def test_row_tilings_agree(loss, monkeypatch, tmp_path):
         monkeypatch.setenv("CGL_FORCE_TILE", tile)
         prob = _problem(d)
         out.append(prob.solve_batch(_specs(prob, sets)))
+        # the tilings in use, as the stats call reports them (code = split-K + 100 * t, with
+        # rows = 256 >> t)
+        code_x, code_xt = ctx().kernel_stats(14)
+        for code in (int(code_x), int(code_xt)):
+            assert code % 100 >= 1 and 256 >> (code // 100) == int(tile), (tile, code)
     for (z0, z1), *rs in zip(sets, *out):
         for r in rs:
             _check(d, r, z0, z1)

@@ -410,7 +410,7 @@ void MixedWork::set_split_xt(int code) {
 // with HIP events.
 // Its cost is that time plus the reading of its partial sums by the next kernel (one FP32 slab
 // of nodes x rows per chunk, charged at 4 TB/s, about what the consumers achieve); the cheapest
-// wins, a later candidate (a larger split, or the 128-row tile) only when it is 2% cheaper.
+// wins, a later candidate (a larger split, or a shorter row tile) only when it is 2% cheaper.
 // Results (the tiling's code) are kept on the context per (pass, rows, k-length, nodes) and in
 // the tuning cache file of the device's architecture, which later contexts load
 // (CGL_TUNE_CACHE); CGL_AUTOTUNE=0 keeps the 256-row tiling's largest split that fills the chip
@@ -424,9 +424,10 @@ void MixedWork::tune_splits(Problem& P) {
   // cache)
   const char* ft = std::getenv("CGL_FORCE_TILE");
   const int force = ft ? std::atoi(ft) : 0;
+  const bool forced = force == 256 || force == 128 || force == 64;
   for (int pass = 0; pass < 2; ++pass) {
     std::vector<int> cand = pass == 0 ? split_cands_x : split_cands_xt;
-    if (force == 256 || force == 128 || force == 64) {
+    if (forced) {
       std::vector<int> keep;
       for (int c : cand)
         if (32 * code_rt(c) == force) keep.push_back(c);
@@ -435,10 +436,10 @@ void MixedWork::tune_splits(Problem& P) {
     const int64_t m_tiles = pass == 0 ? n_pad / GT_M : ldp / GT_M;
     const std::array<int64_t, 4> key = {pass, pass == 0 ? n_pad : ldp, pass == 0 ? ldp : n_pad,
                                         (int64_t)S_pad};
-    auto set = [&](int ks) { pass == 0 ? set_split_x(ks) : set_split_xt(ks); };
+    auto set = [&](int code) { pass == 0 ? set_split_x(code) : set_split_xt(code); };
     auto launch = [&]() { pass == 0 ? launch_gemm_x(md, s) : launch_gemm_xt(md, s); };
     auto hit = ctx->tuned_split.find(key);
-    if (hit != ctx->tuned_split.end() && force == 0) {
+    if (hit != ctx->tuned_split.end() && !forced) {
       set(hit->second);
       ctx->tiling[pass] = hit->second;
       continue;
@@ -468,7 +469,7 @@ void MixedWork::tune_splits(Problem& P) {
     }
     set(choice);
     ctx->tiling[pass] = choice;
-    if (force != 0) continue;
+    if (forced) continue;
     ctx->tuned_split[key] = choice;
     if (tune && cand.size() > 1) ctx->save_tuning(key, choice);
   }

@@ -601,7 +601,8 @@ def main():
         if passes:
             cycles = passes / args.steps
             phases["x_pass_kernel"] = {"count_per_step": cycles,
-                                       "mean_columns_read": round(frac / passes, 4)}
+                                       "mean_columns_read": round(frac / passes, 4),
+                                       "tiling": tiling_desc(ctx.kernel_stats(14)[0])}
             for name in ("iteration_chunks", "chunks_gpu"):
                 phases[name]["us_per_cycle"] = round(1e3 * phases[name]["ms_per_step"] / cycles, 1)
     # one more step, untimed, with kernel events on the roofline's kernel (its launches then run

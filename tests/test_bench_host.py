@@ -78,3 +78,23 @@ def test_traffic_counts_only_for_unchanged_sources(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_SOURCES", orig)
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "none.md"))
     assert bench.measured_traffic("traffic_bytes_xt_pass") is None
+
+
+def test_tiling_codes_and_the_traffic_record():
+    # the engine's tiling codes: split-K, plus 100 for the 128-row tile and 200 for the 64-row one
+    assert bench.tiling_desc(3) == "256 rows x 256 nodes per workgroup, split-K 3"
+    assert bench.tiling_desc(103) == "128 rows x 256 nodes per workgroup, split-K 3"
+    assert bench.tiling_desc(201) == "64 rows x 256 nodes per workgroup, split-K 1"
+    assert bench.tiling_desc(0) is None  # no engine yet
+    rec = bench.measured_traffic("traffic_bytes_xt_pass")
+    if rec is None:
+        pytest.skip("the committed counter record does not match the current kernel sources")
+    # the record holds for the tiling it was taken on, and for no other
+    vals = {}
+    with open(bench.TRAFFIC_FILE) as fh:
+        for line in fh:
+            if line.startswith("tiling_xt_pass:"):
+                vals["xt"] = int(line.split(":")[1])
+    assert bench.measured_traffic("traffic_bytes_xt_pass", tiling=vals["xt"]) == rec
+    other = vals["xt"] + 1 if vals["xt"] % 100 < 99 else vals["xt"] - 1
+    assert bench.measured_traffic("traffic_bytes_xt_pass", tiling=other) is None

@@ -829,7 +829,11 @@ void MixedWork::admit(Problem& P, const std::vector<Admission>& adm) {
     CGL_HIP(hipMemcpyAsync(bres.as<double>() + o, ws.data(), (size_t)P.p * 8,
                            hipMemcpyHostToDevice, s));
   }
-  CGL_HIP(hipStreamSynchronize(s));
+  // The staged warm starts are local: their copies must finish before they go. The other
+  // staging (slot states, class rows, the list) is pinned and rewritten only after the next
+  // chunk's event, and the stream orders these copies before that chunk, so the host need not
+  // wait for them (nor for a certification round queued ahead of them).
+  if (!starts.empty()) CGL_HIP(hipStreamSynchronize(s));
   if (reorder && (int)adm.size() >= S / 4) {
     // many new supports: no prefix (no strays) until a check half an interval later lists them
     const int nopfx = (int)ldp;

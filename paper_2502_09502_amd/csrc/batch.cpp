@@ -99,6 +99,8 @@ void MixedWork::ensure(Problem& P) {
   bdual.alloc(Sp * 8);
   dop.alloc((size_t)S_pad * ldp * 2);
   gop.alloc((size_t)S_pad * n_pad * 2);
+  gop_r.alloc((size_t)S_pad * n_pad * 2);
+  gsel.alloc((size_t)S_pad * sizeof(int));
   dU.alloc(2 * (size_t)S_pad * n_pad * 4);
   // split-K of the two products: the candidates keep >= 16 k-steps of 32 per chunk and at most
   // four rounds of 256 workgroups (one workgroup of the product fits on a compute unit); the
@@ -119,13 +121,15 @@ void MixedWork::ensure(Problem& P) {
   nrt = (int)((n_pad + rchunk - 1) / rchunk);
   lpart.alloc((size_t)S * nrt * 8);
   npart.alloc((size_t)S * nrt * 8);
-  fpart.alloc((size_t)S * nrt * 8);
+  fpart.alloc((size_t)S * 2 * nrt * 8);
   cycle.alloc(sizeof(int));
   CGL_HIP(hipMemsetAsync(cycle.ptr, 0xff, sizeof(int), s));  // -1: the first cycle is 0
   prevsel.alloc((size_t)2 * S * 65 * sizeof(int));
   CGL_HIP(hipMemsetAsync(prevsel.ptr, 0, prevsel.bytes, s));
   CGL_HIP(hipMemsetAsync(dop.ptr, 0, (size_t)S_pad * ldp * 2, s));
   CGL_HIP(hipMemsetAsync(gop.ptr, 0, (size_t)S_pad * n_pad * 2, s));
+  CGL_HIP(hipMemsetAsync(gop_r.ptr, 0, (size_t)S_pad * n_pad * 2, s));
+  CGL_HIP(hipMemsetAsync(gsel.ptr, 0, gsel.bytes, s));
   CGL_HIP(hipMemsetAsync(dU.ptr, 0, 2 * (size_t)S_pad * n_pad * 4, s));
   CGL_HIP(hipMemsetAsync(dH.ptr, 0, dH.bytes, s));
   // certification buffers
@@ -264,6 +268,8 @@ void MixedWork::ensure(Problem& P) {
   md.bdual = bdual.as<double>();
   md.dop = dop.as<uint16_t>();
   md.gop = gop.as<uint16_t>();
+  md.gop_r = gop_r.as<uint16_t>();
+  md.gsel = gsel.as<int>();
   md.dU = dU.as<float>();
   md.dU_ring = (int64_t)S_pad * n_pad;
   md.dUp = dUp.as<float>();
@@ -484,7 +490,7 @@ static void mixed_cycle(MixedWork& W, hipStream_t s, hipEvent_t* ev = nullptr, b
   const bool tx = ev != nullptr && time_x;
   launch_gemm_x(W.md, s, true, tx ? ev[0] : nullptr, tx ? ev[1] : nullptr);
   launch_mixed_loss(W.md, s);
-  launch_mixed_resid(W.md, s);
+  launch_mixed_decide(W.md, s);
   launch_gemm_xt(W.md, s, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
   launch_mixed_node(W.md, s);
 }
@@ -744,7 +750,7 @@ void MixedWork::close_round(Problem& P) {
 
 size_t MixedWork::device_bytes() const {
   const DevBuf* bufs[] = {&Xb, &Xbt, &memtab, &st, &cls, &bring, &beta0, &H0, &base0, &base1, &e0f,
-                          &bres, &bdual, &dop, &gop, &dU, &dUp, &dH, &lpart, &npart, &fpart, &cycle, &prevsel, &B64,
+                          &bres, &bdual, &dop, &gop, &gop_r, &gsel, &dU, &dUp, &dH, &lpart, &npart, &fpart, &cycle, &prevsel, &B64,
                           &U64, &R64, &H64, &cpart, &list,
                           &Xt, &part64, &sflag, &sidx, &scount, &Bu, &G, &pinv, &pinv_new,
                           &perm, &perm_new, &dop_tmp, &pfx, &sj, &sv, &Bret};

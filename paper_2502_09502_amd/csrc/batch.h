@@ -53,7 +53,7 @@ struct MixedWork {
   DevBuf memtab;
   int member_of(const Problem* Q) const;  // index in members, -1 if not served
   void forget_member(const Problem* Q);    // a sharer is destroyed: no more nodes of it come
-  DevBuf Xb, Xbt, st, cls, bring, beta0, H0, base0, base1, e0f, bres, bdual, dop, gop, dU, dUp, dH, lpart, npart,
+  DevBuf Xb, Xbt, st, cls, bring, beta0, H0, base0, base1, e0f, bres, bdual, dop, gop, gop_r, gsel, dU, dUp, dH, lpart, npart,
       fpart, cycle, prevsel, B64, U64, R64, H64, cpart, list, Xt, part64,
       sflag, sidx, scount, Bu, G, Bret, pinv, pinv_new, perm, perm_new, dop_tmp, pfx, sj, sv;
   int64_t ldg = 0;  // least squares: G = X^T X in FP64 (p x ldg), when built

@@ -14,7 +14,8 @@
 // (and the bound certified, Sec. 3.4) when the working-precision gap stops improving.
 //
 // One iteration (cycle) for every active slot: k_gemm_x (split-K; it also advances the cycle
-// counter) -> k_mixed_loss -> k_mixed_resid (restart test and residual operand) -> k_gemm_xt
+// counter) -> k_mixed_loss (loss partials and the residual operand for both outcomes of the
+// restart test) -> k_mixed_decide (restart test; the chosen operand into gop) -> k_gemm_xt
 // (split-K) -> k_mixed_node (prox; commits the restart test).
 #include <limits.h>
 
@@ -43,9 +44,25 @@ __device__ __forceinline__ bool slot_running(const NodeDev* st) {
   return st->active != 0 && st->done == 0 && st->need_base == 0 && st->iter < st->max_iter;
 }
 
+// Momentum coefficient of Alg. 3 for the counter phi. The loss kernel's operand candidates and
+// the decision kernel's stored coefficient both come from here, so the two agree bit for bit.
+__device__ __forceinline__ double momentum_coef(double phi) { return phi / (phi + 3.0); }
+
 // =====================================================================================
-// dU^{t+1} = sum of the X-pass split-K partials (into the ring slot of this cycle) and the loss
-// terms f_i(u_0 + dU) summed per chunk. grid: (chunks, slots); 256 threads.
+// One pass over each slot's rows after the X pass (grid: (chunks, slots); 256 threads):
+// * dU^{t+1} = the sum of the X-pass split-K partials, into the ring slot of this cycle;
+// * the loss terms f_i(u_0 + dU) summed per chunk (and their rounding scale, for the margin of
+//   the restart test);
+// * the residual operand of the X^T pass, G = bf16(grad f(u_gamma) - r_0) with u_gamma = u_0 +
+//   dU^{t+1} + c (dU^{t+1} - dU^t), and on the dual monitor's iterations the F*(-zeta) partial
+//   sums at u_gamma (zeta = -grad f(u_gamma)).
+// The momentum coefficient c depends on the restart test (Alg. 3), which needs f(X beta^{t+1})
+// summed over every chunk. It takes one of two values that are known beforehand: c_r = 1/4 after
+// a restart (phi = 1), c_k for phi + 1 otherwise (phi itself while the momentum is not yet
+// primed). The kernel therefore writes G and the F* partials for both: gop (fragment order) and
+// fpart set 0 for c_k, gop_r (slot-major) and set 1 for c_r (only c_k when no restart is possible this cycle: unprimed, or
+// the first cycle after a rebase). k_mixed_decide takes the test and leaves the chosen operand
+// in gop; the node kernel reads the chosen F* partials.
 //
 // In the first cycle after a re-centre that kept the momentum (rebase), the product of this
 // cycle is X~ bf16(beta^{t+1} - beta_0') against the previous base beta_0', and beta^{t+1} is the
@@ -53,7 +70,7 @@ __device__ __forceinline__ bool slot_running(const NodeDev* st) {
 // product, i.e. X (beta^t - beta^{t+1}) with the rounding of an ordinary cycle's difference.
 // =====================================================================================
 __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
-  __shared__ double red[4];
+  __shared__ double red[4][4];
   // the X pass of this cycle has read the operand extent: its counter restarts for cycle + 2
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) md.keff[*md.cycle & 1] = 0;
   const int slot = blockIdx.y;
@@ -64,6 +81,12 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
   const double* yv = mb.y;
   const int cyc = *md.cycle;
   const bool rebase = st->rebase != 0;
+  // the two candidates of the momentum coefficient, and whether the node kernel of this cycle
+  // runs the dual monitor (uniform over the block)
+  const bool can_restart = st->primed != 0 && !rebase;
+  const double ck = momentum_coef(st->primed != 0 ? st->phi + 1.0 : st->phi);
+  const double cr = momentum_coef(1.0);
+  const bool check = (st->iter % st->check_every) == 0;
   float* dun = md.dU + (int64_t)(cyc & 1) * md.dU_ring + (int64_t)slot * md.n_pad;
   float* duo = md.dU + (int64_t)((cyc + 1) & 1) * md.dU_ring + (int64_t)slot * md.n_pad;
   const int64_t i0 = (int64_t)blockIdx.x * md.rchunk;
@@ -90,11 +113,12 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
     }
     __syncthreads();
   }
-  // four consecutive rows per thread and step (16-byte loads and stores; n_pad and the chunk
-  // bounds are multiples of 256)
-  double ls = 0.0, nz = 0.0;
+  // four consecutive rows per thread and step (16-byte loads and stores, 8-byte operand stores;
+  // n_pad and the chunk bounds are multiples of 256)
+  double ls = 0.0, nz = 0.0, fk = 0.0, fr = 0.0;
   const bool noise = md.restart_slack > 0.0;  // uniform: a launch argument
   const float* dup = md.dUp + (int64_t)slot * md.n_pad;
+  const int64_t nbk = md.S_pad >> 5;
   for (int64_t i = i0 + 4 * (int64_t)threadIdx.x; i < i1; i += 4 * 256) {
     float4 du = *reinterpret_cast<const float4*>(dup + i);
     for (int q = 1; q < md.ksx; ++q) {
@@ -110,8 +134,8 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
       du.z += sdu[i - i0 + 2];
       du.w += sdu[i - i0 + 3];
     }
+    float4 o = *reinterpret_cast<const float4*>(duo + i);  // dU^t
     if (rebase) {
-      float4 o = *reinterpret_cast<const float4*>(duo + i);
       o.x -= du.x;
       o.y -= du.y;
       o.z -= du.z;
@@ -120,10 +144,12 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
       du = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     *reinterpret_cast<float4*>(dun + i) = du;
-    const float dv[4] = {du.x, du.y, du.z, du.w};
+    const float dv[4] = {du.x, du.y, du.z, du.w}, ov[4] = {o.x, o.y, o.z, o.w};
+    uint16_t gk[4] = {0, 0, 0, 0}, gr[4] = {0, 0, 0, 0};
     if (loss == LOSS_LS) {
       const float4 e4 = *reinterpret_cast<const float4*>(md.e0f + (int64_t)slot * md.n_pad + i);
       const float ev[4] = {e4.x, e4.y, e4.z, e4.w};
+#pragma unroll
       for (int c = 0; c < 4; ++c) {
         if (i + c < md.n) {
           const double e = (double)ev[c] + (double)dv[c];  // u - y
@@ -132,128 +158,167 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
             const double t = 2.0 * e * (double)dv[c];
             nz += t * t;
           }
-        }
-      }
-    } else {
-      for (int c = 0; c < 4; ++c)
-        if (i + c < md.n) {
-          const double u = md.base0[(int64_t)slot * md.n_pad + i + c] + (double)dv[c];
-          ls += loss_val(loss, u, yv[i + c]);
-          if (noise) {
-            const double t = loss_grad(loss, u, yv[i + c]) * (double)dv[c];
-            nz += t * t;
+          const double y = yv[i + c];
+          // gamma's correction for each candidate; r = 2 (u_gamma - y); F*(-zeta) at zeta = -r
+          // is ||zeta||^2 / 4 - y.zeta
+          const double dgk = (double)dv[c] + ck * ((double)dv[c] - (double)ov[c]);
+          gk[c] = float_to_bf16((float)(2.0 * dgk));
+          if (check) {
+            const double r = 2.0 * ((double)ev[c] + dgk);
+            fk += 0.25 * r * r + y * r;
+          }
+          if (can_restart) {
+            const double dgr = (double)dv[c] + cr * ((double)dv[c] - (double)ov[c]);
+            gr[c] = float_to_bf16((float)(2.0 * dgr));
+            if (check) {
+              const double r = 2.0 * ((double)ev[c] + dgr);
+              fr += 0.25 * r * r + y * r;
+            }
           }
         }
+      }
+    } else {  // base0 holds u_0, base1 holds r_0 = grad f(u_0)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (i + c < md.n) {
+          const double u0 = md.base0[(int64_t)slot * md.n_pad + i + c];
+          const double r0 = md.base1[(int64_t)slot * md.n_pad + i + c];
+          const double y = yv[i + c];
+          const double u = u0 + (double)dv[c];
+          ls += loss_val(loss, u, y);
+          if (noise) {
+            const double t = loss_grad(loss, u, y) * (double)dv[c];
+            nz += t * t;
+          }
+          const double ugk = u0 + ((double)dv[c] + ck * ((double)dv[c] - (double)ov[c]));
+          gk[c] = float_to_bf16((float)(loss_grad(loss, ugk, y) - r0));
+          if (check) fk += fstar_term(loss, ugk, y);
+          if (can_restart) {
+            const double ugr = u0 + ((double)dv[c] + cr * ((double)dv[c] - (double)ov[c]));
+            gr[c] = float_to_bf16((float)(loss_grad(loss, ugr, y) - r0));
+            if (check) fr += fstar_term(loss, ugr, y);
+          }
+        }
+      }
+    }
+    // rows i .. i + 3 are consecutive within one 8-row group of the fragment layout
+    const int64_t f = frag_index(slot, i, nbk);
+    uint2 w;
+    w.x = (uint32_t)gk[0] | ((uint32_t)gk[1] << 16);
+    w.y = (uint32_t)gk[2] | ((uint32_t)gk[3] << 16);
+    *reinterpret_cast<uint2*>(md.gop + f) = w;
+    if (can_restart) {  // slot-major: only the decision kernel reads it
+      w.x = (uint32_t)gr[0] | ((uint32_t)gr[1] << 16);
+      w.y = (uint32_t)gr[2] | ((uint32_t)gr[3] << 16);
+      *reinterpret_cast<uint2*>(md.gop_r + (int64_t)slot * md.n_pad + i) = w;
     }
   }
-  ls = block_reduce(ls, red, OpAdd(), 0.0);
-  if (threadIdx.x == 0) md.lpart[(int64_t)slot * md.nrt + blockIdx.x] = ls;
-  if (noise) {  // the rounding scale of this chunk's loss terms: each dU_i carries a relative
-                // error of about 2^-9 (BF16 operand), which moves f by about f_i'(u) dU_i 2^-9
-    nz = block_reduce(nz, red, OpAdd(), 0.0);
-    if (threadIdx.x == 0) md.npart[(int64_t)slot * md.nrt + blockIdx.x] = nz;
+  // the four sums of the block in one pass: per wave, then over the waves
+  const double v4[4] = {ls, nz, fk, fr};
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double t = wave_sum(v4[v]);
+    if (lane == 0) red[v][wid] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int v = threadIdx.x;
+    const double t = (red[v][0] + red[v][1]) + (red[v][2] + red[v][3]);
+    const int64_t b = (int64_t)slot * md.nrt + blockIdx.x;
+    if (v == 0) md.lpart[b] = t;
+    // the rounding scale of this chunk's loss terms: each dU_i carries a relative error of
+    // about 2^-9 (BF16 operand), which moves f by about f_i'(u) dU_i 2^-9
+    else if (v == 1 && noise) md.npart[b] = t;
+    else if (v == 2 && check) md.fpart[((int64_t)slot * 2) * md.nrt + blockIdx.x] = t;
+    else if (v == 3 && check && can_restart)
+      md.fpart[((int64_t)slot * 2 + 1) * md.nrt + blockIdx.x] = t;
   }
 }
 
 // =====================================================================================
-// Restart test (Alg. 3) and residual operand. Every block of a slot evaluates the test from the
-// slot's state (L^{t+1} = f(X beta^{t+1}) + 2 lambda2 g(beta^{t+1}) from the loss partials, in a
-// fixed order) to get the momentum coefficient c; block 0 stores c and the outcome, which the
-// node kernel commits (no block of this kernel writes what another reads).
-// Then u_gamma = u_0 + dU^{t+1} + c (dU^{t+1} - dU^t); r = grad f(u_gamma); G = bf16(r - r_0);
-// F*(-zeta) partial sums with zeta = -r (dual monitor at gamma).
-// grid: (chunks, slots); 256 threads.
+// Restart test of Alg. 3 for every running slot: L^{t+1} = f(X beta^{t+1}) + 2 lambda2
+// g(beta^{t+1}) from the loss kernel's partials (in chunk order), against L^t plus the rounding
+// margin. Block 0 of a slot stores the momentum coefficient and the outcome, which the node
+// kernel commits, and gsel (1 after a restart: the node kernel then reads F* partial set 1).
+// After a restart every block copies its share of the slot's restart operand (gop_r) over gop,
+// so that the X^T pass reads one buffer (the two candidates of a node block in separate buffers
+// would double the pass's B traffic through L2). Every block evaluates the test from the same
+// partials with the same instructions, so they agree. grid: (kDecideBlocks, slots); 256 threads.
 // =====================================================================================
-__global__ __launch_bounds__(256) void k_mixed_resid(MixedDev md) {
-  __shared__ double red[4];
-  __shared__ double cs;
+constexpr int kDecideBlocks = 4;
+
+__global__ __launch_bounds__(256) void k_mixed_decide(MixedDev md) {
+  __shared__ int sel_s;
   const int slot = blockIdx.y;
-  NodeDev* st = md.st + slot;
-  if (!slot_running(st)) return;
-  const MemberDev& mb = md.mem[st->member];
-  const int loss = mb.loss;
-  const int cyc = *md.cycle;
-  const float* dun = md.dU + (int64_t)(cyc & 1) * md.dU_ring + (int64_t)slot * md.n_pad;
-  const float* duo = md.dU + (int64_t)((cyc + 1) & 1) * md.dU_ring + (int64_t)slot * md.n_pad;
+  const NodeDev* st = md.st + slot;
   if (threadIdx.x < 64) {
+    // the partials and the slot's state are loaded together (neither address depends on the
+    // other); the sums run across the wave in a fixed order, so every block gets the same values
+    const double* lp = md.lpart + (int64_t)slot * md.nrt;
+    const double* np = md.npart + (int64_t)slot * md.nrt;
+    const bool noise = md.restart_slack > 0.0;
     double a = 0.0, nz = 0.0;
-    for (int i = threadIdx.x; i < md.nrt; i += 64) a += md.lpart[(int64_t)slot * md.nrt + i];
-    a = wave_sum(a);
-    if (md.restart_slack > 0.0) {
-      for (int i = threadIdx.x; i < md.nrt; i += 64) nz += md.npart[(int64_t)slot * md.nrt + i];
-      nz = wave_sum(nz);
+    for (int i = threadIdx.x; i < md.nrt; i += 64) {
+      a += lp[i];
+      if (noise) nz += np[i];
     }
-    // rounding margin of the working objective (zero: Alg. 3's plain comparison)
-    const double margin = md.restart_slack * 0x1p-9 * sqrt(nz);
+    const bool run = slot_running(st);
+    const int primed = st->primed, rebase = st->rebase, restarts = st->restarts;
+    const double phi = st->phi, L_prev = st->L_prev, bsq = st->bsq_new, gnew = st->g_new;
+    const int mi = st->member;  // read before the slot is known to run: kept in the table
+    const MemberDev& mb = md.mem[(unsigned)mi < (unsigned)kMaxMembers ? mi : 0];
+    const double shift = mb.shift, lam2 = mb.lam2;
+    a = wave_sum(a);
+    nz = wave_sum(nz);
     if (threadIdx.x == 0) {
-      const double Lnew = a - mb.shift * st->bsq_new + 2.0 * (mb.lam2 + mb.shift) * st->g_new;
-      double phi = st->phi;
-      int primed = st->primed, restarts = st->restarts;
-      if (!primed) {
-        primed = 1;
-      } else if (st->rebase) {
-        // L^t was evaluated against the previous base: the momentum runs on untested
-        phi += 1.0;
-      } else if (Lnew >= st->L_prev + margin) {
-        phi = 1.0;
-        restarts += 1;
-      } else {
-        phi += 1.0;
+      int sel = -1;  // not running: nothing to decide
+      if (run) {
+        // rounding margin of the working objective (zero: Alg. 3's plain comparison)
+        const double margin = md.restart_slack * 0x1p-9 * sqrt(nz);
+        const double Lnew = a - shift * bsq + 2.0 * (lam2 + shift) * gnew;
+        double phin = phi;
+        int primedn = primed, restartsn = restarts;
+        sel = 0;
+        if (!primed) {
+          primedn = 1;
+        } else if (rebase) {
+          // L^t was evaluated against the previous base: the momentum runs on untested
+          phin += 1.0;
+        } else if (Lnew >= L_prev + margin) {
+          phin = 1.0;
+          restartsn += 1;
+          sel = 1;
+        } else {
+          phin += 1.0;
+        }
+        if (blockIdx.x == 0) {
+          NodeDev* sw = md.st + slot;
+          sw->c = momentum_coef(phin);
+          sw->rs_phi = phin;
+          sw->rs_L = Lnew;
+          sw->rs_primed = primedn;
+          sw->rs_restarts = restartsn;
+          md.gsel[slot] = sel;
+        }
       }
-      cs = phi / (phi + 3.0);
-      if (blockIdx.x == 0) {
-        st->c = cs;
-        st->rs_phi = phi;
-        st->rs_L = Lnew;
-        st->rs_primed = primed;
-        st->rs_restarts = restarts;
-      }
+      sel_s = sel;
     }
   }
   __syncthreads();
-  const double c = cs;
-  const int64_t i0 = (int64_t)blockIdx.x * md.rchunk;
-  const int64_t i1 = min(md.n_pad, i0 + md.rchunk);
-  // four consecutive rows per thread and step (16-byte loads; 8-byte operand stores)
-  double fs = 0.0;
-  const int64_t nbk = md.S_pad >> 5;
-  for (int64_t i = i0 + 4 * (int64_t)threadIdx.x; i < i1; i += 4 * 256) {
-    const float4 n4 = *reinterpret_cast<const float4*>(dun + i);
-    const float4 o4 = *reinterpret_cast<const float4*>(duo + i);
-    const float nv[4] = {n4.x, n4.y, n4.z, n4.w}, ov[4] = {o4.x, o4.y, o4.z, o4.w};
-    float ev[4] = {0.f, 0.f, 0.f, 0.f};
-    if (loss == LOSS_LS) {
-      const float4 e4 = *reinterpret_cast<const float4*>(md.e0f + (int64_t)slot * md.n_pad + i);
-      ev[0] = e4.x;
-      ev[1] = e4.y;
-      ev[2] = e4.z;
-      ev[3] = e4.w;
-    }
-    uint16_t gv[4] = {0, 0, 0, 0};
-    for (int k = 0; k < 4; ++k) {
-      if (i + k >= md.n) continue;
-      const double dg = (double)nv[k] + c * ((double)nv[k] - (double)ov[k]);
-      const double y = mb.y[i + k];
-      if (loss == LOSS_LS) {
-        const double e = (double)ev[k] + dg;  // u_gamma - y
-        const double r = 2.0 * e;
-        fs += 0.25 * r * r + y * r;  // F*(-zeta), zeta = -r: ||zeta||^2/4 - y.zeta
-        gv[k] = float_to_bf16((float)(2.0 * dg));
-      } else {  // base0 holds u_0, base1 holds r_0 = grad f(u_0)
-        const double u = md.base0[(int64_t)slot * md.n_pad + i + k] + dg;
-        const double r = loss_grad(loss, u, y);
-        fs += fstar_term(loss, u, y);
-        gv[k] = float_to_bf16((float)(r - md.base1[(int64_t)slot * md.n_pad + i + k]));
-      }
-    }
-    // rows i .. i + 3 are consecutive within one 8-row group of the fragment layout
-    uint2 w;
-    w.x = (uint32_t)gv[0] | ((uint32_t)gv[1] << 16);
-    w.y = (uint32_t)gv[2] | ((uint32_t)gv[3] << 16);
-    *reinterpret_cast<uint2*>(md.gop + frag_index(slot, i, nbk)) = w;
+  if (sel_s <= 0) return;
+  // rows 8t .. 8t + 7 of the slot (16 bytes of gop_r, slot-major) are one segment of the
+  // fragment order: k-block t / 2, lane slot % 32 (t even) or slot % 32 + 32 (t odd) of the
+  // slot's node block
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const int64_t nb = md.S_pad >> 5;
+  const int64_t nseg = md.n_pad >> 3;
+  const uint16_t* src = md.gop_r + (int64_t)slot * md.n_pad;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < nseg;
+       t += (int64_t)gridDim.x * 256) {
+    const int64_t off = ((t >> 1) * nb + (slot >> 5)) * 512 + ((slot & 31) + 32 * (t & 1)) * 8;
+    *reinterpret_cast<u32x4*>(md.gop + off) = *reinterpret_cast<const u32x4*>(src + 8 * t);
   }
-  fs = block_reduce(fs, red, OpAdd(), 0.0);
-  if (threadIdx.x == 0) md.fpart[(int64_t)slot * md.nrt + blockIdx.x] = fs;
 }
 
 // =====================================================================================
@@ -284,15 +349,15 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
     st->L_prev = st->rs_L;
     st->L_work = st->rs_L;
     if (st->rs_L < st->P_best) st->P_best = st->rs_L;  // working-precision best (monitor only)
-    st->rebase = 0;  // read by the loss and residual kernels of this cycle only
+    st->rebase = 0;  // read by the loss and decision kernels of this cycle only
   }
   const double c = st->c;
   const double invL = 1.0 / mb.L;
   const int iter = st->iter;
   const bool check = (iter % st->check_every) == 0;
   // read ahead (their latency is spent on the loads of H): the winners of this slot's last two
-  // selections (where the registers allow), and the F* partials of the residual kernel (summed
-  // per wave below)
+  // selections (where the registers allow), and the F* partials of the loss kernel at the chosen
+  // gamma (summed per wave below; read only when the dual monitor runs)
   constexpr bool kAhead = E <= 12;
   int* const rtop = md.prevtop + (int64_t)slot * 65;
   int* const rhead = md.prevhead + (int64_t)slot * 65;
@@ -302,7 +367,10 @@ __global__ __launch_bounds__(1024) void k_mixed_node(MixedDev md) {
     whead = warm_prev(rhead);
   }
   double fpre = 0.0;
-  for (int i = threadIdx.x; i < md.nrt; i += blockDim.x) fpre += md.fpart[(int64_t)slot * md.nrt + i];
+  if (check) {
+    const double* fp = md.fpart + ((int64_t)slot * 2 + (md.gsel[slot] != 0)) * md.nrt;
+    for (int i = threadIdx.x; i < md.nrt; i += blockDim.x) fpre += fp[i];
+  }
   // H at gamma (FP64 base + BF16-product corrections) into the per-thread value slice
   __shared__ double vbuf[ProxVals<E>::nl * kProxThreads];
   ProxVals<E> pv;
@@ -813,6 +881,7 @@ __global__ __launch_bounds__(256) void k_admit(MixedDev md, const int* list, int
     md.dU[o] = 0.f;
     md.dU[md.dU_ring + o] = 0.f;
     md.gop[frag_index(slot, i, md.S_pad >> 5)] = 0;
+    md.gop_r[(int64_t)slot * md.n_pad + i] = 0;
   }
 }
 
@@ -1020,6 +1089,7 @@ __global__ __launch_bounds__(256) void k_slot_clear(MixedDev md, int slot) {
     md.dop[frag_index(slot, j, md.S_pad >> 5)] = 0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < md.n_pad; i += (int64_t)gridDim.x * 256) {
     md.gop[frag_index(slot, i, md.S_pad >> 5)] = 0;
+    md.gop_r[(int64_t)slot * md.n_pad + i] = 0;
     md.dU[(int64_t)slot * md.n_pad + i] = 0.f;
     md.dU[md.dU_ring + (int64_t)slot * md.n_pad + i] = 0.f;
   }
@@ -1130,9 +1200,8 @@ void launch_mixed_loss(const MixedDev& md, hipStream_t s) {
                      md);
 }
 
-void launch_mixed_resid(const MixedDev& md, hipStream_t s) {
-  hipLaunchKernelGGL(k_mixed_resid, dim3((unsigned)md.nrt, (unsigned)md.slots), dim3(256), 0, s,
-                     md);
+void launch_mixed_decide(const MixedDev& md, hipStream_t s) {
+  hipLaunchKernelGGL(k_mixed_decide, dim3(kDecideBlocks, (unsigned)md.slots), dim3(256), 0, s, md);
 }
 
 #define CGL_E_SWITCH(E_, CALL)   \

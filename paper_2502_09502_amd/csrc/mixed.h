@@ -52,7 +52,10 @@ struct MixedDev {
   double* bdual;        // S x ldp: the iterate whose dual point zeta = -grad f(X beta) gave the
                         // best certified bound
   uint16_t* dop;        // S_pad x ldp: bf16(beta - beta_0)
-  uint16_t* gop;        // S_pad x n_pad: bf16(grad f(u_gamma) - r_0)
+  uint16_t* gop;        // S_pad x n_pad: bf16(grad f(u_gamma) - r_0) without a restart
+  uint16_t* gop_r;      // S_pad x n_pad, slot-major: the same after a restart (c = 1/4)
+  int* gsel;            // S_pad: 1 where this cycle's restart test restarted (gop_r was copied
+                        // into gop; the node kernel reads F* partial set 1)
   float* dU;            // 2 rings x S_pad x n_pad
   int64_t dU_ring;
   float* dUp;           // ksx x S_pad x n_pad split-K partials of the X pass
@@ -68,7 +71,7 @@ struct MixedDev {
   double* lpart;        // S x nrt loss partials
   double* npart;        // S x nrt: sums of (f_i'(u) dU_i)^2, the scale of the loss's rounding
   double restart_slack; // > 0: a restart needs L^{t+1} >= L^t + slack 2^-9 sqrt(sum npart)
-  double* fpart;        // S x nrt F* partials (residual kernel)
+  double* fpart;        // S x 2 x nrt F* partials at gamma (loss kernel; set 1: after a restart)
   int nrt;
   int64_t rchunk;
   int* cycle;           // cycle counter: the cycle running, or between cycles the last one run
@@ -92,7 +95,7 @@ struct MixedDev {
 };
 
 constexpr int kStrayCap = 64;
-constexpr int kLossChunk = 2048;  // rows per block of the loss and residual kernels (8 per thread)
+constexpr int kLossChunk = 1024;  // rows per block of the loss kernel (4 per thread)
 
 void launch_make_bf16(int xtype, const void* X, int64_t ldx, int64_t n, int64_t p, int64_t n_pad,
                       int64_t ldp, uint16_t* Xb, uint16_t* Xbt, hipStream_t s);
@@ -103,7 +106,7 @@ void launch_gemm_x(const MixedDev& md, hipStream_t s, bool advance = false,
 void launch_gemm_xt(const MixedDev& md, hipStream_t s, hipEvent_t e0 = nullptr,
                     hipEvent_t e1 = nullptr);
 void launch_mixed_loss(const MixedDev& md, hipStream_t s);
-void launch_mixed_resid(const MixedDev& md, hipStream_t s);
+void launch_mixed_decide(const MixedDev& md, hipStream_t s);
 void launch_mixed_node(const MixedDev& md, hipStream_t s);
 // C[q][m] = sum_k A[m][k] B[q][k] in FP64 (A row-major in the design's stored precision);
 // part: split-K scratch of part_cap bytes (the split is limited to what fits).

@@ -49,7 +49,7 @@ struct NodeDev {
   int need_base;     // warm start admitted: parked until an FP64 round sets its base point
   double bsq_new;    // ||beta^{t+1}||^2 (eigen-perspective objective)
   int rebase;        // mixed path: the base moved under a running momentum (next cycle only)
-  // mixed path: restart-test outcome of the current cycle, taken by the residual kernel from the
+  // mixed path: restart-test outcome of the current cycle, taken by the decision kernel from the
   // state above and committed by the node kernel (phi, L^{t+1}, primed, restarts)
   double rs_phi;
   double rs_L;

@@ -92,22 +92,40 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
   const int64_t i0 = (int64_t)blockIdx.x * md.rchunk;
   const int64_t i1 = min(md.n_pad, i0 + md.rchunk);
   // strays of the operand: X~ column j is row j of X~^T; each thread sums them for 8 consecutive
-  // rows of the chunk (16-byte loads), in list order
+  // rows of the chunk (16-byte loads), in list order. The list goes through LDS first and the
+  // rows are loaded eight strays at a time: one slot's strays are a chain of dependent loads
+  // otherwise, which sets the kernel's time when few slots run.
   const int ns = md.sn[slot];
   __shared__ float sdu[kLossChunk];
+  __shared__ int sjs[kStrayCap];
+  __shared__ float svs[kStrayCap];
   if (ns > 0) {  // uniform over the block
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    if (threadIdx.x < ns) {
+      sjs[threadIdx.x] = md.sj[(int64_t)slot * kStrayCap + threadIdx.x];
+      svs[threadIdx.x] = md.sv[(int64_t)slot * kStrayCap + threadIdx.x];
+    }
+    __syncthreads();
     const int64_t r8 = 8 * (int64_t)threadIdx.x;
     if (i0 + r8 < i1) {
+      const uint16_t* xr = md.Xbt + i0 + r8;
       float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      for (int e = 0; e < ns; ++e) {
-        const int64_t j = md.sj[(int64_t)slot * kStrayCap + e];
-        const float v = md.sv[(int64_t)slot * kStrayCap + e];
-        const u32x4 x = *reinterpret_cast<const u32x4*>(md.Xbt + j * md.n_pad + i0 + r8);
+      auto add = [&](const u32x4& x, float v) {
 #pragma unroll
         for (int c = 0; c < 8; ++c)
           a[c] += bf16_to_float((uint16_t)((x[c >> 1] >> (16 * (c & 1))) & 0xffffu)) * v;
+      };
+      int e = 0;
+      for (; e + 8 <= ns; e += 8) {
+        u32x4 x[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          x[q] = *reinterpret_cast<const u32x4*>(xr + (int64_t)sjs[e + q] * md.n_pad);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) add(x[q], svs[e + q]);
       }
+      for (; e < ns; ++e)
+        add(*reinterpret_cast<const u32x4*>(xr + (int64_t)sjs[e] * md.n_pad), svs[e]);
 #pragma unroll
       for (int c = 0; c < 8; ++c) sdu[r8 + c] = a[c];
     }

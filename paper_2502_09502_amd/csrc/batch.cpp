@@ -284,6 +284,7 @@ void MixedWork::ensure(Problem& P) {
   md.npart = npart.as<double>();
   md.fpart = fpart.as<double>();
   md.nrt = nrt;
+  md.loss_kinds = (any_ls ? 1 : 0) | (any_other ? 2 : 0);
   md.rchunk = rchunk;
   md.cycle = cycle.as<int>();
   md.prevhead = prevsel.as<int>();

@@ -69,7 +69,12 @@ __device__ __forceinline__ double momentum_coef(double phi) { return phi / (phi 
 // new base: dU^{t+1} = 0 and the previous correction becomes X~ bf16(beta^t - beta_0') minus this
 // product, i.e. X (beta^t - beta^{t+1}) with the rounding of an ordinary cycle's difference.
 // =====================================================================================
-__global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
+// LS: the instantiation for the least-squares slots (the other serves the other losses; an engine
+// launches the ones its problems need). The least-squares code alone needs far fewer registers
+// than the FP64 transcendental work of the other losses; its kernel asks for 6 waves per SIMD
+// (it fits 8 without spills), so more waves keep loads in flight.
+template <bool LS>
+__device__ __forceinline__ void mixed_loss_body(const MixedDev& md) {
   __shared__ double red[4][4];
   // the X pass of this cycle has read the operand extent: its counter restarts for cycle + 2
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) md.keff[*md.cycle & 1] = 0;
@@ -78,6 +83,7 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
   if (!slot_running(st)) return;
   const MemberDev& mb = md.mem[st->member];
   const int loss = mb.loss;
+  if ((loss == LOSS_LS) != LS) return;
   const double* yv = mb.y;
   const int cyc = *md.cycle;
   const bool rebase = st->rebase != 0;
@@ -164,7 +170,7 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
     *reinterpret_cast<float4*>(dun + i) = du;
     const float dv[4] = {du.x, du.y, du.z, du.w}, ov[4] = {o.x, o.y, o.z, o.w};
     uint16_t gk[4] = {0, 0, 0, 0}, gr[4] = {0, 0, 0, 0};
-    if (loss == LOSS_LS) {
+    if constexpr (LS) {
       const float4 e4 = *reinterpret_cast<const float4*>(md.e0f + (int64_t)slot * md.n_pad + i);
       const float ev[4] = {e4.x, e4.y, e4.z, e4.w};
 #pragma unroll
@@ -252,6 +258,17 @@ __global__ __launch_bounds__(256) void k_mixed_loss(MixedDev md) {
     else if (v == 3 && check && can_restart)
       md.fpart[((int64_t)slot * 2 + 1) * md.nrt + blockIdx.x] = t;
   }
+}
+
+template <bool LS>
+__global__ void k_mixed_loss(MixedDev md);
+template <>
+__global__ __launch_bounds__(256, 6) void k_mixed_loss<true>(MixedDev md) {
+  mixed_loss_body<true>(md);
+}
+template <>
+__global__ __launch_bounds__(256) void k_mixed_loss<false>(MixedDev md) {
+  mixed_loss_body<false>(md);
 }
 
 // =====================================================================================
@@ -1214,8 +1231,9 @@ void launch_gemm_xt(const MixedDev& md, hipStream_t s, hipEvent_t e0, hipEvent_t
 }
 
 void launch_mixed_loss(const MixedDev& md, hipStream_t s) {
-  hipLaunchKernelGGL(k_mixed_loss, dim3((unsigned)md.nrt, (unsigned)md.slots), dim3(256), 0, s,
-                     md);
+  const dim3 grid((unsigned)md.nrt, (unsigned)md.slots);
+  if (md.loss_kinds & 1) hipLaunchKernelGGL(k_mixed_loss<true>, grid, dim3(256), 0, s, md);
+  if (md.loss_kinds & 2) hipLaunchKernelGGL(k_mixed_loss<false>, grid, dim3(256), 0, s, md);
 }
 
 void launch_mixed_decide(const MixedDev& md, hipStream_t s) {

@@ -33,6 +33,7 @@ struct MixedDev {
   const uint16_t* Xbt;  // ldp x n_pad, its transpose
   int64_t n, p, n_pad, ldp;
   const MemberDev* mem; // kMaxMembers entries (device)
+  int loss_kinds;       // bit 0: a problem with least squares; bit 1: one with another loss
   double cert_gap;      // a node asks for an FP64 round when its working gap is <= cert_gap * tol
   int stall_cycles;     // ... or when that gap has not halved for this many cycles
   // slots

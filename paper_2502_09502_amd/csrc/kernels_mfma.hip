@@ -349,10 +349,21 @@ __global__ __launch_bounds__(256) void k_mixed_decide(MixedDev md) {
   const int64_t nb = md.S_pad >> 5;
   const int64_t nseg = md.n_pad >> 3;
   const uint16_t* src = md.gop_r + (int64_t)slot * md.n_pad;
-  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < nseg;
-       t += (int64_t)gridDim.x * 256) {
-    const int64_t off = ((t >> 1) * nb + (slot >> 5)) * 512 + ((slot & 31) + 32 * (t & 1)) * 8;
-    *reinterpret_cast<u32x4*>(md.gop + off) = *reinterpret_cast<const u32x4*>(src + 8 * t);
+  // four segments per thread and round: their loads are issued before any of the stores (one
+  // load latency per round rather than one per segment)
+  const int64_t step = (int64_t)gridDim.x * 256;
+  for (int64_t t0 = (int64_t)blockIdx.x * 256 + threadIdx.x; t0 < nseg; t0 += 4 * step) {
+    u32x4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (t0 + k * step < nseg) v[k] = *reinterpret_cast<const u32x4*>(src + 8 * (t0 + k * step));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t t = t0 + k * step;
+      if (t < nseg)
+        *reinterpret_cast<u32x4*>(md.gop + ((t >> 1) * nb + (slot >> 5)) * 512 +
+                                  ((slot & 31) + 32 * (t & 1)) * 8) = v[k];
+    }
   }
 }
 

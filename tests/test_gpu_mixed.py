@@ -177,6 +177,27 @@ def test_gram_certificate_matches_direct_product(dtype, monkeypatch):
 
 
 @pytest.mark.parametrize("loss", ["ls", "logistic"])
+def test_plain_restart_comparison_matches_oracle(loss, monkeypatch):
+    """Alg. 3's restart test without the rounding margin (CGL_RESTART_SLACK=0) restarts far more
+    often on the working-precision objective. Every restart takes the residual operand that the
+    loss kernel wrote for the restart coefficient (copied into place by the decision kernel), so
+    these solves lean on that path: they still match the oracle, and they restart at least as
+    often as the same nodes with the default margin."""
+    d = synth.make_dataset(500, 300, 6, loss=loss, config_id=91)
+    sets = synth.node_sets(d.p, d.k, 10, 15, config_id=91)
+    dm = _problem(d)
+    a = dm.solve_batch(_specs(dm, sets))
+    monkeypatch.setenv("CGL_RESTART_SLACK", "0")
+    pl = _problem(d)
+    b = pl.solve_batch(_specs(pl, sets))
+    for (z0, z1), ra, rb in zip(sets, a, b):
+        _check(d, ra, z0, z1)
+        _check(d, rb, z0, z1)
+    ra_, rb_ = [r.restarts for r in a], [r.restarts for r in b]
+    assert sum(rb_) > 0 and sum(rb_) >= sum(ra_), (ra_, rb_)
+
+
+@pytest.mark.parametrize("loss", ["ls", "logistic"])
 def test_operand_reorder_matches_natural_order(loss, monkeypatch):
     """The X pass reads only the prefix of a support-first column order of X~ (re-laid every few
     cycles while the nodes run); with the reordering turned off the same nodes give the same

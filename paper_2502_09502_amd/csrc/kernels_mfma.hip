@@ -60,9 +60,9 @@ __device__ __forceinline__ double momentum_coef(double phi) { return phi / (phi 
 // summed over every chunk. It takes one of two values that are known beforehand: c_r = 1/4 after
 // a restart (phi = 1), c_k for phi + 1 otherwise (phi itself while the momentum is not yet
 // primed). The kernel therefore writes G and the F* partials for both: gop (fragment order) and
-// fpart set 0 for c_k, gop_r (slot-major) and set 1 for c_r (only c_k when no restart is possible this cycle: unprimed, or
-// the first cycle after a rebase). k_mixed_decide takes the test and leaves the chosen operand
-// in gop; the node kernel reads the chosen F* partials.
+// fpart set 0 for c_k, gop_r (slot-major) and set 1 for c_r (only c_k when no restart is
+// possible this cycle: unprimed, or the first cycle after a rebase). k_mixed_decide takes the
+// test and leaves the chosen operand in gop; the node kernel reads the chosen F* partials.
 //
 // In the first cycle after a re-centre that kept the momentum (rebase), the product of this
 // cycle is X~ bf16(beta^{t+1} - beta_0') against the previous base beta_0', and beta^{t+1} is the
